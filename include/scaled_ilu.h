@@ -1,0 +1,240 @@
+/*
+ * scaled_ilu.h -- C-ABI of libscaledilu.so, the MI355X (gfx950) solve phase of
+ * the scaled ILU smoother of Thomas, Carr, Mullowney, Swirydowicz and Day,
+ * "Scaled ILU Smoothers for Navier-Stokes Pressure Projection"
+ * (arXiv 2111.09512).
+ *
+ * The smoother step is x <- x + M^{-1} (b - A x) with M = L D U~ (Section 3.1,
+ * eq. ILUsplit).  Its two triangular solves are replaced by a few Richardson
+ * sweeps on the unit-diagonal factors, the row scaling D^{-1} having been
+ * folded into U once (Section 5.1, eqs. extractD and newD; Algorithm 2;
+ * Section 5.2, eq. richard).  Each sweep is one CSR pass over a strictly
+ * triangular factor.  The level-scheduled direct triangular solve (Section 4)
+ * is provided as the comparison solve.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are CSR with int32 row pointers and column indices, columns
+ *     sorted ascending and unique inside each row.  All sizes < 2^31.
+ *   - Unless stated otherwise every pointer is a DEVICE pointer on the device
+ *     that was current when the context was created.  The caller owns every
+ *     buffer it passes (matrices, vectors, workspace) and keeps it alive until
+ *     the work queued on the context's stream has passed the call.  The library
+ *     never frees caller memory.
+ *   - Calls marked "asynchronous" only enqueue work on the context's stream and
+ *     return; calls marked "synchronous" wait for their own work to finish.
+ *   - Every entry point returns an int status: SILU_OK (0) or a negative code
+ *     below.  Nothing throws and nothing exits across the ABI.  After
+ *     SILU_ERR_HIP, silu_last_hip_error() gives the HIP error code.
+ */
+#ifndef SCALED_ILU_H
+#define SCALED_ILU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SILU_OK 0
+#define SILU_ERR_ARG (-1)         /* null pointer, negative size, bad flag or count */
+#define SILU_ERR_SHAPE (-2)       /* dimension mismatch or non-square matrix */
+#define SILU_ERR_PATTERN (-3)     /* CSR structure violates the stated pattern */
+#define SILU_ERR_ZERO_PIVOT (-4)  /* u_ii == 0 or not finite; see silu_bad_row() */
+#define SILU_ERR_NONFINITE (-5)   /* SILU_CHECK_FINITE found a NaN/Inf in x */
+#define SILU_ERR_NOMEM (-6)       /* caller workspace smaller than silu_workspace_size() */
+#define SILU_ERR_HIP (-7)         /* a HIP runtime call failed */
+#define SILU_ERR_UNSUPPORTED (-8) /* valid request this build does not implement */
+
+/* ---- value types of silu_csr.val ------------------------------------- */
+#define SILU_F64 0
+#define SILU_F32 1
+
+/* ---- flags ------------------------------------------------------------- */
+#define SILU_ITER 0x0         /* ilu_smooth: Richardson sweeps (default)                  */
+#define SILU_DIRECT 0x1       /* ilu_smooth: level-scheduled substitution instead          */
+#define SILU_MIXED 0x2        /* ilu_smooth: FP32 factor values, iterates, accumulation    */
+#define SILU_CHECK_FINITE 0x4 /* ilu_smooth: after the step, scan x (synchronous)          */
+#define SILU_VALIDATE 0x8     /* check CSR structure first (synchronous; copies to host)   */
+#define SILU_NO_SCALING 0x10  /* ilu_scale_factors: keep U's values (the unscaled variant) */
+#define SILU_KERNEL_STREAM 0x100 /* force the LDS-staged CSR-stream sweep kernel           */
+#define SILU_KERNEL_VECTOR 0x200 /* force the vector-CSR (lanes-per-row) sweep kernel      */
+
+#define SILU_LOWER 0
+#define SILU_UPPER 1
+#define SILU_UNIT 0
+#define SILU_NONUNIT 1
+
+/* Square sparse matrix (n_rows == n_cols) in CSR form. */
+typedef struct {
+    int64_t n_rows;
+    int64_t n_cols;
+    int64_t nnz;
+    int32_t *row_ptr; /* [n_rows + 1] */
+    int32_t *col_idx; /* [nnz]        */
+    void *val;        /* [nnz] of dtype */
+    int32_t dtype;    /* SILU_F64 or SILU_F32 */
+} silu_csr;
+
+/*
+ * The factors the smoother reads, all on the device.
+ *   Ls       strictly lower part of L = I + Ls (the unit diagonal is implied),
+ *            FP64 values.  ilu_scale_factors copies the caller's L here.
+ *   Us       strictly upper part of U~ = D^{-1} U (eq. newD), FP64; written by
+ *            ilu_scale_factors into caller-allocated arrays: row_ptr [n+1],
+ *            col_idx and val [nnz(U) - n].  With SILU_NO_SCALING, Us holds
+ *            the strictly upper part of U itself.
+ *   d        diag(U) [n] (eq. extractD)
+ *   dinv     1 / diag(U) [n]
+ *   Ls_val32 optional FP32 copy of Ls.val (round to nearest even), or NULL
+ *   Us_val32 optional FP32 copy of Us.val, or NULL
+ *   scaled   1 after row scaling, 0 with SILU_NO_SCALING
+ */
+typedef struct {
+    silu_csr Ls;
+    silu_csr Us;
+    double *d;
+    double *dinv;
+    float *Ls_val32;
+    float *Us_val32;
+    int32_t scaled;
+} silu_factors;
+
+typedef struct silu_ctx silu_ctx;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on the current device that enqueues on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  The stream is borrowed, not owned.
+ * The context owns its level analyses, graphs, events and a few bytes of
+ * device flags, all freed by silu_destroy.  Synchronous. */
+int silu_create(silu_ctx **ctx, void *hip_stream);
+int silu_destroy(silu_ctx *ctx);
+/* Change the stream later calls enqueue on (borrowed). */
+int silu_set_stream(silu_ctx *ctx, void *hip_stream);
+
+/* Row of the last ZERO_PIVOT / PATTERN error, or -1. */
+int64_t silu_bad_row(const silu_ctx *ctx);
+/* HIP error code behind the last SILU_ERR_HIP on this context (0 if none). */
+int silu_last_hip_error(const silu_ctx *ctx);
+/* Static description of a status code. */
+const char *silu_status_string(int status);
+
+/* Workspace bytes ilu_smooth / trisolve_iter need for n rows under `flags`.
+ * The caller allocates the workspace (at least 256-byte aligned) and passes
+ * it in, so every byte the library touches is visible to the caller. */
+int silu_workspace_size(silu_ctx *ctx, int64_t n, int flags, size_t *bytes);
+
+/* ---- setup: row scaling (Section 5.1, eqs. extractD and newD) ----------- */
+
+/*
+ * L: strictly lower CSR (unit diagonal implied), FP64.  U: upper CSR, FP64,
+ * whose FIRST entry in every row is the diagonal.  Writes, in F:
+ *   F->Ls = *L;  F->d[i] = u_ii;  F->dinv[i] = 1/u_ii;
+ *   F->Us (row_ptr, col_idx, val) = strictly upper part of U with every value
+ *   divided by its row's diagonal (one IEEE division per entry), or copied
+ *   unchanged with SILU_NO_SCALING;
+ *   F->Ls_val32 / F->Us_val32 if non-NULL: FP32 copies of the values.
+ * The caller allocates F->Us.row_ptr [n+1], F->Us.col_idx and F->Us.val
+ * [nnz(U)-n] (FP64), F->d and F->dinv [n], and the optional FP32 arrays.
+ * Synchronous.  Errors: ARG, SHAPE, PATTERN (a row of U does not start with
+ * its diagonal), ZERO_PIVOT (u_ii == 0 or not finite; silu_bad_row gives the
+ * first such row).
+ */
+int ilu_scale_factors(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags);
+
+/* ---- the smoother (eq. ILUsplit, Algorithm 2, eq. richard) -------------- */
+
+/*
+ * `outer_sweeps` smoothing steps on x (in/out; x = 0 for a pure
+ * preconditioner application):
+ *   r = b - A x;  y = m_L Richardson steps on L y = r from y = 0;
+ *   s = D^{-1} y;  z = m_U Richardson steps on U~ z = s from z = 0;  x += z.
+ * A: n x n FP64 CSR.  F: from ilu_scale_factors.  b, x: FP64 [n].
+ * flags: SILU_DIRECT replaces both Richardson loops by level-scheduled
+ * substitution (m_L, m_U ignored); SILU_MIXED runs the two Richardson loops on
+ * F->Ls_val32 / F->Us_val32 with FP32 iterates and accumulation (r, the
+ * scaling s = (float)(dinv * y) and x += z stay FP64); SILU_CHECK_FINITE adds
+ * a synchronous scan of x (returns NONFINITE); SILU_VALIDATE checks the CSR
+ * structures first.  With F->scaled == 0 (SILU_NO_SCALING) the U loop is the
+ * unscaled Richardson iteration z <- y - (U - I) z (FP64 only).
+ * ws: workspace of at least silu_workspace_size(ctx, n, flags) bytes.
+ * Asynchronous on the context stream (unless CHECK_FINITE / VALIDATE).
+ * Errors: ARG (null, outer_sweeps < 1, m_L < 1 or m_U < 1 in ITER mode),
+ * SHAPE, NOMEM (ws_bytes too small), UNSUPPORTED (MIXED without FP32 copies,
+ * MIXED or DIRECT with unscaled factors), PATTERN (with VALIDATE), NONFINITE,
+ * HIP.
+ */
+int ilu_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+               int outer_sweeps, int inner_iters, int flags, void *ws, size_t ws_bytes);
+/* Same with separate inner iteration counts for the L and the U factor. */
+int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes);
+
+/* ---- triangular solves ------------------------------------------------- */
+
+/*
+ * Direct solve T out = rhs by level-set scheduling (Section 4): rows are
+ * grouped by the level of the elimination DAG and each level is one kernel
+ * launch, rows inside a level in parallel.  T: FP64 CSR, lower (uplo =
+ * SILU_LOWER) or upper triangular.  diag = SILU_UNIT: the diagonal is taken
+ * as 1 and stored diagonal entries are not read; SILU_NONUNIT: every row must
+ * store its diagonal, and the row is divided by it.  rhs, out: FP64 [n],
+ * distinct.  The level analysis of T is made on first use (synchronous: the
+ * pattern is copied to the host) and cached in the context, keyed by T's
+ * pointers and sizes; the solve itself is asynchronous.
+ * Errors: ARG, SHAPE, PATTERN (an entry on the wrong side), HIP.
+ */
+int trisolve_direct(silu_ctx *ctx, const silu_csr *T, int uplo, int diag, const double *rhs, double *out,
+                    int flags);
+
+/*
+ * Iterative counterpart (Section 4; eq. richard): m Richardson steps
+ * out_k = s - T out_{k-1} from out_0 = 0 for the unit triangular system
+ * (I + T) out = s, where T is STRICTLY triangular (no stored diagonal; lower
+ * or upper) and s = rhs, or s = dinv * rhs when dinv is non-NULL.  m >= the
+ * number of levels of T gives the exact solution (T is nilpotent).  FP64;
+ * rhs and out distinct.  ws: silu_workspace_size(ctx, n, 0) bytes.
+ * Asynchronous.  Errors: ARG (m < 1), SHAPE, NOMEM, PATTERN (with
+ * SILU_VALIDATE), HIP.
+ */
+int trisolve_iter(silu_ctx *ctx, const silu_csr *T, const double *dinv, const double *rhs, double *out, int m,
+                  int flags, void *ws, size_t ws_bytes);
+
+/* Level analysis of T (made now if not cached): number of levels in
+ * *depth and, if rows_per_level is non-NULL, the row count of every level
+ * (host array of at least *depth entries; call once with NULL to size it).
+ * Synchronous. */
+int silu_analyze(silu_ctx *ctx, const silu_csr *T, int uplo, int32_t *depth, int32_t *rows_per_level);
+
+/* ---- measurement ------------------------------------------------------- */
+
+/*
+ * Per-kernel timing.  With timing on, every kernel launch the context makes
+ * is bracketed by a pair of HIP events recorded on the context stream, and the
+ * launch is credited with its algorithmic HBM bytes (each CSR entry read once,
+ * each dense vector read or written once).  silu_stats_collect synchronizes
+ * the stream and folds the recorded events into per-kernel totals; it
+ * returns the number of kernel kinds seen.  silu_stats_get reads entry idx:
+ * kernel name (NUL-terminated, truncated to name_len), launch count, summed
+ * duration in milliseconds and summed algorithmic bytes.  silu_stats_reset
+ * clears them.
+ */
+int silu_set_timing(silu_ctx *ctx, int enable);
+int silu_stats_collect(silu_ctx *ctx);
+int silu_stats_get(silu_ctx *ctx, int idx, char *name, int name_len, int64_t *launches, double *ms,
+                   double *bytes);
+int silu_stats_reset(silu_ctx *ctx);
+
+/* Plain device copy dst[0..bytes) = src[0..bytes) with a streaming kernel
+ * (16-byte vector loads and stores), used to measure achievable HBM
+ * bandwidth and to calibrate traffic counters.  bytes must be a multiple of
+ * 16 and both pointers 16-byte aligned.  Asynchronous. */
+int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCALED_ILU_H */

@@ -1,0 +1,381 @@
+"""Thin Python binding over libscaledilu.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels (or, for the host-side
+factorization set-up, in its C++ code); this module only turns torch tensors
+into device pointers and sizes, passes the current torch stream, and raises on
+a non-zero status.  The entry points keep the C-ABI names: ``ilu_scale_factors``,
+``ilu_smooth``, ``trisolve_direct``, ``trisolve_iter``, ``silu_analyze``.
+
+There is no fallback: if the shared library is missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libscaledilu.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "(or `python paper_2111_09512_amd/build.py`). There is no CPU fallback."
+    )
+_lib = C.CDLL(LIB_PATH)
+
+SILU_F64, SILU_F32 = 0, 1
+SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
+SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR = 0x100, 0x200
+SILU_LOWER, SILU_UPPER = 0, 1
+SILU_UNIT, SILU_NONUNIT = 0, 1
+
+STATUS = {
+    0: "SILU_OK", -1: "SILU_ERR_ARG", -2: "SILU_ERR_SHAPE", -3: "SILU_ERR_PATTERN", -4: "SILU_ERR_ZERO_PIVOT",
+    -5: "SILU_ERR_NONFINITE", -6: "SILU_ERR_NOMEM", -7: "SILU_ERR_HIP", -8: "SILU_ERR_UNSUPPORTED",
+}
+
+
+class silu_csr(C.Structure):
+    _fields_ = [
+        ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("nnz", C.c_int64),
+        ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p), ("dtype", C.c_int32),
+    ]
+
+
+class silu_factors(C.Structure):
+    _fields_ = [
+        ("Ls", silu_csr), ("Us", silu_csr), ("d", C.c_void_p), ("dinv", C.c_void_p),
+        ("Ls_val32", C.c_void_p), ("Us_val32", C.c_void_p), ("scaled", C.c_int32),
+    ]
+
+
+class silu_host_csr(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.POINTER(C.c_int32)),
+        ("col_idx", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double)),
+    ]
+
+
+_P = C.c_void_p
+_sig = {
+    "silu_create": (C.c_int, [C.POINTER(_P), _P]),
+    "silu_destroy": (C.c_int, [_P]),
+    "silu_set_stream": (C.c_int, [_P, _P]),
+    "silu_bad_row": (C.c_int64, [_P]),
+    "silu_last_hip_error": (C.c_int, [_P]),
+    "silu_status_string": (C.c_char_p, [C.c_int]),
+    "silu_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int, C.POINTER(C.c_size_t)]),
+    "ilu_scale_factors": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
+    "ilu_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int,
+                             _P, C.c_size_t]),
+    "ilu_smooth2": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
+                              C.c_int, C.c_int, _P, C.c_size_t]),
+    "trisolve_direct": (C.c_int, [_P, C.POINTER(silu_csr), C.c_int, C.c_int, _P, _P, C.c_int]),
+    "trisolve_iter": (C.c_int, [_P, C.POINTER(silu_csr), _P, _P, _P, C.c_int, C.c_int, _P, C.c_size_t]),
+    "silu_analyze": (C.c_int, [_P, C.POINTER(silu_csr), C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "silu_set_timing": (C.c_int, [_P, C.c_int]),
+    "silu_stats_collect": (C.c_int, [_P]),
+    "silu_stats_get": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double)]),
+    "silu_stats_reset": (C.c_int, [_P]),
+    "silu_stream_copy": (C.c_int, [_P, _P, _P, C.c_size_t]),
+    "silu_factor_iluk": (C.c_int, [C.POINTER(silu_host_csr), C.c_int, C.POINTER(silu_host_csr),
+                                   C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
+    "silu_factor_ilut": (C.c_int, [C.POINTER(silu_host_csr), C.c_double, C.c_int, C.POINTER(silu_host_csr),
+                                   C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
+    "silu_host_csr_free": (None, [C.POINTER(silu_host_csr)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class SiluError(RuntimeError):
+    def __init__(self, status: int, where: str, row: int = -1, hip: int = 0):
+        msg = f"{where}: {STATUS.get(status, status)} ({_lib.silu_status_string(status).decode()})"
+        if row >= 0:
+            msg += f", row {row}"
+        if hip:
+            msg += f", hip error {hip}"
+        super().__init__(msg)
+        self.status = status
+        self.row = row
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+# --------------------------------------------------------------------------
+# device containers
+# --------------------------------------------------------------------------
+
+@dataclass
+class Csr:
+    """Device CSR: int32 row_ptr / col_idx, float64 (or float32) values, torch tensors."""
+
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.row_ptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.col_idx.numel()
+
+    def c(self) -> silu_csr:
+        for t in (self.row_ptr, self.col_idx, self.val):
+            if not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous")
+        if self.row_ptr.dtype != torch.int32 or self.col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr and col_idx must be int32")
+        dt = {torch.float64: SILU_F64, torch.float32: SILU_F32}[self.val.dtype]
+        return silu_csr(self.n, self.n, self.nnz, self.row_ptr.data_ptr(), _ptr(self.col_idx) if self.nnz else None,
+                        _ptr(self.val) if self.nnz else None, dt)
+
+    @staticmethod
+    def from_host(M, device="cuda") -> "Csr":
+        """Upload a host CSR (anything with row_ptr, col, val numpy arrays)."""
+        return Csr(torch.from_numpy(np.ascontiguousarray(M.row_ptr, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(M.col, np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(M.val, np.float64)).to(device))
+
+
+@dataclass
+class Factors:
+    Ls: Csr
+    Us: Csr
+    d: torch.Tensor
+    dinv: torch.Tensor
+    Ls_val32: torch.Tensor | None
+    Us_val32: torch.Tensor | None
+    scaled: bool
+
+    def c(self) -> silu_factors:
+        return silu_factors(self.Ls.c(), self.Us.c(), _ptr(self.d), _ptr(self.dinv), _ptr(self.Ls_val32),
+                            _ptr(self.Us_val32), 1 if self.scaled else 0)
+
+    def nbytes(self) -> int:
+        ts = [self.Ls.row_ptr, self.Ls.col_idx, self.Ls.val, self.Us.row_ptr, self.Us.col_idx, self.Us.val, self.d,
+              self.dinv, self.Ls_val32, self.Us_val32]
+        return sum(t.numel() * t.element_size() for t in ts if t is not None)
+
+
+# --------------------------------------------------------------------------
+# context
+# --------------------------------------------------------------------------
+
+class Context:
+    """Owns a silu_ctx bound to a torch stream (default: the current stream)."""
+
+    def __init__(self, stream: torch.cuda.Stream | None = None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = _lib.silu_create(C.byref(h), C.c_void_p(self.stream.cuda_stream))
+        if st:
+            raise SiluError(st, "silu_create")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.silu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, where: str):
+        if st:
+            raise SiluError(st, where, int(_lib.silu_bad_row(self._h)), int(_lib.silu_last_hip_error(self._h)))
+
+    # ---- workspace ----
+    def workspace_size(self, n: int, flags: int = 0) -> int:
+        b = C.c_size_t()
+        self._check(_lib.silu_workspace_size(self._h, n, flags, C.byref(b)), "silu_workspace_size")
+        return b.value
+
+    def workspace(self, n: int, flags: int = 0) -> torch.Tensor:
+        need = self.workspace_size(n, flags)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    # ---- setup ----
+    def ilu_scale_factors(self, L: Csr, U: Csr, fp32: bool = False, scale: bool = True,
+                          validate: bool = False) -> Factors:
+        n = U.n
+        nnz_s = U.nnz - n
+        dev = U.val.device
+        Us = Csr(torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(max(nnz_s, 0), dtype=torch.int32,
+                                                                               device=dev),
+                 torch.empty(max(nnz_s, 0), dtype=torch.float64, device=dev))
+        F = Factors(L, Us, torch.empty(n, dtype=torch.float64, device=dev),
+                    torch.empty(n, dtype=torch.float64, device=dev),
+                    torch.empty(L.nnz, dtype=torch.float32, device=dev) if fp32 else None,
+                    torch.empty(max(nnz_s, 0), dtype=torch.float32, device=dev) if fp32 else None, scale)
+        Fc = F.c()
+        Fc.Us = silu_csr(n, n, max(nnz_s, 0), Us.row_ptr.data_ptr(), _ptr(Us.col_idx) if nnz_s else None,
+                         _ptr(Us.val) if nnz_s else None, SILU_F64)
+        flags = (0 if scale else SILU_NO_SCALING) | (SILU_VALIDATE if validate else 0)
+        Lc, Uc = L.c(), U.c()
+        self._check(_lib.ilu_scale_factors(self._h, C.byref(Lc), C.byref(Uc), C.byref(Fc), flags), "ilu_scale_factors")
+        return F
+
+    # ---- the smoother ----
+    def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
+                   m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
+                   validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+        """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned)."""
+        m_U = m_L if m_U is None else m_U
+        flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) |
+                 (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
+                 {None: 0, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}[kernel])
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        ws = self.workspace(A.n, flags) if ws is None else ws
+        Ac, Fc = A.c(), F.c()
+        self._check(_lib.ilu_smooth2(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags,
+                                     C.c_void_p(ws.data_ptr()), ws.numel()), "ilu_smooth")
+        return x
+
+    def trisolve_direct(self, T: Csr, uplo: int, diag: int, rhs: torch.Tensor, out: torch.Tensor | None = None,
+                        validate: bool = False) -> torch.Tensor:
+        _vec(rhs, T.n, "rhs")
+        out = torch.empty_like(rhs) if out is None else out
+        Tc = T.c()
+        self._check(_lib.trisolve_direct(self._h, C.byref(Tc), uplo, diag, C.c_void_p(rhs.data_ptr()),
+                                         C.c_void_p(out.data_ptr()), SILU_VALIDATE if validate else 0),
+                    "trisolve_direct")
+        return out
+
+    def trisolve_iter(self, T: Csr, rhs: torch.Tensor, m: int, dinv: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None, kernel: str | None = None) -> torch.Tensor:
+        _vec(rhs, T.n, "rhs")
+        out = torch.empty_like(rhs) if out is None else out
+        flags = {None: 0, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}[kernel]
+        ws = self.workspace(T.n, 0)
+        Tc = T.c()
+        self._check(_lib.trisolve_iter(self._h, C.byref(Tc), C.c_void_p(_ptr(dinv)), C.c_void_p(rhs.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), m, flags, C.c_void_p(ws.data_ptr()),
+                                       ws.numel()), "trisolve_iter")
+        return out
+
+    def silu_analyze(self, T: Csr, uplo: int):
+        depth = C.c_int32()
+        Tc = T.c()
+        self._check(_lib.silu_analyze(self._h, C.byref(Tc), uplo, C.byref(depth), None), "silu_analyze")
+        rows = (C.c_int32 * max(depth.value, 1))()
+        self._check(_lib.silu_analyze(self._h, C.byref(Tc), uplo, C.byref(depth), rows), "silu_analyze")
+        return depth.value, np.ctypeslib.as_array(rows)[: depth.value].copy()
+
+    # ---- measurement ----
+    def set_timing(self, on: bool):
+        self._check(_lib.silu_set_timing(self._h, 1 if on else 0), "silu_set_timing")
+
+    def stats(self) -> dict:
+        k = _lib.silu_stats_collect(self._h)
+        if k < 0:
+            self._check(k, "silu_stats_collect")
+        out = {}
+        buf = C.create_string_buffer(64)
+        for i in range(k):
+            la, ms, by = C.c_int64(), C.c_double(), C.c_double()
+            self._check(_lib.silu_stats_get(self._h, i, buf, 64, C.byref(la), C.byref(ms), C.byref(by)),
+                        "silu_stats_get")
+            out[buf.value.decode()] = {"launches": la.value, "ms": ms.value, "bytes": by.value}
+        return out
+
+    def stats_reset(self):
+        self._check(_lib.silu_stats_reset(self._h), "silu_stats_reset")
+
+    def stream_copy(self, src: torch.Tensor, dst: torch.Tensor):
+        nb = src.numel() * src.element_size()
+        self._check(_lib.silu_stream_copy(self._h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb),
+                    "silu_stream_copy")
+
+
+def _vec(t: torch.Tensor, n: int, what: str):
+    if t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{what} must be a contiguous float64 CUDA tensor of length {n}")
+
+
+# --------------------------------------------------------------------------
+# host-side factorization set-up (silu_factor.h)
+# --------------------------------------------------------------------------
+
+@dataclass
+class HostCsr:
+    n: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def _host_in(A) -> tuple[silu_host_csr, tuple]:
+    rp = np.ascontiguousarray(A.row_ptr, np.int32)
+    col = np.ascontiguousarray(A.col, np.int32)
+    val = np.ascontiguousarray(A.val, np.float64)
+    h = silu_host_csr(int(A.n), int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                      col.ctypes.data_as(C.POINTER(C.c_int32)), val.ctypes.data_as(C.POINTER(C.c_double)))
+    return h, (rp, col, val)
+
+
+def _host_out(h: silu_host_csr) -> HostCsr:
+    n, nnz = int(h.n), int(h.nnz)
+    rp = np.ctypeslib.as_array(h.row_ptr, shape=(n + 1,)).copy()
+    if nnz:
+        col = np.ctypeslib.as_array(h.col_idx, shape=(nnz,)).copy()
+        val = np.ctypeslib.as_array(h.val, shape=(nnz,)).copy()
+    else:
+        col, val = np.zeros(0, np.int32), np.zeros(0)
+    _lib.silu_host_csr_free(C.byref(h))
+    return HostCsr(n, rp, col, val)
+
+
+def factor_iluk(A, k: int) -> tuple[HostCsr, HostCsr]:
+    """ILU(k) on the host (set-up): returns (strictly lower L, upper U with diagonal first)."""
+    h, keep = _host_in(A)
+    L, U, bad = silu_host_csr(), silu_host_csr(), C.c_int64(-1)
+    st = _lib.silu_factor_iluk(C.byref(h), int(k), C.byref(L), C.byref(U), C.byref(bad))
+    if st:
+        raise SiluError(st, f"silu_factor_iluk(k={k})", int(bad.value))
+    return _host_out(L), _host_out(U)
+
+
+def factor_ilut(A, tau: float, p: int) -> tuple[HostCsr, HostCsr]:
+    """ILUT(tau, p) on the host (set-up)."""
+    h, keep = _host_in(A)
+    L, U, bad = silu_host_csr(), silu_host_csr(), C.c_int64(-1)
+    st = _lib.silu_factor_ilut(C.byref(h), float(tau), int(p), C.byref(L), C.byref(U), C.byref(bad))
+    if st:
+        raise SiluError(st, f"silu_factor_ilut(tau={tau}, p={p})", int(bad.value))
+    return _host_out(L), _host_out(U)
+
+
+def factor(A, kind: str, params: dict) -> tuple[HostCsr, HostCsr]:
+    if kind == "ilu0":
+        return factor_iluk(A, 0)
+    if kind == "iluk":
+        return factor_iluk(A, params["k"])
+    if kind == "ilut":
+        return factor_ilut(A, params["tau"], params["p"])
+    raise KeyError(kind)

@@ -1,0 +1,632 @@
+// C-ABI of libscaledilu.so: argument checks, context, level analysis,
+// per-kernel timing and the launch sequences of the smoother.
+//
+// One smoothing step (Algorithm 2 with the row scaling of eqs. extractD and
+// newD folded into U, eq. ILUsplit) is the launch sequence
+//     r = b - A x                          (1 launch; fused D^{-1} when m_L = 1)
+//     y_k = r - Ls y_{k-1},  k = 2..m_L     (y_1 = r costs nothing; the last
+//                                            launch writes s = D^{-1} y)
+//     z_k = s - Us z_{k-1},  k = 2..m_U     (z_1 = s; the last launch does x += z)
+// so 1 + (m_L - 1) + (m_U - 1) launches, each streaming one CSR matrix once.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/scaled_ilu.h"
+#include "internal.h"
+
+using namespace silu;
+
+namespace {
+
+struct LevelInfo {
+    int32_t *d_perm = nullptr;
+    std::vector<int32_t> level_ptr; // [depth + 1], host
+    std::vector<int64_t> level_nnz; // off-diagonal entries per level, host
+    int depth = 0;
+};
+
+using LevelKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
+
+struct Pending {
+    int kid;
+    hipEvent_t e0, e1;
+    double bytes;
+};
+
+} // namespace
+
+struct silu_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t bad_row = -1;
+    hipError_t last_hip = hipSuccess;
+    int32_t *d_flags = nullptr; // [4] device status words
+    std::map<LevelKey, LevelInfo> levels;
+    bool timing = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::string> knames;
+    std::vector<int64_t> klaunch;
+    std::vector<double> kms, kbytes;
+};
+
+namespace {
+
+int hip_fail(silu_ctx *c, hipError_t e)
+{
+    c->last_hip = e;
+    return SILU_ERR_HIP;
+}
+
+#define HIPCHK(ctx, expr)                                                                                           \
+    do {                                                                                                            \
+        hipError_t _e = (expr);                                                                                     \
+        if (_e != hipSuccess) return hip_fail((ctx), _e);                                                           \
+    } while (0)
+
+int kernel_id(silu_ctx *c, const char *name)
+{
+    for (size_t i = 0; i < c->knames.size(); i++)
+        if (c->knames[i] == name) return (int)i;
+    c->knames.emplace_back(name);
+    c->klaunch.push_back(0);
+    c->kms.push_back(0.0);
+    c->kbytes.push_back(0.0);
+    return (int)c->knames.size() - 1;
+}
+
+hipError_t get_event(silu_ctx *c, hipEvent_t *e)
+{
+    if (!c->free_events.empty()) {
+        *e = c->free_events.back();
+        c->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Launch through `fn(const char** name)`, bracketed by timing events when on.
+template <class F>
+int timed_launch(silu_ctx *c, double bytes, F &&fn)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        HIPCHK(c, get_event(c, &e0));
+        HIPCHK(c, get_event(c, &e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    const char *name = "kernel";
+    hipError_t err = fn(&name);
+    if (err != hipSuccess) return hip_fail(c, err);
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->pending.push_back({kernel_id(c, name), e0, e1, bytes});
+    }
+    return SILU_OK;
+}
+
+bool csr_ok(const silu_csr *M, int dtype)
+{
+    return M && M->row_ptr && M->n_rows > 0 && M->n_rows < INT32_MAX && M->n_rows == M->n_cols && M->nnz >= 0 &&
+           M->nnz < INT32_MAX && (M->nnz == 0 || (M->col_idx && M->val)) && M->dtype == dtype;
+}
+
+int check_square(const silu_csr *M, int dtype)
+{
+    if (!M || !M->row_ptr || (M->nnz > 0 && (!M->col_idx || !M->val))) return SILU_ERR_ARG;
+    if (M->n_rows != M->n_cols) return SILU_ERR_SHAPE;
+    if (!csr_ok(M, dtype)) return SILU_ERR_ARG;
+    return SILU_OK;
+}
+
+// Host-side structural check (SILU_VALIDATE).  side: 0 any, -1 strictly
+// lower, +1 strictly upper, 2 upper with the diagonal first.
+int validate(silu_ctx *c, const silu_csr *M, int side)
+{
+    const int64_t n = M->n_rows;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)std::max<int64_t>(M->nnz, 1));
+    HIPCHK(c, hipMemcpyAsync(rp.data(), M->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    if (M->nnz) HIPCHK(c, hipMemcpyAsync(col.data(), M->col_idx, (size_t)M->nnz * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (rp[0] != 0 || rp[(size_t)n] != M->nnz) {
+        c->bad_row = 0;
+        return SILU_ERR_PATTERN;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t a = rp[(size_t)i], b = rp[(size_t)i + 1];
+        bool bad = b < a;
+        for (int32_t p = a; !bad && p < b; p++) {
+            const int32_t j = col[(size_t)p];
+            bad = j < 0 || j >= n || (p > a && j <= col[(size_t)p - 1]) || (side == -1 && j >= i) ||
+                  (side == 1 && j <= i) || (side == 2 && (p == a ? j != i : j <= i));
+        }
+        if (side == 2 && b <= a) bad = true;
+        if (bad) {
+            c->bad_row = i;
+            return SILU_ERR_PATTERN;
+        }
+    }
+    return SILU_OK;
+}
+
+struct Ws {
+    char *base;
+    size_t vec; // bytes per vector slot
+    void *slot(int k) const { return base + (size_t)k * vec; }
+};
+
+size_t ws_vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
+
+double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift)
+{
+    double vb = 8, xb = 8, rb = 8, ob = 8;
+    if (p == Prec::MIX_RES) ob = 4;
+    if (p == Prec::MIX_L) vb = xb = ob = 4;
+    if (p == Prec::MIX_U) vb = xb = rb = ob = 4;
+    if (p == Prec::MIX_L1) vb = ob = 4;
+    double b = 4.0 * (double)(n + 1) + (double)nnz * (vb + 4.0) + (double)n * (xb + rb);
+    switch (epi) {
+    case EPI_STORE: b += n * ob; break;
+    case EPI_SCALE: b += n * (8.0 + ob); break;
+    case EPI_UPDATE: b += n * 16.0; break;
+    default: b += n * 24.0; break;
+    }
+    if (dshift) b += 8.0 * n;
+    return b;
+}
+
+int sweep(silu_ctx *c, Prec p, const SweepGeom &g, const silu_csr *N, const void *val, const void *xin,
+          const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift)
+{
+    SweepArgs a;
+    a.n = (int)N->n_rows;
+    a.rp = N->row_ptr;
+    a.col = N->col_idx;
+    a.val = val;
+    a.xin = xin;
+    a.rhs = rhs;
+    a.epi = epi;
+    a.out = out;
+    a.dinv = dinv;
+    a.x = x;
+    a.dshift = dshift;
+    const double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr);
+    return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
+}
+
+// ---- level analysis (Section 4: level-set scheduling) ----------------------
+int get_levels(silu_ctx *c, const silu_csr *T, int uplo, LevelInfo **out)
+{
+    LevelKey key{T->row_ptr, T->col_idx, T->n_rows, T->nnz, uplo};
+    auto it = c->levels.find(key);
+    if (it != c->levels.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    const int64_t n = T->n_rows;
+    std::vector<int32_t> rp((size_t)n + 1), col((size_t)std::max<int64_t>(T->nnz, 1));
+    HIPCHK(c, hipMemcpyAsync(rp.data(), T->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    if (T->nnz) HIPCHK(c, hipMemcpyAsync(col.data(), T->col_idx, (size_t)T->nnz * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<int32_t> lev((size_t)n, 0);
+    int32_t depth = 0;
+    for (int64_t s = 0; s < n; s++) {
+        const int64_t i = uplo == SILU_LOWER ? s : n - 1 - s;
+        int32_t l = 0;
+        for (int32_t p = rp[(size_t)i]; p < rp[(size_t)i + 1]; p++) {
+            const int32_t j = col[(size_t)p];
+            if (j == i) continue;
+            if (j < 0 || j >= n || (uplo == SILU_LOWER ? j > i : j < i)) {
+                c->bad_row = i;
+                return SILU_ERR_PATTERN;
+            }
+            l = std::max(l, lev[(size_t)j] + 1);
+        }
+        lev[(size_t)i] = l;
+        depth = std::max(depth, l + 1);
+    }
+    LevelInfo info;
+    info.depth = depth;
+    info.level_ptr.assign((size_t)depth + 1, 0);
+    info.level_nnz.assign((size_t)depth, 0);
+    for (int64_t i = 0; i < n; i++) {
+        info.level_ptr[(size_t)lev[(size_t)i] + 1]++;
+        int64_t off = 0;
+        for (int32_t p = rp[(size_t)i]; p < rp[(size_t)i + 1]; p++) off += col[(size_t)p] != i;
+        info.level_nnz[(size_t)lev[(size_t)i]] += off;
+    }
+    for (int32_t l = 0; l < depth; l++) info.level_ptr[(size_t)l + 1] += info.level_ptr[(size_t)l];
+    std::vector<int32_t> perm((size_t)n), fill(info.level_ptr.begin(), info.level_ptr.end() - 1);
+    for (int64_t i = 0; i < n; i++) perm[(size_t)fill[(size_t)lev[(size_t)i]]++] = (int32_t)i;
+    HIPCHK(c, hipMalloc(&info.d_perm, (size_t)n * 4));
+    hipError_t e = hipMemcpy(info.d_perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(info.d_perm);
+        return hip_fail(c, e);
+    }
+    auto res = c->levels.emplace(key, std::move(info));
+    *out = &res.first->second;
+    return SILU_OK;
+}
+
+int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const double *rhs, double *out,
+               const double *dinv, double *s_out, double *xupd)
+{
+    LevelArgs a;
+    a.perm = li->d_perm;
+    a.rp = T->row_ptr;
+    a.col = T->col_idx;
+    a.val = (const double *)T->val;
+    a.rhs = rhs;
+    a.out = out;
+    a.dinv = dinv;
+    a.s_out = s_out;
+    a.xupd = xupd;
+    for (int l = 0; l < li->depth; l++) {
+        const int start = li->level_ptr[(size_t)l], count = li->level_ptr[(size_t)l + 1] - start;
+        double bytes = count * (4.0 + 8.0 + 8.0 + 8.0 + 8.0) + 12.0 * (double)li->level_nnz[(size_t)l];
+        if (s_out) bytes += count * 16.0;
+        if (xupd) bytes += count * 16.0;
+        int st = timed_launch(c, bytes, [&](const char **nm) {
+            return launch_level(a, unit, start, count, c->stream, nm);
+        });
+        if (st) return st;
+    }
+    return SILU_OK;
+}
+
+int check_finite(silu_ctx *c, int64_t n, const double *x)
+{
+    HIPCHK(c, launch_init_flags(c->d_flags, 4, INT32_MAX, c->stream));
+    HIPCHK(c, launch_finite_check((int)n, x, c->d_flags, c->stream));
+    int32_t h[4];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[2] != INT32_MAX) {
+        c->bad_row = h[2];
+        return SILU_ERR_NONFINITE;
+    }
+    return SILU_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int silu_create(silu_ctx **ctx, void *hip_stream)
+{
+    if (!ctx) return SILU_ERR_ARG;
+    *ctx = nullptr;
+    silu_ctx *c = new (std::nothrow) silu_ctx();
+    if (!c) return SILU_ERR_NOMEM;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->d_flags, 4 * sizeof(int32_t));
+    if (e != hipSuccess) {
+        delete c;
+        return SILU_ERR_HIP;
+    }
+    *ctx = c;
+    return SILU_OK;
+}
+
+int silu_destroy(silu_ctx *c)
+{
+    if (!c) return SILU_ERR_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &kv : c->levels) (void)hipFree(kv.second.d_perm);
+    for (auto &p : c->pending) {
+        (void)hipEventDestroy(p.e0);
+        (void)hipEventDestroy(p.e1);
+    }
+    for (auto e : c->free_events) (void)hipEventDestroy(e);
+    (void)hipFree(c->d_flags);
+    delete c;
+    return SILU_OK;
+}
+
+int silu_set_stream(silu_ctx *c, void *hip_stream)
+{
+    if (!c) return SILU_ERR_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return SILU_OK;
+}
+
+int64_t silu_bad_row(const silu_ctx *c) { return c ? c->bad_row : -1; }
+
+int silu_last_hip_error(const silu_ctx *c) { return c ? (int)c->last_hip : 0; }
+
+const char *silu_status_string(int s)
+{
+    switch (s) {
+    case SILU_OK: return "ok";
+    case SILU_ERR_ARG: return "invalid argument";
+    case SILU_ERR_SHAPE: return "dimension mismatch";
+    case SILU_ERR_PATTERN: return "CSR pattern violates the required structure";
+    case SILU_ERR_ZERO_PIVOT: return "zero or non-finite pivot";
+    case SILU_ERR_NONFINITE: return "non-finite value in the result";
+    case SILU_ERR_NOMEM: return "workspace too small or out of memory";
+    case SILU_ERR_HIP: return "HIP runtime error";
+    case SILU_ERR_UNSUPPORTED: return "unsupported combination of arguments";
+    default: return "unknown status";
+    }
+}
+
+int silu_workspace_size(silu_ctx *c, int64_t n, int flags, size_t *bytes)
+{
+    (void)flags;
+    if (!c || !bytes || n < 0) return SILU_ERR_ARG;
+    *bytes = 4 * ws_vec_bytes(n);
+    return SILU_OK;
+}
+
+int ilu_scale_factors(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags)
+{
+    if (!c || !L || !U || !F) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(U, SILU_F64);
+    if (st) return st;
+    st = check_square(L, SILU_F64);
+    if (st) return st;
+    const int64_t n = U->n_rows;
+    if (L->n_rows != n) return SILU_ERR_SHAPE;
+    if (U->nnz < n) return SILU_ERR_PATTERN;
+    if (!F->Us.row_ptr || !F->d || !F->dinv || (U->nnz > n && (!F->Us.col_idx || !F->Us.val)))
+        return SILU_ERR_ARG;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, L, -1))) return st;
+        if ((st = validate(c, U, 2))) return st;
+    }
+    const bool noscale = (flags & SILU_NO_SCALING) != 0;
+    F->Ls = *L;
+    F->Us.n_rows = F->Us.n_cols = n;
+    F->Us.nnz = U->nnz - n;
+    F->Us.dtype = SILU_F64;
+    F->scaled = noscale ? 0 : 1;
+    HIPCHK(c, launch_init_flags(c->d_flags, 4, INT32_MAX, c->stream));
+    HIPCHK(c, launch_scale_rows((int)n, U->row_ptr, U->col_idx, (const double *)U->val, F->Us.row_ptr,
+                                F->Us.col_idx, (double *)F->Us.val, F->d, F->dinv, F->Us_val32, noscale ? 1 : 0,
+                                (int32_t)(U->nnz - n), c->d_flags, c->stream));
+    if (F->Ls_val32) HIPCHK(c, launch_to_f32(L->nnz, (const double *)L->val, F->Ls_val32, c->stream));
+    int32_t h[4];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[0] != INT32_MAX) {
+        c->bad_row = h[0];
+        return SILU_ERR_PATTERN;
+    }
+    if (h[1] != INT32_MAX) {
+        c->bad_row = h[1];
+        return SILU_ERR_ZERO_PIVOT;
+    }
+    return SILU_OK;
+}
+
+int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes)
+{
+    if (!c || !A || !F || !b || !x || !ws) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    const bool mixed = (flags & SILU_MIXED) != 0, direct = (flags & SILU_DIRECT) != 0;
+    if (outer_sweeps < 1 || (!direct && (m_L < 1 || m_U < 1))) return SILU_ERR_ARG;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    if ((st = check_square(&F->Ls, SILU_F64))) return st;
+    if ((st = check_square(&F->Us, SILU_F64))) return st;
+    const int64_t n = A->n_rows;
+    if (F->Ls.n_rows != n || F->Us.n_rows != n) return SILU_ERR_SHAPE;
+    if (!F->dinv || (!F->scaled && !F->d)) return SILU_ERR_ARG;
+    if (mixed && ((F->Ls.nnz > 0 && !F->Ls_val32) || (F->Us.nnz > 0 && !F->Us_val32))) return SILU_ERR_UNSUPPORTED;
+    if (!F->scaled && (mixed || direct)) return SILU_ERR_UNSUPPORTED;
+    if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
+    size_t need = 0;
+    silu_workspace_size(c, n, flags, &need);
+    if (ws_bytes < need) return SILU_ERR_NOMEM;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+        if ((st = validate(c, &F->Ls, -1))) return st;
+        if ((st = validate(c, &F->Us, 1))) return st;
+    }
+    Ws w{(char *)ws, ws_vec_bytes(n)};
+    void *r = w.slot(0), *s = w.slot(1), *tmp[2] = {w.slot(2), w.slot(3)};
+    const SweepGeom gA = pick_geom(n, A->nnz, flags), gL = pick_geom(n, F->Ls.nnz, flags),
+                    gU = pick_geom(n, F->Us.nnz, flags);
+    const bool scaled = F->scaled != 0;
+    const double *dshift = scaled ? nullptr : F->d;
+    const Prec pL = mixed ? Prec::MIX_L : Prec::F64, pU = mixed ? Prec::MIX_U : Prec::F64;
+    const void *Lval = mixed ? (const void *)F->Ls_val32 : F->Ls.val;
+    const void *Uval = mixed ? (const void *)F->Us_val32 : F->Us.val;
+    const int to_s = scaled ? EPI_SCALE : EPI_STORE;
+    const int to_x = scaled ? EPI_SCALE_UPDATE : EPI_UPDATE;
+
+    for (int it = 0; it < outer_sweeps; it++) {
+        if (direct) {
+            LevelInfo *lL = nullptr, *lU = nullptr;
+            if ((st = get_levels(c, &F->Ls, SILU_LOWER, &lL))) return st;
+            if ((st = get_levels(c, &F->Us, SILU_UPPER, &lU))) return st;
+            if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, r, nullptr, nullptr, nullptr))) return st;
+            if ((st = run_levels(c, &F->Ls, lL, 1, (const double *)r, (double *)tmp[0], F->dinv, (double *)s,
+                                 nullptr)))
+                return st;
+            if ((st = run_levels(c, &F->Us, lU, 1, (const double *)s, (double *)tmp[1], nullptr, nullptr, x)))
+                return st;
+            continue;
+        }
+        // residual r = b - A x (fused with D^{-1} when m_L = 1)
+        if (m_L >= 2) {
+            st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, r, nullptr, nullptr, nullptr);
+        } else if (scaled) {
+            st = sweep(c, mixed ? Prec::MIX_RES : Prec::F64, gA, A, A->val, x, b, EPI_SCALE, s, F->dinv, nullptr,
+                       nullptr);
+        } else {
+            st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, s, nullptr, nullptr, nullptr);
+        }
+        if (st) return st;
+        if (m_L == 1 && m_U == 1) {
+            st = timed_launch(c, 24.0 * (double)n, [&](const char **nm) {
+                *nm = "axpy";
+                return launch_axpy((int)n, s, mixed ? 1 : 0, x, c->stream);
+            });
+            if (st) return st;
+            continue;
+        }
+        // L sweeps: y_1 = r, y_k = r - Ls y_{k-1}
+        const void *cur = r;
+        for (int k = 2; k <= m_L; k++) {
+            const bool last = k == m_L;
+            void *out = last ? s : tmp[k & 1];
+            int epi = last ? (m_U >= 2 ? to_s : to_x) : EPI_STORE;
+            // in the mixed form y_1 = (float) r is never stored: the first sweep gathers r and rounds it
+            const Prec p = (mixed && k == 2) ? Prec::MIX_L1 : pL;
+            st = sweep(c, p, gL, &F->Ls, Lval, cur, r, epi, (epi == EPI_SCALE || epi == EPI_STORE) ? out : nullptr,
+                       F->dinv, x, nullptr);
+            if (st) return st;
+            cur = out;
+        }
+        // U sweeps: z_1 = s, z_k = s - Us z_{k-1}; the last adds z to x
+        cur = s;
+        for (int k = 2; k <= m_U; k++) {
+            const bool last = k == m_U;
+            void *out = last ? nullptr : tmp[k & 1];
+            st = sweep(c, pU, gU, &F->Us, Uval, cur, s, last ? EPI_UPDATE : EPI_STORE, out, F->dinv, x, dshift);
+            if (st) return st;
+            cur = out;
+        }
+    }
+    if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
+    return SILU_OK;
+}
+
+int ilu_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x, int outer_sweeps,
+               int inner_iters, int flags, void *ws, size_t ws_bytes)
+{
+    return ilu_smooth2(c, A, F, b, x, outer_sweeps, inner_iters, inner_iters, flags, ws, ws_bytes);
+}
+
+int trisolve_direct(silu_ctx *c, const silu_csr *T, int uplo, int diag, const double *rhs, double *out, int flags)
+{
+    if (!c || !T || !rhs || !out || rhs == out) return SILU_ERR_ARG;
+    if ((uplo != SILU_LOWER && uplo != SILU_UPPER) || (diag != SILU_UNIT && diag != SILU_NONUNIT)) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(T, SILU_F64);
+    if (st) return st;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, T, 0))) return st;
+    }
+    LevelInfo *li = nullptr;
+    if ((st = get_levels(c, T, uplo, &li))) return st;
+    return run_levels(c, T, li, diag == SILU_UNIT ? 1 : 0, rhs, out, nullptr, nullptr, nullptr);
+}
+
+int trisolve_iter(silu_ctx *c, const silu_csr *T, const double *dinv, const double *rhs, double *out, int m,
+                  int flags, void *ws, size_t ws_bytes)
+{
+    if (!c || !T || !rhs || !out || !ws || m < 1) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(T, SILU_F64);
+    if (st) return st;
+    const int64_t n = T->n_rows;
+    if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
+    size_t need = 0;
+    silu_workspace_size(c, n, 0, &need);
+    if (ws_bytes < need) return SILU_ERR_NOMEM;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, T, 0))) return st;
+    }
+    Ws w{(char *)ws, ws_vec_bytes(n)};
+    double *sv = m == 1 ? out : (double *)w.slot(0);
+    void *tmp[2] = {w.slot(1), w.slot(2)};
+    st = timed_launch(c, (dinv ? 24.0 : 16.0) * (double)n, [&](const char **nm) {
+        *nm = "scale_copy";
+        return launch_scale_copy((int)n, rhs, dinv, sv, c->stream);
+    });
+    if (st) return st;
+    const SweepGeom g = pick_geom(n, T->nnz, flags);
+    const void *cur = sv;
+    for (int k = 2; k <= m; k++) {
+        void *o = k == m ? (void *)out : tmp[k & 1];
+        if ((st = sweep(c, Prec::F64, g, T, T->val, cur, sv, EPI_STORE, o, nullptr, nullptr, nullptr))) return st;
+        cur = o;
+    }
+    return SILU_OK;
+}
+
+int silu_analyze(silu_ctx *c, const silu_csr *T, int uplo, int32_t *depth, int32_t *rows_per_level)
+{
+    if (!c || !T || !depth || (uplo != SILU_LOWER && uplo != SILU_UPPER)) return SILU_ERR_ARG;
+    int st = check_square(T, SILU_F64);
+    if (st) return st;
+    LevelInfo *li = nullptr;
+    if ((st = get_levels(c, T, uplo, &li))) return st;
+    *depth = li->depth;
+    if (rows_per_level)
+        for (int l = 0; l < li->depth; l++) rows_per_level[l] = li->level_ptr[(size_t)l + 1] - li->level_ptr[(size_t)l];
+    return SILU_OK;
+}
+
+int silu_set_timing(silu_ctx *c, int enable)
+{
+    if (!c) return SILU_ERR_ARG;
+    c->timing = enable != 0;
+    return SILU_OK;
+}
+
+int silu_stats_collect(silu_ctx *c)
+{
+    if (!c) return SILU_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, p.e0, p.e1));
+        c->klaunch[(size_t)p.kid] += 1;
+        c->kms[(size_t)p.kid] += ms;
+        c->kbytes[(size_t)p.kid] += p.bytes;
+        c->free_events.push_back(p.e0);
+        c->free_events.push_back(p.e1);
+    }
+    c->pending.clear();
+    return (int)c->knames.size();
+}
+
+int silu_stats_get(silu_ctx *c, int idx, char *name, int name_len, int64_t *launches, double *ms, double *bytes)
+{
+    if (!c || idx < 0 || idx >= (int)c->knames.size()) return SILU_ERR_ARG;
+    if (name && name_len > 0) {
+        std::strncpy(name, c->knames[(size_t)idx].c_str(), (size_t)name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (launches) *launches = c->klaunch[(size_t)idx];
+    if (ms) *ms = c->kms[(size_t)idx];
+    if (bytes) *bytes = c->kbytes[(size_t)idx];
+    return SILU_OK;
+}
+
+int silu_stats_reset(silu_ctx *c)
+{
+    if (!c) return SILU_ERR_ARG;
+    int st = silu_stats_collect(c);
+    if (st < 0) return st;
+    for (size_t i = 0; i < c->knames.size(); i++) {
+        c->klaunch[i] = 0;
+        c->kms[i] = 0.0;
+        c->kbytes[i] = 0.0;
+    }
+    return SILU_OK;
+}
+
+int silu_stream_copy(silu_ctx *c, const void *src, void *dst, size_t bytes)
+{
+    if (!c || !src || !dst || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return SILU_ERR_ARG;
+    return timed_launch(c, 2.0 * (double)bytes, [&](const char **nm) {
+        *nm = "stream_copy";
+        return launch_copy(src, dst, bytes, c->stream);
+    });
+}
+
+} // extern "C"

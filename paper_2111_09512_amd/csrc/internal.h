@@ -1,0 +1,78 @@
+// Internal declarations of libscaledilu.so (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace silu {
+
+// What a CSR sweep kernel does with t_i = rhs_i - sum_j N_ij xin_j (after
+// rounding t to the iterate type IT of its precision):
+enum Epi : int {
+    EPI_STORE = 0,        // out_i = t_i
+    EPI_SCALE = 1,        // out_i = dinv_i * t_i                  (s = D^{-1} y)
+    EPI_UPDATE = 2,       // x_i = x_i + t_i                       (x += z)
+    EPI_SCALE_UPDATE = 3  // x_i = x_i + (OT)(dinv_i * t_i)        (x += D^{-1} y when m_U = 1)
+};
+
+// Precision of one sweep launch.
+enum class Prec : int {
+    F64 = 0,     // FP64 matrix, iterate, rhs, accumulation (residual and FP64 sweeps)
+    MIX_RES = 1, // FP64 residual whose result is rounded to FP32 before D^{-1} (mixed, m_L = 1)
+    MIX_L = 2,   // FP32 matrix/iterate/accumulation, FP64 rhs r (mixed L sweeps)
+    MIX_U = 3,   // FP32 matrix/iterate/accumulation/rhs (mixed U sweeps)
+    MIX_L1 = 4   // first mixed L sweep: gathers y_1 = r from the FP64 residual, rounding each value to FP32
+};
+
+enum class SweepKernel : int { STREAM = 0, VECTOR = 1 };
+
+struct SweepArgs {
+    int n;
+    const int32_t *rp;
+    const int32_t *col;
+    const void *val;
+    const void *xin;      // iterate gathered through col
+    const void *rhs;      // right-hand side of the Richardson step
+    int epi;
+    void *out;            // EPI_STORE / EPI_SCALE destination
+    const double *dinv;   // EPI_SCALE / EPI_SCALE_UPDATE
+    double *x;            // EPI_UPDATE / EPI_SCALE_UPDATE
+    const double *dshift; // unscaled variant: adds (d_i - 1) * xin_i to the row sum (FP64 only)
+};
+
+// Kernel geometry for a sweep, picked from the mean row length.
+struct SweepGeom {
+    SweepKernel kind;
+    int rows_per_block; // STREAM: rows per workgroup
+    int lanes;          // VECTOR: lanes per row
+};
+
+SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);
+hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name);
+
+struct LevelArgs {
+    const int32_t *perm; // rows ordered by level
+    const int32_t *rp;
+    const int32_t *col;
+    const double *val;
+    const double *rhs;
+    double *out;
+    const double *dinv; // optional: s_out = dinv * out
+    double *s_out;
+    double *xupd;       // optional: xupd += out
+};
+hipError_t launch_level(const LevelArgs &a, int unit, int start, int count, hipStream_t s, const char **name);
+
+hipError_t launch_scale_rows(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, int32_t *Usrp,
+                             int32_t *Uscol, double *Usval, double *d, double *dinv, float *Us32, int noscale,
+                             int32_t us_nnz, int32_t *flags, hipStream_t s);
+hipError_t launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
+hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, double *x, hipStream_t s);
+hipError_t launch_init_flags(int32_t *flags, int count, int32_t value, hipStream_t s);
+hipError_t launch_finite_check(int n, const double *x, int32_t *flags, hipStream_t s);
+hipError_t launch_scale_copy(int n, const double *rhs, const double *dinv, double *out, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace silu

@@ -1,0 +1,189 @@
+// Set-up and auxiliary kernels: row scaling of the U factor, FP32 copies,
+// the level-scheduled substitution step, small vector kernels and a
+// streaming copy for bandwidth calibration.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace silu {
+namespace {
+
+// flags[0]: first row whose U row does not start with its diagonal (or has
+//           an entry left of it); flags[1]: first row with a zero or
+//           non-finite pivot.  Both start at INT32_MAX.
+__global__ void __launch_bounds__(256) k_scale_rows(int n, const int32_t *__restrict__ Urp,
+                                                    const int32_t *__restrict__ Ucol,
+                                                    const double *__restrict__ Uval, int32_t *__restrict__ Usrp,
+                                                    int32_t *__restrict__ Uscol, double *__restrict__ Usval,
+                                                    double *__restrict__ d, double *__restrict__ dinv,
+                                                    float *__restrict__ Us32, int noscale, int32_t us_nnz,
+                                                    int32_t *flags)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int p0 = Urp[i], p1 = Urp[i + 1];
+    if (i == n - 1) Usrp[n] = p1 - n;
+    Usrp[i] = p0 - i;
+    if (p1 <= p0 || Ucol[p0] != i) {
+        atomicMin(&flags[0], i);
+        return;
+    }
+    const double u = Uval[p0];
+    if (!(u != 0.0) || !isfinite(u)) atomicMin(&flags[1], i);
+    d[i] = u;
+    dinv[i] = 1.0 / u;
+    // rows before i each lost exactly their diagonal; a malformed U (flagged
+    // above by the row that lacks it) could shift o, so every store is bounded
+    int o = p0 - i;
+    for (int p = p0 + 1; p < p1; ++p, ++o) {
+        const int j = Ucol[p];
+        if (j <= i) atomicMin(&flags[0], i);
+        if (o < 0 || o >= us_nnz) {
+            atomicMin(&flags[0], i);
+            continue;
+        }
+        const double v = noscale ? Uval[p] : Uval[p] / u;
+        Uscol[o] = j;
+        Usval[o] = v;
+        if (Us32) Us32[o] = (float)v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (float)src[i];
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) k_axpy(int n, const ST *__restrict__ s, double *__restrict__ x)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) x[i] = x[i] + (double)s[i];
+}
+
+__global__ void k_init_flags(int32_t *flags, int count, int32_t value)
+{
+    const int i = (int)threadIdx.x;
+    if (i < count) flags[i] = value;
+}
+
+__global__ void __launch_bounds__(256) k_finite_check(int n, const double *__restrict__ x, int32_t *flags)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n && !isfinite(x[i])) atomicMin(&flags[2], i);
+}
+
+// One level of a level-scheduled substitution: each lane finishes one row
+// whose dependencies all lie in earlier levels.  The row sum runs in
+// ascending column order, like a sequential substitution.
+template <int UNIT>
+__global__ void __launch_bounds__(256) k_level(LevelArgs a, int start, int count)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= count) return;
+    const int i = a.perm[start + t];
+    const int p0 = a.rp[i], p1 = a.rp[i + 1];
+    double sum = 0.0, dii = 1.0;
+    for (int p = p0; p < p1; ++p) {
+        const int j = a.col[p];
+        const double v = a.val[p];
+        if (j == i) {
+            dii = v;
+            continue;
+        }
+        sum = sum + v * a.out[j];
+    }
+    double v = a.rhs[i] - sum;
+    if (!UNIT) v = v / dii;
+    a.out[i] = v;
+    if (a.s_out) a.s_out[i] = a.dinv[i] * v;
+    if (a.xupd) a.xupd[i] = a.xupd[i] + v;
+}
+
+__global__ void __launch_bounds__(256) k_scale_copy(int n, const double *__restrict__ rhs,
+                                                    const double *__restrict__ dinv, double *__restrict__ out)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) out[i] = dinv ? dinv[i] * rhs[i] : rhs[i];
+}
+
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
+
+} // namespace
+
+hipError_t launch_scale_rows(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, int32_t *Usrp,
+                             int32_t *Uscol, double *Usval, double *d, double *dinv, float *Us32, int noscale,
+                             int32_t us_nnz, int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_rows, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, Urp, Ucol, Uval, Usrp, Uscol,
+                       Usval, d, dinv, Us32, noscale, us_nnz, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(blocks_for(n, 256), 65536);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, double *x, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (s_is_f32)
+        hipLaunchKernelGGL(k_axpy<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const float *)s_vec, x);
+    else
+        hipLaunchKernelGGL(k_axpy<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const double *)s_vec, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_flags(int32_t *flags, int count, int32_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, s, flags, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(int n, const double *x, int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finite_check, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, x, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_level(const LevelArgs &a, int unit, int start, int count, hipStream_t s, const char **name)
+{
+    if (name) *name = "level_f64";
+    if (count <= 0) return hipSuccess;
+    if (unit)
+        hipLaunchKernelGGL(k_level<1>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count);
+    else
+        hipLaunchKernelGGL(k_level<0>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(int n, const double *rhs, const double *dinv, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rhs, dinv, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n16 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    return hipGetLastError();
+}
+
+} // namespace silu

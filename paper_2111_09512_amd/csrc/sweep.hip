@@ -1,0 +1,264 @@
+// Fused Richardson-sweep kernels for gfx950 (CDNA4, wave64).
+//
+// One launch computes, for every row i of a CSR matrix N,
+//     t_i = rhs_i - sum_j N_ij xin_j
+// and applies an epilogue (store t, store D^{-1} t, x += t, x += D^{-1} t).
+// With N = A and rhs = b this is the residual r = b - A x (eq. ILUsplit);
+// with N = the strictly triangular part of a unit factor it is one Richardson
+// step y_k = rhs - N y_{k-1} (eq. richard; Algorithm 2).  The diagonal scaling
+// and the update of x are fused into the last sweep, so each step reads its
+// matrix exactly once.  The work is bandwidth-bound (about 0.1 flop per byte),
+// so there is no MFMA: the kernels are shaped for coalesced HBM streaming.
+//
+// Two shapes:
+//  * CSR-stream (short rows, the 3-6 entries of ILU(0)/ILU(1) factors): a
+//    workgroup owns RPB consecutive rows, streams their contiguous val/col
+//    range with unit-stride loads, writes the products val*xin[col] to LDS,
+//    then one lane per row adds its products in ascending column order.
+//  * vector-CSR (long rows): K lanes per row, strided over the row, partial
+//    sums combined with cross-lane shuffles.
+// Workgroups are remapped so that each XCD (the hardware deals workgroups
+// round-robin over the 8 XCDs) walks one contiguous slab of rows, keeping the
+// gathered iterate window resident in that XCD's L2.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace silu {
+namespace {
+
+// precision bundles: value, gathered-iterate, rhs, accumulate, iterate-rounding, output types
+struct TF64 {
+    using VT = double;
+    using XT = double;
+    using RT = double;
+    using AT = double;
+    using IT = double;
+    using OT = double;
+};
+struct TMixRes {
+    using VT = double;
+    using XT = double;
+    using RT = double;
+    using AT = double;
+    using IT = float;
+    using OT = float;
+};
+struct TMixL {
+    using VT = float;
+    using XT = float;
+    using RT = double;
+    using AT = float;
+    using IT = float;
+    using OT = float;
+};
+struct TMixL1 {
+    using VT = float;
+    using XT = double;
+    using RT = double;
+    using AT = float;
+    using IT = float;
+    using OT = float;
+};
+struct TMixU {
+    using VT = float;
+    using XT = float;
+    using RT = float;
+    using AT = float;
+    using IT = float;
+    using OT = float;
+};
+
+__device__ __forceinline__ int xcd_slab_block(int b, int G)
+{
+    const int q = G >> 3, r = G & 7, xcd = b & 7, k = b >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+template <class T>
+__device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T::AT t)
+{
+    using IT = typename T::IT;
+    using OT = typename T::OT;
+    const IT v = (IT)t;
+    switch (a.epi) {
+    case EPI_STORE:
+        ((OT *)a.out)[row] = (OT)v;
+        break;
+    case EPI_SCALE:
+        ((OT *)a.out)[row] = (OT)(a.dinv[row] * (double)v);
+        break;
+    case EPI_UPDATE:
+        a.x[row] = a.x[row] + (double)v;
+        break;
+    default: // EPI_SCALE_UPDATE
+        a.x[row] = a.x[row] + (double)(OT)(a.dinv[row] * (double)v);
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR-stream: RPB rows per workgroup of BLOCK lanes (RPB <= BLOCK); products
+// staged in LDS in chunks of CAP entries.
+// ---------------------------------------------------------------------------
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    static_assert(RPB <= BLOCK && CAP % BLOCK == 0, "geometry");
+    __shared__ AT prod[CAP];
+    __shared__ int32_t srp[RPB + 1];
+
+    const int blk = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int r0 = blk * RPB;
+    const int nr = min(RPB, a.n - r0);
+    const int tid = (int)threadIdx.x;
+    for (int t = tid; t <= nr; t += BLOCK) srp[t] = a.rp[r0 + t];
+    __syncthreads();
+
+    const VT *__restrict__ val = (const VT *)a.val;
+    const int32_t *__restrict__ col = a.col;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    const int e0 = srp[0], e1 = srp[nr];
+
+    AT sum = (AT)0;
+    int mylo = 0, myhi = 0;
+    if (tid < nr) {
+        mylo = srp[tid];
+        myhi = srp[tid + 1];
+        if (a.dshift) sum = (AT)((a.dshift[r0 + tid] - 1.0) * (double)xin[r0 + tid]);
+    }
+    for (int c0 = e0; c0 < e1; c0 += CAP) {
+        const int c1 = min(c0 + CAP, e1);
+#pragma unroll 4
+        for (int e = c0 + tid; e < c1; e += BLOCK) prod[e - c0] = (AT)val[e] * (AT)xin[col[e]];
+        __syncthreads();
+        const int lo = max(mylo, c0), hi = min(myhi, c1);
+        for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
+        __syncthreads();
+    }
+    if (tid < nr) {
+        const int row = r0 + tid;
+        const AT t = (AT)((const RT *)a.rhs)[row] - sum;
+        epilogue<T>(a, row, t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vector-CSR: K lanes per row (K divides 64).
+// ---------------------------------------------------------------------------
+template <class T, int BLOCK, int K>
+__global__ void __launch_bounds__(BLOCK) k_sweep_vector(SweepArgs a)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    static_assert(64 % K == 0 && BLOCK % 64 == 0, "geometry");
+    const int blk = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int lane = (int)threadIdx.x & (K - 1);
+    const int row = (blk * BLOCK + (int)threadIdx.x) / K;
+    const bool live = row < a.n;
+    const VT *__restrict__ val = (const VT *)a.val;
+    const int32_t *__restrict__ col = a.col;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    AT sum = (AT)0;
+    if (live) {
+        const int rs = a.rp[row], re = a.rp[row + 1];
+        for (int e = rs + lane; e < re; e += K) sum = sum + (AT)val[e] * (AT)xin[col[e]];
+    }
+#pragma unroll
+    for (int off = K / 2; off > 0; off >>= 1) sum = sum + __shfl_xor(sum, off, K);
+    if (live && lane == 0) {
+        if (a.dshift) sum = sum + (AT)((a.dshift[row] - 1.0) * (double)xin[row]);
+        const AT t = (AT)((const RT *)a.rhs)[row] - sum;
+        epilogue<T>(a, row, t);
+    }
+}
+
+template <class T, int BLOCK, int RPB, int CAP>
+hipError_t go_stream(const SweepArgs &a, hipStream_t s)
+{
+    const int grid = (a.n + RPB - 1) / RPB;
+    hipLaunchKernelGGL((k_sweep_stream<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, int K>
+hipError_t go_vector(const SweepArgs &a, hipStream_t s)
+{
+    constexpr int BLOCK = 256;
+    const long long rows_per_block = BLOCK / K;
+    const int grid = (int)((a.n + rows_per_block - 1) / rows_per_block);
+    hipLaunchKernelGGL((k_sweep_vector<T, BLOCK, K>), dim3(grid), dim3(BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (g.kind == SweepKernel::STREAM) {
+        switch (g.rows_per_block) {
+        case 256: return go_stream<T, 256, 256, 1024>(a, s);
+        case 128: return go_stream<T, 256, 128, 1024>(a, s);
+        case 64: return go_stream<T, 256, 64, 2048>(a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (g.lanes) {
+    case 4: return go_vector<T, 4>(a, s);
+    case 8: return go_vector<T, 8>(a, s);
+    case 16: return go_vector<T, 16>(a, s);
+    case 32: return go_vector<T, 32>(a, s);
+    case 64: return go_vector<T, 64>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+const char *kname(Prec p, SweepKernel k)
+{
+    static const char *names[2][5] = {
+        {"sweep_stream_f64", "sweep_stream_mixres", "sweep_stream_mixL", "sweep_stream_mixU", "sweep_stream_mixL1"},
+        {"sweep_vector_f64", "sweep_vector_mixres", "sweep_vector_mixL", "sweep_vector_mixU", "sweep_vector_mixL1"}};
+    return names[(int)k][(int)p];
+}
+
+} // namespace
+
+SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
+{
+    const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
+    SweepGeom g;
+    bool stream = mean <= 12.0;
+    if (flags & 0x100) stream = true;  // SILU_KERNEL_STREAM
+    if (flags & 0x200) stream = false; // SILU_KERNEL_VECTOR
+    if (stream) {
+        g.kind = SweepKernel::STREAM;
+        g.rows_per_block = mean <= 4.0 ? 256 : (mean <= 8.0 ? 128 : 64);
+        g.lanes = 1;
+    } else {
+        g.kind = SweepKernel::VECTOR;
+        g.rows_per_block = 0;
+        g.lanes = mean <= 6.0 ? 4 : (mean <= 12.0 ? 8 : (mean <= 24.0 ? 16 : (mean <= 48.0 ? 32 : 64)));
+    }
+    return g;
+}
+
+hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name)
+{
+    if (name) *name = kname(p, g.kind);
+    switch (p) {
+    case Prec::F64: return dispatch<TF64>(g, a, s);
+    case Prec::MIX_RES: return dispatch<TMixRes>(g, a, s);
+    case Prec::MIX_L: return dispatch<TMixL>(g, a, s);
+    case Prec::MIX_U: return dispatch<TMixU>(g, a, s);
+    case Prec::MIX_L1: return dispatch<TMixL1>(g, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+} // namespace silu

@@ -1,0 +1,309 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle, on
+seeded inputs that span several workgroups and end in a ragged tail.
+
+Tolerances: FP64 path 1e-12 relative, mixed path 1e-5 relative to the FP64
+oracle (both element by element against the output's max norm, and norm-wise).
+Where the kernel sums each row in the oracle's order (CSR-stream sweeps, the
+level-scheduled substitution, the row scaling) the result is also checked to
+be bit-identical."""
+import numpy as np
+import pytest
+
+from paper_2111_09512_amd import workloads as W
+from tests.gpu_common import F64_TOL, MIXED_TOL, Case, assert_close, dev, host, need_gpu, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    need_gpu()
+    from paper_2111_09512_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context()
+
+
+SMALL = {
+    "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
+    "vardens13_ilu1": (lambda: W.vardens7(13), "iluk", {"k": 1}),
+    "aniso11_ilut": (lambda: W.aniso27(11), "ilut", {"tau": 1e-3, "p": 20}),
+    "perm9": (lambda: W.permuted_longrange7(9, seed=1), "ilu0", {}),
+}
+
+
+@pytest.fixture(scope="module")
+def cases(orc, B, ctx):
+    out = {}
+    for name, (make, kind, params) in SMALL.items():
+        out[name] = Case(orc, B, ctx, make(), kind, params, fp32=True)
+    return out
+
+
+# --------------------------------------------------------------------------
+# row scaling (eqs. extractD, newD)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_scale_factors_bitwise(cases, name):
+    say("scale", name)
+    c = cases[name]
+    F = c.F
+    np.testing.assert_array_equal(host(F.Us.row_ptr), c.Us.row_ptr)
+    np.testing.assert_array_equal(host(F.Us.col_idx), c.Us.col)
+    np.testing.assert_array_equal(host(F.Us.val), c.Us.val)
+    np.testing.assert_array_equal(host(F.d), c.d)
+    np.testing.assert_array_equal(host(F.dinv), c.dinv)
+    np.testing.assert_array_equal(host(F.Ls_val32), c.Ls.val.astype(np.float32))
+    np.testing.assert_array_equal(host(F.Us_val32), c.Us.val.astype(np.float32))
+
+
+def test_scale_factors_errors(B, ctx):
+    say("scale errors")
+    U = W.CSR.from_dense(np.array([[2.0, 1.0, 0.0], [0.0, 1.0, 3.0], [0.0, 0.0, 1.0]]))
+    U.val[U.row_ptr[1]] = 0.0
+    L = W.CSR.from_dense(np.zeros((3, 3)))
+    L.row_ptr[:] = 0
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_scale_factors(B.Csr.from_host(L), B.Csr.from_host(U))
+    assert e.value.status == -4 and e.value.row == 1
+    U2 = W.CSR.from_dense(np.array([[2.0, 1.0, 0.0], [0.0, 0.0, 3.0], [0.0, 0.0, 1.0]]))  # row 1 lacks its diagonal
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_scale_factors(B.Csr.from_host(L), B.Csr.from_host(U2))
+    assert e.value.status == -3 and e.value.row == 1
+
+
+# --------------------------------------------------------------------------
+# the smoother, FP64
+# --------------------------------------------------------------------------
+
+SCHED = [(1, 3, 3), (2, 4, 4), (1, 1, 1), (1, 1, 3), (1, 3, 1), (3, 2, 5)]
+
+
+@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("sched", SCHED, ids=lambda s: "o%dL%dU%d" % s)
+@pytest.mark.parametrize("name", list(SMALL))
+def test_smooth_f64(orc, ctx, cases, name, sched, kernel):
+    outer, mL, mU = sched
+    say("smooth f64", name, sched, kernel)
+    c = cases[name]
+    b = W.rhs(c.A.n, 0)
+    x0 = W.rhs(c.A.n, 7) if outer > 1 else np.zeros(c.A.n)
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, x0, outer, mL, mU)
+    x = dev(x0)
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU, kernel=kernel)
+    got = host(x)
+    assert_close(got, ref, F64_TOL, f"{name} {sched} {kernel}")
+    if kernel == "stream":  # same per-row summation order as the oracle
+        np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_smooth_direct(orc, ctx, cases, name):
+    say("smooth direct", name)
+    c = cases[name]
+    b = W.rhs(c.A.n, 0)
+    x0 = W.rhs(c.A.n, 3)
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, x0, 2, 0, 0, direct=True)
+    x = dev(x0)
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 1, 1, direct=True, kernel="stream")
+    got = host(x)
+    assert_close(got, ref, F64_TOL, f"direct {name}")
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("sched", [(1, 3, 3), (2, 4, 4), (1, 1, 1), (1, 2, 1), (1, 1, 2)], ids=lambda s: "o%dL%dU%d" % s)
+@pytest.mark.parametrize("name", list(SMALL))
+def test_smooth_mixed(orc, ctx, cases, name, sched, kernel):
+    """FP32-inner form: within 1e-5 of the FP64 oracle, and equal to the
+    oracle's emulation of the same rounding points up to FP32 summation order."""
+    outer, mL, mU = sched
+    say("smooth mixed", name, sched, kernel)
+    c = cases[name]
+    b = W.rhs(c.A.n, 0)
+    x0 = np.zeros(c.A.n)
+    ref64 = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, x0, outer, mL, mU)
+    ref32 = orc.smooth_mixed(c.A, c.Ls, c.Us, c.dinv, b, x0, outer, mL, mU)
+    x = dev(x0)
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU, mixed=True, kernel=kernel)
+    got = host(x)
+    err = rel_err(got, ref64)
+    say("  mixed rel err vs fp64 oracle", f"{err:.3e}")
+    assert_close(got, ref64, MIXED_TOL, f"mixed {name} {sched}")
+    if kernel == "stream":
+        np.testing.assert_array_equal(got, ref32)
+    else:
+        assert rel_err(got, ref32) <= 1e-6
+
+
+@pytest.mark.parametrize("sched", [(1, 3, 3), (1, 1, 1), (1, 3, 1), (2, 2, 4)], ids=lambda s: "o%dL%dU%d" % s)
+def test_smooth_unscaled(orc, B, ctx, sched):
+    """The unscaled variant z <- y - (U - I) z (Section 6.1): same arithmetic
+    as the oracle, compared relative to the magnitude the iteration reaches."""
+    outer, mL, mU = sched
+    say("unscaled", sched)
+    A = W.vardens7(9)
+    c = Case(orc, B, ctx, A, "iluk", {"k": 1}, scale=False)
+    np.testing.assert_array_equal(host(c.F.Us.val), c.U.val[np.repeat(np.arange(A.n), np.diff(c.U.row_ptr)) != c.U.col])
+    b = W.rhs(A.n, 0)
+    ref = orc.smooth_unscaled(A, c.Ls, c.U, b, np.zeros(A.n), outer, mL, mU)
+    x = dev(np.zeros(A.n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU, kernel="stream")
+    got = host(x)
+    np.testing.assert_array_equal(got, ref)
+
+
+# --------------------------------------------------------------------------
+# triangular solves and level analysis (Section 4)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_trisolve_direct_bitwise(orc, B, ctx, cases, name):
+    say("trisolve_direct", name)
+    c = cases[name]
+    rhs = W.rhs(c.A.n, 5)
+    for T, Td, uplo, unit in ((c.Ls, c.Ld, B.SILU_LOWER, True), (c.Us, c.F.Us, B.SILU_UPPER, True),
+                              (c.U, c.Ud, B.SILU_UPPER, False)):
+        ref = orc.trisolve(T, "L" if uplo == B.SILU_LOWER else "U", unit, rhs)
+        got = host(ctx.trisolve_direct(Td, uplo, B.SILU_UNIT if unit else B.SILU_NONUNIT, dev(rhs)))
+        np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_analyze_levels(orc, B, ctx, cases, name):
+    say("analyze", name)
+    c = cases[name]
+    for T, Td, uplo in ((c.Ls, c.Ld, "L"), (c.Us, c.F.Us, "U")):
+        lev, depth = orc.levels(T, uplo)
+        d, rows = ctx.silu_analyze(Td, B.SILU_LOWER if uplo == "L" else B.SILU_UPPER)
+        assert d == depth
+        np.testing.assert_array_equal(rows, np.bincount(lev, minlength=depth))
+
+
+@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_trisolve_iter(orc, B, ctx, cases, name, kernel):
+    """m Richardson steps against the oracle, and m = depth (nilpotence) against
+    the level-scheduled direct solve."""
+    say("trisolve_iter", name, kernel)
+    c = cases[name]
+    rhs = W.rhs(c.A.n, 6)
+    for T, Td, uplo in ((c.Ls, c.Ld, "L"), (c.Us, c.F.Us, "U")):
+        for m in (1, 2, 5):
+            ref = orc.richardson(T, c.dinv * rhs if uplo == "U" else rhs, m)
+            got = host(ctx.trisolve_iter(Td, dev(rhs), m, dinv=c.F.dinv if uplo == "U" else None, kernel=kernel))
+            assert_close(got, ref, F64_TOL, f"iter {name} {uplo} m={m}")
+        depth, _ = ctx.silu_analyze(Td, B.SILU_LOWER if uplo == "L" else B.SILU_UPPER)
+        exact = host(ctx.trisolve_direct(Td, B.SILU_LOWER if uplo == "L" else B.SILU_UPPER, B.SILU_UNIT, dev(rhs)))
+        got = host(ctx.trisolve_iter(Td, dev(rhs), depth, kernel=kernel))
+        assert_close(got, exact, F64_TOL, f"nilpotence {name} {uplo}")
+        if kernel == "stream":
+            np.testing.assert_array_equal(got, exact)
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+def test_edge_single_row(orc, B, ctx):
+    say("edge n=1")
+    A = W.CSR.from_dense(np.array([[4.0]]))
+    c = Case(orc, B, ctx, A, "ilu0", {}, fp32=True)
+    b = np.array([2.0])
+    for mixed in (False, True):
+        x = dev(np.zeros(1))
+        ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 3, 3, mixed=mixed)
+        assert host(x)[0] == orc.smooth(A, c.Ls, c.Us, c.dinv, b, np.zeros(1), 2, 3, 3)[0] == 0.5
+
+
+def test_edge_diagonal_matrix_empty_factors(orc, B, ctx):
+    """A diagonal A has empty strict factors (nnz = 0): one step is exact."""
+    say("edge diagonal")
+    d = np.linspace(1.0, 3.0, 1000)
+    A = W.CSR.from_dense(np.diag(d))
+    c = Case(orc, B, ctx, A, "ilu0", {}, fp32=True)
+    assert c.Ls.nnz == 0 and c.Us.nnz == 0
+    b = W.rhs(A.n, 0)
+    x = dev(np.zeros(A.n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 1, 3, 3)
+    np.testing.assert_array_equal(host(x), orc.smooth(A, c.Ls, c.Us, c.dinv, b, np.zeros(A.n), 1, 3, 3))
+    x = dev(np.zeros(A.n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 1, 1, 1, direct=True)
+    np.testing.assert_allclose(host(x), b / d, rtol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", ["stream", "vector"])
+def test_edge_long_rows(orc, B, ctx, kernel):
+    """Rows far longer than one LDS chunk of the CSR-stream kernel (several
+    chunks per workgroup) next to empty rows."""
+    say("edge long rows", kernel)
+    n = 3000
+    rng = np.random.default_rng(1)
+    M = np.diag(np.full(n, 4.0 * n))
+    M[n - 1, : n - 1] = -rng.random(n - 1)  # one full lower row
+    M[0, 1:] = -rng.random(n - 1)           # one full upper row
+    M[n // 2, : n // 2] = -rng.random(n // 2)
+    A = W.CSR.from_dense(M)
+    c = Case(orc, B, ctx, A, "ilu0", {}, fp32=True)
+    b = W.rhs(n, 0)
+    ref = orc.smooth(A, c.Ls, c.Us, c.dinv, b, np.zeros(n), 1, 3, 3)
+    x = dev(np.zeros(n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 1, 3, 3, kernel=kernel)
+    assert_close(host(x), ref, F64_TOL, "long rows")
+    if kernel == "stream":
+        np.testing.assert_array_equal(host(x), ref)
+
+
+def test_error_paths(B, ctx, cases):
+    say("error paths")
+    c = cases["poisson17"]
+    n = c.A.n
+    b, x = dev(W.rhs(n, 0)), dev(np.zeros(n))
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(c.Ad, c.F, b, x, 0, 3)
+    assert e.value.status == -1
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(c.Ad, c.F, b, x, 1, 0)
+    assert e.value.status == -1
+    small = __import__("torch").empty(1024, dtype=__import__("torch").uint8, device="cuda")
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(c.Ad, c.F, b, x, 1, 3, ws=small)
+    assert e.value.status == -6
+    F32less = B.Factors(c.F.Ls, c.F.Us, c.F.d, c.F.dinv, None, None, True)
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(c.Ad, F32less, b, x, 1, 3, mixed=True)
+    assert e.value.status == -8
+    bad = b.clone()
+    bad[n // 3] = float("nan")
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(c.Ad, c.F, bad, x, 1, 3, check_finite=True)
+    assert e.value.status == -5
+    # VALIDATE catches an unsorted row
+    Abad = B.Csr(c.Ad.row_ptr.clone(), c.Ad.col_idx.clone(), c.Ad.val.clone())
+    cols = Abad.col_idx.cpu()
+    cols[1], cols[2] = cols[2].item(), cols[1].item()
+    Abad.col_idx.copy_(cols.cuda())
+    with pytest.raises(B.SiluError) as e:
+        ctx.ilu_smooth(Abad, c.F, b, x, 1, 3, validate=True)
+    assert e.value.status == -3
+
+
+def test_timing_stats(B, ctx, cases):
+    say("timing stats")
+    c = cases["aniso11_ilut"]
+    n = c.A.n
+    ctx.stats_reset()
+    ctx.set_timing(True)
+    x = dev(np.zeros(n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(W.rhs(n, 0)), x, 2, 4, 4)
+    ctx.set_timing(False)
+    st = ctx.stats()
+    total = sum(v["launches"] for v in st.values())
+    assert total == 2 * (1 + 3 + 3)
+    assert all(v["ms"] > 0 and v["bytes"] > 0 for v in st.values() if v["launches"])
+    ctx.stats_reset()
