@@ -58,8 +58,10 @@ extern "C" {
 #define SILU_CHECK_FINITE 0x4 /* ilu_smooth: after the step, scan x (synchronous)          */
 #define SILU_VALIDATE 0x8     /* check CSR structure first (synchronous; copies to host)   */
 #define SILU_NO_SCALING 0x10  /* ilu_scale_factors: keep U's values (the unscaled variant) */
-#define SILU_KERNEL_STREAM 0x100 /* force the LDS-staged CSR-stream sweep kernel           */
-#define SILU_KERNEL_VECTOR 0x200 /* force the vector-CSR (lanes-per-row) sweep kernel      */
+#define SILU_KERNEL_STREAM 0x100  /* CSR-stream sweep kernel (the default)                   */
+#define SILU_KERNEL_VECTOR 0x200  /* vector-CSR (lanes-per-row) sweep kernel                */
+#define SILU_KERNEL_BLOCKED 0x400 /* CSR-stream over a row-block partition                  */
+#define SILU_NO_GRAPH 0x800       /* level-scheduled solves: plain launches, no hipGraph     */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -177,7 +179,9 @@ int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const d
 /*
  * Direct solve T out = rhs by level-set scheduling (Section 4): rows are
  * grouped by the level of the elimination DAG and each level is one kernel
- * launch, rows inside a level in parallel.  T: FP64 CSR, lower (uplo =
+ * launch, rows inside a level in parallel.  The launch sequence is captured
+ * once into a hipGraph (cached in the context, keyed by the pointers of T,
+ * rhs and out) and replayed; SILU_NO_GRAPH launches the levels one by one.  T: FP64 CSR, lower (uplo =
  * SILU_LOWER) or upper triangular.  diag = SILU_UNIT: the diagonal is taken
  * as 1 and stored diagonal entries are not read; SILU_NONUNIT: every row must
  * store its diagonal, and the row is divided by it.  rhs, out: FP64 [n],

@@ -29,7 +29,9 @@ _lib = C.CDLL(LIB_PATH)
 
 SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
-SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR = 0x100, 0x200
+SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
+SILU_NO_GRAPH = 0x800
+KERNELS = {None: 0, "blocked": SILU_KERNEL_BLOCKED, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}
 SILU_LOWER, SILU_UPPER = 0, 1
 SILU_UNIT, SILU_NONUNIT = 0, 1
 
@@ -238,12 +240,13 @@ class Context:
     # ---- the smoother ----
     def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
                    m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
-                   validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+                   validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None,
+                   graph: bool = True) -> torch.Tensor:
         """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned)."""
         m_U = m_L if m_U is None else m_U
         flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) |
                  (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
-                 {None: 0, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}[kernel])
+                 (0 if graph else SILU_NO_GRAPH) | KERNELS[kernel])
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws
@@ -254,12 +257,13 @@ class Context:
         return x
 
     def trisolve_direct(self, T: Csr, uplo: int, diag: int, rhs: torch.Tensor, out: torch.Tensor | None = None,
-                        validate: bool = False) -> torch.Tensor:
+                        validate: bool = False, graph: bool = True) -> torch.Tensor:
         _vec(rhs, T.n, "rhs")
         out = torch.empty_like(rhs) if out is None else out
         Tc = T.c()
         self._check(_lib.trisolve_direct(self._h, C.byref(Tc), uplo, diag, C.c_void_p(rhs.data_ptr()),
-                                         C.c_void_p(out.data_ptr()), SILU_VALIDATE if validate else 0),
+                                         C.c_void_p(out.data_ptr()),
+                                         (SILU_VALIDATE if validate else 0) | (0 if graph else SILU_NO_GRAPH)),
                     "trisolve_direct")
         return out
 
@@ -267,7 +271,7 @@ class Context:
                       out: torch.Tensor | None = None, kernel: str | None = None) -> torch.Tensor:
         _vec(rhs, T.n, "rhs")
         out = torch.empty_like(rhs) if out is None else out
-        flags = {None: 0, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}[kernel]
+        flags = KERNELS[kernel]
         ws = self.workspace(T.n, 0)
         Tc = T.c()
         self._check(_lib.trisolve_iter(self._h, C.byref(Tc), C.c_void_p(_ptr(dinv)), C.c_void_p(rhs.data_ptr()),

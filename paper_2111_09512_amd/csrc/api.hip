@@ -33,6 +33,16 @@ struct LevelInfo {
 
 using LevelKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
 
+struct Partition {
+    int32_t *d_blk = nullptr; // [nblk + 1] row starts
+    int nblk = 0;
+};
+using PartKey = std::tuple<const void *, int64_t, int64_t, int>;
+
+// A captured level sequence: one kernel node per level.
+using GraphKey = std::tuple<const void *, const void *, const void *, const void *, const void *, const void *,
+                            const void *, const void *, const void *, int>;
+
 struct Pending {
     int kid;
     hipEvent_t e0, e1;
@@ -48,6 +58,9 @@ struct silu_ctx {
     hipError_t last_hip = hipSuccess;
     int32_t *d_flags = nullptr; // [4] device status words
     std::map<LevelKey, LevelInfo> levels;
+    std::map<PartKey, Partition> parts;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    hipStream_t capture_stream = nullptr; // private, default priority, for graph capture
     bool timing = false;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
@@ -181,9 +194,60 @@ double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift)
     return b;
 }
 
-int sweep(silu_ctx *c, Prec p, const SweepGeom &g, const silu_csr *N, const void *val, const void *xin,
+// Row-block partition for the blocked CSR-stream kernel, made on first use
+// (the row pointers are copied to the host) and cached per matrix.
+int get_partition(silu_ctx *c, const silu_csr *M, int cap, int rmax, Partition **out)
+{
+    PartKey key{M->row_ptr, M->n_rows, M->nnz, cap * 4096 + rmax};
+    auto it = c->parts.find(key);
+    if (it != c->parts.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    const int64_t n = M->n_rows;
+    std::vector<int32_t> rp((size_t)n + 1);
+    HIPCHK(c, hipMemcpyAsync(rp.data(), M->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // (row start, entry start) of every block, then the end sentinel
+    std::vector<int32_t> blk{0, rp[0]};
+    int64_t r = 0;
+    while (r < n) {
+        const int64_t start = r;
+        if (rp[(size_t)r + 1] - rp[(size_t)r] > cap) {
+            r++;
+        } else {
+            int64_t cnt = 0;
+            while (r < n && r - start < rmax && cnt + (rp[(size_t)r + 1] - rp[(size_t)r]) <= cap) {
+                cnt += rp[(size_t)r + 1] - rp[(size_t)r];
+                r++;
+            }
+        }
+        blk.push_back((int32_t)r);
+        blk.push_back(rp[(size_t)r]);
+    }
+    Partition P;
+    P.nblk = (int)blk.size() / 2 - 1;
+    HIPCHK(c, hipMalloc(&P.d_blk, blk.size() * 4));
+    hipError_t e = hipMemcpy(P.d_blk, blk.data(), blk.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(P.d_blk);
+        return hip_fail(c, e);
+    }
+    auto res = c->parts.emplace(key, P);
+    *out = &res.first->second;
+    return SILU_OK;
+}
+
+int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
           const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift)
 {
+    if (g.kind == SweepKernel::BLOCKED) {
+        Partition *P = nullptr;
+        int st = get_partition(c, N, g.cap, RB_RMAX, &P);
+        if (st) return st;
+        g.blk = P->d_blk;
+        g.nblk = P->nblk;
+    }
     SweepArgs a;
     a.n = (int)N->n_rows;
     a.rp = N->row_ptr;
@@ -255,9 +319,62 @@ int get_levels(silu_ctx *c, const silu_csr *T, int uplo, LevelInfo **out)
     return SILU_OK;
 }
 
-int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const double *rhs, double *out,
-               const double *dinv, double *s_out, double *xupd)
+// Enqueue every level of a level-scheduled substitution on stream s.
+hipError_t enqueue_levels(const LevelArgs &a, const LevelInfo *li, int unit, hipStream_t s)
 {
+    for (int l = 0; l < li->depth; l++) {
+        const int start = li->level_ptr[(size_t)l], count = li->level_ptr[(size_t)l + 1] - start;
+        hipError_t e = launch_level(a, unit, start, count, s, nullptr);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const double *rhs, double *out,
+               const double *dinv, double *s_out, double *xupd, bool graph)
+{
+    if (graph && li->depth > 1) {
+        LevelArgs a;
+        a.perm = li->d_perm;
+        a.rp = T->row_ptr;
+        a.col = T->col_idx;
+        a.val = (const double *)T->val;
+        a.rhs = rhs;
+        a.out = out;
+        a.dinv = dinv;
+        a.s_out = s_out;
+        a.xupd = xupd;
+        GraphKey key{li, T->row_ptr, T->col_idx, T->val, rhs, out, dinv, s_out, xupd, unit};
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_levels(a, li, unit, c->capture_stream);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->capture_stream, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(c, e != hipSuccess ? e : e2);
+            }
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(c, e);
+            it = c->graphs.emplace(key, ex).first;
+        }
+        double bytes = 0.0;
+        for (int l = 0; l < li->depth; l++) {
+            const int count = li->level_ptr[(size_t)l + 1] - li->level_ptr[(size_t)l];
+            bytes += count * (4.0 + 8.0 + 8.0 + 8.0 + 8.0) + 12.0 * (double)li->level_nnz[(size_t)l];
+            if (s_out) bytes += count * 16.0;
+            if (xupd) bytes += count * 16.0;
+        }
+        hipGraphExec_t ex = it->second;
+        return timed_launch(c, bytes, [&](const char **nm) {
+            *nm = "level_graph";
+            return hipGraphLaunch(ex, c->stream);
+        });
+    }
     LevelArgs a;
     a.perm = li->d_perm;
     a.rp = T->row_ptr;
@@ -321,6 +438,9 @@ int silu_destroy(silu_ctx *c)
     if (!c) return SILU_ERR_ARG;
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->levels) (void)hipFree(kv.second.d_perm);
+    for (auto &kv : c->parts) (void)hipFree(kv.second.d_blk);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
         (void)hipEventDestroy(p.e0);
         (void)hipEventDestroy(p.e1);
@@ -451,10 +571,11 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             if ((st = get_levels(c, &F->Ls, SILU_LOWER, &lL))) return st;
             if ((st = get_levels(c, &F->Us, SILU_UPPER, &lU))) return st;
             if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, r, nullptr, nullptr, nullptr))) return st;
+            const bool graph = !(flags & SILU_NO_GRAPH);
             if ((st = run_levels(c, &F->Ls, lL, 1, (const double *)r, (double *)tmp[0], F->dinv, (double *)s,
-                                 nullptr)))
+                                 nullptr, graph)))
                 return st;
-            if ((st = run_levels(c, &F->Us, lU, 1, (const double *)s, (double *)tmp[1], nullptr, nullptr, x)))
+            if ((st = run_levels(c, &F->Us, lU, 1, (const double *)s, (double *)tmp[1], nullptr, nullptr, x, graph)))
                 return st;
             continue;
         }
@@ -521,7 +642,8 @@ int trisolve_direct(silu_ctx *c, const silu_csr *T, int uplo, int diag, const do
     }
     LevelInfo *li = nullptr;
     if ((st = get_levels(c, T, uplo, &li))) return st;
-    return run_levels(c, T, li, diag == SILU_UNIT ? 1 : 0, rhs, out, nullptr, nullptr, nullptr);
+    return run_levels(c, T, li, diag == SILU_UNIT ? 1 : 0, rhs, out, nullptr, nullptr, nullptr,
+                      !(flags & SILU_NO_GRAPH));
 }
 
 int trisolve_iter(silu_ctx *c, const silu_csr *T, const double *dinv, const double *rhs, double *out, int m,

@@ -26,7 +26,12 @@ enum class Prec : int {
     MIX_L1 = 4   // first mixed L sweep: gathers y_1 = r from the FP64 residual, rounding each value to FP32
 };
 
-enum class SweepKernel : int { STREAM = 0, VECTOR = 1 };
+enum class SweepKernel : int { STREAM = 0, VECTOR = 1, BLOCKED = 2 };
+
+// Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
+// and RB_CAP entries per workgroup (a longer row gets a workgroup alone).
+constexpr int RB_CAP = 2048;
+constexpr int RB_RMAX = 1024;
 
 struct SweepArgs {
     int n;
@@ -45,8 +50,11 @@ struct SweepArgs {
 // Kernel geometry for a sweep, picked from the mean row length.
 struct SweepGeom {
     SweepKernel kind;
-    int rows_per_block; // STREAM: rows per workgroup
-    int lanes;          // VECTOR: lanes per row
+    int rows_per_block;           // STREAM: rows per workgroup
+    int lanes;                    // VECTOR: lanes per row
+    int cap = RB_CAP;             // BLOCKED: entries per row block
+    const int32_t *blk = nullptr; // BLOCKED: device (row start, entry start) pairs [nblk + 1]
+    int nblk = 0;
 };
 
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);

@@ -108,10 +108,27 @@ __global__ void __launch_bounds__(256) k_scale_copy(int n, const double *__restr
     if (i < n) out[i] = dinv ? dinv[i] * rhs[i] : rhs[i];
 }
 
-__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Streaming copy: each lane moves four 16-byte vectors per iteration, all four
+// loads issued before the stores; non-temporal hints keep the stream out of
+// the caches.
+__global__ void __launch_bounds__(256) k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n16)
 {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    const size_t bd = blockDim.x;
+    const size_t stride = (size_t)gridDim.x * bd * 4;
+    size_t i = (size_t)blockIdx.x * bd * 4 + threadIdx.x;
+    for (; i + 3 * bd < n16; i += stride) {
+        const u32x4 a = __builtin_nontemporal_load(&src[i]);
+        const u32x4 b = __builtin_nontemporal_load(&src[i + bd]);
+        const u32x4 c = __builtin_nontemporal_load(&src[i + 2 * bd]);
+        const u32x4 d = __builtin_nontemporal_load(&src[i + 3 * bd]);
+        __builtin_nontemporal_store(a, &dst[i]);
+        __builtin_nontemporal_store(b, &dst[i + bd]);
+        __builtin_nontemporal_store(c, &dst[i + 2 * bd]);
+        __builtin_nontemporal_store(d, &dst[i + 3 * bd]);
+    }
+    for (; i < n16; i += bd) dst[i] = src[i];
 }
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
@@ -181,8 +198,8 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
-    const int grid = (int)std::min<size_t>((n16 + 255) / 256, 256 * 64);
-    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, n16);
+    const int grid = (int)std::min<size_t>((n16 + 1023) / 1024, 256 * 16);
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError();
 }
 

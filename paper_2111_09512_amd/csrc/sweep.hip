@@ -10,16 +10,23 @@
 // matrix exactly once.  The work is bandwidth-bound (about 0.1 flop per byte),
 // so there is no MFMA: the kernels are shaped for coalesced HBM streaming.
 //
-// Two shapes:
-//  * CSR-stream (short rows, the 3-6 entries of ILU(0)/ILU(1) factors): a
-//    workgroup owns RPB consecutive rows, streams their contiguous val/col
-//    range with unit-stride loads, writes the products val*xin[col] to LDS,
-//    then one lane per row adds its products in ascending column order.
-//  * vector-CSR (long rows): K lanes per row, strided over the row, partial
-//    sums combined with cross-lane shuffles.
+// Shapes:
+//  * CSR-stream (default): a workgroup owns RPB consecutive rows, streams
+//    their contiguous val/col range with unit-stride, non-temporal loads
+//    (the factor is read once per sweep and must not evict the gathered
+//    iterate from L2), writes the products val*xin[col] to LDS, then one lane
+//    per row adds its products in ascending column order -- the oracle's
+//    order, so FP64 results are bit-identical to it.
+//  * CSR-stream over a row-block partition (entries per workgroup capped,
+//    computed once per matrix on the host).
+//  * vector-CSR: K lanes per row, partial sums combined with cross-lane
+//    shuffles (different summation order; within rounding of the oracle).
 // Workgroups are remapped so that each XCD (the hardware deals workgroups
 // round-robin over the 8 XCDs) walks one contiguous slab of rows, keeping the
 // gathered iterate window resident in that XCD's L2.
+#include <cstdio>
+#include <cstdlib>
+
 #include "internal.h"
 
 #pragma clang fp contract(off)
@@ -134,7 +141,8 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
     for (int c0 = e0; c0 < e1; c0 += CAP) {
         const int c1 = min(c0 + CAP, e1);
 #pragma unroll 4
-        for (int e = c0 + tid; e < c1; e += BLOCK) prod[e - c0] = (AT)val[e] * (AT)xin[col[e]];
+        for (int e = c0 + tid; e < c1; e += BLOCK)
+            prod[e - c0] = (AT)__builtin_nontemporal_load(&val[e]) * (AT)xin[__builtin_nontemporal_load(&col[e])];
         __syncthreads();
         const int lo = max(mylo, c0), hi = min(myhi, c1);
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
@@ -145,6 +153,83 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
         const AT t = (AT)((const RT *)a.rhs)[row] - sum;
         epilogue<T>(a, row, t);
     }
+}
+
+// ---------------------------------------------------------------------------
+// CSR-stream over a row-block partition: workgroup b owns rows
+// [blk[b].row, blk[b+1].row) whose entries are [blk[b].ent, blk[b+1].ent): at
+// most RMAX rows and CAP entries (a single longer row gets a workgroup alone
+// and is streamed in chunks).  The partition carries the entry offsets, so
+// every lane issues its CAP/BLOCK val and col loads at once, with no wait on
+// the row pointers, and with non-temporal hints: the factor is streamed once
+// per sweep and must not evict the gathered iterate window from L2.  The
+// products go to LDS and each row is then summed by one lane in ascending
+// column order.
+// ---------------------------------------------------------------------------
+template <class T, int BLOCK, int CAP, int RMAX>
+__global__ void __launch_bounds__(BLOCK) k_sweep_rb(SweepArgs a, const int2 *__restrict__ blk)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    constexpr int U = CAP / BLOCK;
+    static_assert(CAP % BLOCK == 0 && RMAX % BLOCK == 0, "geometry");
+    __shared__ AT prod[CAP];
+    __shared__ int32_t srp[RMAX + 1];
+
+    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int2 lo = blk[b], hi = blk[b + 1];
+    const int r0 = lo.x, nr = hi.x - lo.x, e0 = lo.y, e1 = hi.y;
+    const int tid = (int)threadIdx.x;
+
+    const VT *__restrict__ val = (const VT *)a.val;
+    const int32_t *__restrict__ col = a.col;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    const RT *__restrict__ rhs = (const RT *)a.rhs;
+
+    if (e1 - e0 <= CAP) {
+        const int cn = e1 - e0;
+        VT v[U];
+        int32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = u * BLOCK + tid;
+            if (k < cn) {
+                v[u] = __builtin_nontemporal_load(&val[e0 + k]);
+                c[u] = __builtin_nontemporal_load(&col[e0 + k]);
+            }
+        }
+        for (int t = tid; t <= nr; t += BLOCK) srp[t] = a.rp[r0 + t];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = u * BLOCK + tid;
+            if (k < cn) prod[k] = (AT)v[u] * (AT)xin[c[u]];
+        }
+        __syncthreads();
+        for (int t = tid; t < nr; t += BLOCK) {
+            const int row = r0 + t;
+            AT sum = (AT)0;
+            if (a.dshift) sum = (AT)((a.dshift[row] - 1.0) * (double)xin[row]);
+            const int klo = srp[t] - e0, khi = srp[t + 1] - e0;
+            for (int k = klo; k < khi; ++k) sum = sum + prod[k];
+            epilogue<T>(a, row, (AT)rhs[row] - sum);
+        }
+        return;
+    }
+    // one long row, streamed through LDS in chunks of CAP entries
+    const int row = r0;
+    AT sum = (AT)0;
+    if (a.dshift) sum = (AT)((a.dshift[row] - 1.0) * (double)xin[row]);
+    for (int c0 = e0; c0 < e1; c0 += CAP) {
+        const int cn = min(CAP, e1 - c0);
+        for (int k = tid; k < cn; k += BLOCK) prod[k] = (AT)val[c0 + k] * (AT)xin[col[c0 + k]];
+        __syncthreads();
+        if (tid == 0)
+            for (int k = 0; k < cn; ++k) sum = sum + prod[k];
+        __syncthreads();
+    }
+    if (tid == 0) epilogue<T>(a, row, (AT)rhs[row] - sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +286,17 @@ template <class T>
 hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
+    if (g.kind == SweepKernel::BLOCKED) {
+        if (g.nblk <= 0 || !g.blk) return hipErrorInvalidValue;
+        const int2 *blk = (const int2 *)g.blk;
+        switch (g.cap) {
+        case 1024: hipLaunchKernelGGL((k_sweep_rb<T, 256, 1024, RB_RMAX>), dim3(g.nblk), dim3(256), 0, s, a, blk); break;
+        case 2048: hipLaunchKernelGGL((k_sweep_rb<T, 256, 2048, RB_RMAX>), dim3(g.nblk), dim3(256), 0, s, a, blk); break;
+        case 4096: hipLaunchKernelGGL((k_sweep_rb<T, 256, 4096, RB_RMAX>), dim3(g.nblk), dim3(256), 0, s, a, blk); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (g.kind == SweepKernel::STREAM) {
         switch (g.rows_per_block) {
         case 256: return go_stream<T, 256, 256, 1024>(a, s);
@@ -221,30 +317,61 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 
 const char *kname(Prec p, SweepKernel k)
 {
-    static const char *names[2][5] = {
+    static const char *names[3][5] = {
         {"sweep_stream_f64", "sweep_stream_mixres", "sweep_stream_mixL", "sweep_stream_mixU", "sweep_stream_mixL1"},
-        {"sweep_vector_f64", "sweep_vector_mixres", "sweep_vector_mixL", "sweep_vector_mixU", "sweep_vector_mixL1"}};
+        {"sweep_vector_f64", "sweep_vector_mixres", "sweep_vector_mixL", "sweep_vector_mixU", "sweep_vector_mixL1"},
+        {"sweep_rb_f64", "sweep_rb_mixres", "sweep_rb_mixL", "sweep_rb_mixU", "sweep_rb_mixL1"}};
     return names[(int)k][(int)p];
 }
 
 } // namespace
 
+// SILU_SWEEP_GEOM (tuning override, read per call): "blocked:CAP",
+// "stream:RPB" or "vector:LANES".
+static bool geom_override(SweepGeom &g)
+{
+    const char *e = getenv("SILU_SWEEP_GEOM");
+    if (!e || !*e) return false;
+    int v = 0;
+    if (sscanf(e, "blocked:%d", &v) == 1 && (v == 1024 || v == 2048 || v == 4096)) {
+        g.kind = SweepKernel::BLOCKED;
+        g.cap = v;
+        return true;
+    }
+    if (sscanf(e, "stream:%d", &v) == 1 && (v == 64 || v == 128 || v == 256)) {
+        g.kind = SweepKernel::STREAM;
+        g.rows_per_block = v;
+        return true;
+    }
+    if (sscanf(e, "vector:%d", &v) == 1 && v >= 4 && v <= 64 && (v & (v - 1)) == 0) {
+        g.kind = SweepKernel::VECTOR;
+        g.lanes = v;
+        return true;
+    }
+    return false;
+}
+
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
 {
     const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
     SweepGeom g;
-    bool stream = mean <= 12.0;
-    if (flags & 0x100) stream = true;  // SILU_KERNEL_STREAM
-    if (flags & 0x200) stream = false; // SILU_KERNEL_VECTOR
-    if (stream) {
-        g.kind = SweepKernel::STREAM;
-        g.rows_per_block = mean <= 4.0 ? 256 : (mean <= 8.0 ? 128 : 64);
-        g.lanes = 1;
-    } else {
-        g.kind = SweepKernel::VECTOR;
-        g.rows_per_block = 0;
-        g.lanes = mean <= 6.0 ? 4 : (mean <= 12.0 ? 8 : (mean <= 24.0 ? 16 : (mean <= 48.0 ? 32 : 64)));
+    g.rows_per_block = 0;
+    g.lanes = 1;
+    g.cap = RB_CAP;
+    if (geom_override(g)) return g;
+    if (flags & 0x400) { // SILU_KERNEL_BLOCKED
+        g.kind = SweepKernel::BLOCKED;
+        return g; // the caller attaches the row-block partition
     }
+    if (flags & 0x200) { // SILU_KERNEL_VECTOR
+        g.kind = SweepKernel::VECTOR;
+        g.lanes = mean <= 6.0 ? 4 : (mean <= 12.0 ? 8 : (mean <= 24.0 ? 16 : (mean <= 48.0 ? 32 : 64)));
+        return g;
+    }
+    // default (and SILU_KERNEL_STREAM): CSR-stream; short rows fill a
+    // workgroup with 256 of them, long rows take 64 so one LDS chunk holds them
+    g.kind = SweepKernel::STREAM;
+    g.rows_per_block = mean <= 8.0 ? 256 : (mean <= 16.0 ? 128 : 64);
     return g;
 }
 

@@ -199,7 +199,7 @@ def aniso27(N: int, ratio: float = 1.0e3) -> CSR:
     return A
 
 
-def permuted_longrange7(N: int, seed: int = 1, frac: float = 0.1, wmax: float = 1.0e-2) -> CSR:
+def permuted_longrange7(N: int, seed: int = 1, frac: float = 0.1, wmax: float = 1.0e-2, coo: bool = False) -> CSR:
     """7-point 256^3-style operator with random long-range couplings, symmetrically permuted.
 
     Start from the constant-coefficient 7-point grid (diagonal 6, face weight 1).
@@ -211,7 +211,8 @@ def permuted_longrange7(N: int, seed: int = 1, frac: float = 0.1, wmax: float = 
     (a,b) is replaced by the coupling (a,c) with entry -w on both sides.  The
     diagonal stays 6.  Finally the matrix is permuted symmetrically, row r of
     the result being row pi[r] of the unpermuted matrix (with columns mapped
-    the same way).
+    the same way).  ``coo=True`` assembles the same matrix through a plain
+    COO sort (slow; used to check the fast construction).
     """
     n = N**3
     rng = np.random.default_rng(seed)
@@ -232,7 +233,8 @@ def permuted_longrange7(N: int, seed: int = 1, frac: float = 0.1, wmax: float = 
     keep = np.ones(E, dtype=bool)
     keep[chosen] = False
     ga, gb = ea[keep], eb[keep]
-    del ea, eb, keep, chosen
+    chosen_idx = chosen
+    del ea, eb, keep
 
     def is_grid_nb(a, c):
         d = np.abs(a - c)
@@ -263,15 +265,73 @@ def permuted_longrange7(N: int, seed: int = 1, frac: float = 0.1, wmax: float = 
     else:  # pragma: no cover - astronomically unlikely
         raise RuntimeError("could not draw valid long-range partners")
     w = rng.uniform(0.0, wmax, size=k)
-
-    # COO of the unpermuted symmetric matrix
-    rows = np.concatenate([idx, ga, gb, ca, c])
-    cols = np.concatenate([idx, gb, ga, c, ca])
-    vals = np.concatenate([np.full(n, 6.0), -np.ones(ga.size), -np.ones(gb.size), -w, -w])
-    del ga, gb, ca, c, w, x, y, z
+    if coo:
+        # COO of the unpermuted symmetric matrix (plain reference construction)
+        rows = np.concatenate([idx, ga, gb, ca, c])
+        cols = np.concatenate([idx, gb, ga, c, ca])
+        vals = np.concatenate([np.full(n, 6.0), -np.ones(ga.size), -np.ones(gb.size), -w, -w])
+        inv = np.empty(n, dtype=np.int64)
+        inv[pi] = np.arange(n, dtype=np.int64)
+        A = _coo_to_csr(n, inv[rows], inv[cols], vals)
+        A.meta = {"kind": "permuted_longrange7", "N": N, "seed": seed, "frac": frac}
+        return A
+    del ga, gb
+    # Fast construction: a padded table of each unpermuted row (grid slots
+    # -z,-y,-x,diag,+x,+y,+z, then long-range partners), columns mapped through
+    # the inverse permutation, rows permuted, each short row sorted.
+    nxe = N * N * (N - 1)  # edges per direction
+    present = np.ones((3, n), dtype=bool)  # present[d][a]: edge (a, a+step_d) kept
+    present[0, x == N - 1] = False
+    present[1, y == N - 1] = False
+    present[2, z == N - 1] = False
+    # chosen edge indices were drawn over [x-edges | y-edges | z-edges]
+    d_of = (chosen_idx // nxe).astype(np.int64)
+    present[d_of, ca] = False
+    steps = (1, N, N * N)
+    nodes = np.concatenate([ca, c])
+    deg = np.bincount(nodes, minlength=n)
+    maxdeg = int(deg.max()) if deg.size else 0
+    K = 7 + maxdeg
+    tcol = np.full((n, K), -1, dtype=np.int64)
+    tval = np.zeros((n, K))
+    for slot, (dd, sign) in enumerate([(2, -1), (1, -1), (0, -1)]):
+        st = steps[dd]
+        ok = np.zeros(n, dtype=bool)
+        ok[st:] = present[dd, :-st] if st < n else False
+        tcol[:, slot] = np.where(ok, idx - st, -1)
+        tval[:, slot] = np.where(ok, -1.0, 0.0)
+    tcol[:, 3] = idx
+    tval[:, 3] = 6.0
+    for slot, dd in zip((4, 5, 6), (0, 1, 2)):
+        st = steps[dd]
+        ok = present[dd]
+        tcol[:, slot] = np.where(ok, idx + st, -1)
+        tval[:, slot] = np.where(ok, -1.0, 0.0)
+    del present, x, y, z
+    partners = np.concatenate([c, ca])
+    ww = np.concatenate([w, w])
+    order = np.argsort(nodes, kind="stable")
+    nodes_s = nodes[order]
+    first = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(deg, out=first[1:])
+    rank = np.arange(nodes_s.size) - first[nodes_s]
+    tcol[nodes_s, 7 + rank] = partners[order]
+    tval[nodes_s, 7 + rank] = -ww[order]
+    del nodes, partners, ww, order, nodes_s, rank
     inv = np.empty(n, dtype=np.int64)
     inv[pi] = np.arange(n, dtype=np.int64)
-    A = _coo_to_csr(n, inv[rows], inv[cols], vals)
+    tcol = tcol[pi]
+    tval = tval[pi]
+    newc = np.where(tcol >= 0, inv[np.maximum(tcol, 0)], n)
+    del tcol
+    srt = np.argsort(newc, axis=1, kind="stable")
+    newc = np.take_along_axis(newc, srt, axis=1)
+    tval = np.take_along_axis(tval, srt, axis=1)
+    del srt
+    valid = newc < n
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(valid.sum(1), out=rp[1:])
+    A = CSR(n, rp.astype(np.int32), newc[valid].astype(np.int32), tval[valid])
     A.meta = {"kind": "permuted_longrange7", "N": N, "seed": seed, "frac": frac}
     return A
 

@@ -1,0 +1,123 @@
+"""GPU parity at the full sizes of the four synthetic workloads, in the launch
+configuration the benchmark times (default kernel selection).
+
+The oracle factors each operator itself (FP64, plain C) and those factors are
+the device inputs, so every expected value comes from the oracle alone.  The
+FP64 path is required to match the oracle to 1e-12 (and, with the default
+CSR-stream kernel, bit for bit); the mixed path to 1e-5 of the FP64 oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2111_09512_amd import workloads as W
+from tests.gpu_common import F64_TOL, MIXED_TOL, Case, assert_close, dev, host, need_gpu, rel_err, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+@pytest.fixture(scope="module")
+def B():
+    need_gpu()
+    from paper_2111_09512_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context()
+
+
+def build(orc, B, ctx, name):
+    t = time.time()
+    wl = W.workload(name)
+    c = Case(orc, B, ctx, wl.A, wl.factor, wl.factor_params, fp32=True)
+    say(f"{name}: n={wl.A.n} nnz(A)={wl.A.nnz} nnz(Ls)={c.Ls.nnz} nnz(Us)={c.Us.nnz} set-up {time.time() - t:.1f}s")
+    return wl, c
+
+
+@pytest.mark.timeout(300)
+def test_full_poisson32(orc, B, ctx):
+    wl, c = build(orc, B, ctx, "poisson32")
+    b = wl.b
+    for direct in (False, True):
+        ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(c.A.n), wl.outer, wl.m_L, wl.m_U, direct=direct)
+        x = dev(np.zeros(c.A.n))
+        ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, direct=direct)
+        np.testing.assert_array_equal(host(x), ref)
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(c.A.n), wl.outer, wl.m_L, wl.m_U)
+    x = dev(np.zeros(c.A.n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, mixed=True)
+    assert_close(host(x), ref, MIXED_TOL, "poisson32 mixed")
+
+
+@pytest.mark.timeout(300)
+def test_full_vardens128_inner_sweep(orc, B, ctx):
+    """ILU(1) on the variable-density cut-cell operator, inner iterations
+    1..8, scaled vs unscaled, iterative vs direct."""
+    wl, c = build(orc, B, ctx, "vardens128")
+    n = c.A.n
+    b = wl.b
+    bd = dev(b)
+    x = dev(np.zeros(n))
+    for m in range(1, 9):
+        ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), 1, m, m)
+        x.zero_()
+        ctx.ilu_smooth(c.Ad, c.F, bd, x, 1, m, m)
+        got = host(x)
+        np.testing.assert_array_equal(got, ref)
+        say(f"  m={m}: bit-identical to the oracle")
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), 1, 0, 0, direct=True)
+    x.zero_()
+    ctx.ilu_smooth(c.Ad, c.F, bd, x, 1, 1, 1, direct=True)
+    np.testing.assert_array_equal(host(x), ref)
+    # the unscaled variant on the same ILU(1) factors
+    Fu = ctx.ilu_scale_factors(c.Ld, c.Ud, scale=False)
+    ref = orc.smooth_unscaled(c.A, c.Ls, c.U, b, np.zeros(n), 1, 3, 3)
+    x.zero_()
+    ctx.ilu_smooth(c.Ad, Fu, bd, x, 1, 3, 3)
+    np.testing.assert_array_equal(host(x), ref)
+
+
+@pytest.mark.timeout(400)
+def test_full_aniso200(orc, B, ctx):
+    """The headline workload: n = 8M, ILUT(1e-3, 20), 2 outer x 4 inner."""
+    wl, c = build(orc, B, ctx, "aniso200")
+    n = c.A.n
+    b = wl.b
+    t = time.time()
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), wl.outer, wl.m_L, wl.m_U)
+    say(f"  oracle FP64 smoother {time.time() - t:.1f}s")
+    x = dev(np.zeros(n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U)
+    np.testing.assert_array_equal(host(x), ref)
+    x.zero_()
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, mixed=True)
+    got = host(x)
+    err = rel_err(got, ref)
+    say(f"  mixed vs FP64 oracle: {err:.3e}")
+    assert_close(got, ref, MIXED_TOL, "aniso200 mixed")
+
+
+@pytest.mark.timeout(400)
+def test_full_perm256_mixed(orc, B, ctx):
+    """n = 16.8M permuted operator with long-range couplings: FP32 factor values,
+    FP64 x/r, 3 inner iterations."""
+    wl, c = build(orc, B, ctx, "perm256")
+    n = c.A.n
+    b = wl.b
+    t = time.time()
+    ref64 = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), wl.outer, wl.m_L, wl.m_U)
+    ref32 = orc.smooth_mixed(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), wl.outer, wl.m_L, wl.m_U)
+    say(f"  oracle smoothers {time.time() - t:.1f}s")
+    x = dev(np.zeros(n))
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, mixed=True)
+    got = host(x)
+    say(f"  mixed vs FP64 oracle: {rel_err(got, ref64):.3e}")
+    assert_close(got, ref64, MIXED_TOL, "perm256 mixed")
+    np.testing.assert_array_equal(got, ref32)
+    x.zero_()
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U)
+    np.testing.assert_array_equal(host(x), ref64)

@@ -28,6 +28,8 @@ def ctx(B):
     return B.Context()
 
 
+KERNELS = [None, "blocked", "stream", "vector"]  # None: the default (pipelined CSR-stream)
+
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
     "vardens13_ilu1": (lambda: W.vardens7(13), "iluk", {"k": 1}),
@@ -84,7 +86,7 @@ def test_scale_factors_errors(B, ctx):
 SCHED = [(1, 3, 3), (2, 4, 4), (1, 1, 1), (1, 1, 3), (1, 3, 1), (3, 2, 5)]
 
 
-@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("sched", SCHED, ids=lambda s: "o%dL%dU%d" % s)
 @pytest.mark.parametrize("name", list(SMALL))
 def test_smooth_f64(orc, ctx, cases, name, sched, kernel):
@@ -98,7 +100,7 @@ def test_smooth_f64(orc, ctx, cases, name, sched, kernel):
     ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU, kernel=kernel)
     got = host(x)
     assert_close(got, ref, F64_TOL, f"{name} {sched} {kernel}")
-    if kernel == "stream":  # same per-row summation order as the oracle
+    if kernel != "vector":  # same per-row summation order as the oracle
         np.testing.assert_array_equal(got, ref)
 
 
@@ -110,13 +112,13 @@ def test_smooth_direct(orc, ctx, cases, name):
     x0 = W.rhs(c.A.n, 3)
     ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, x0, 2, 0, 0, direct=True)
     x = dev(x0)
-    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 1, 1, direct=True, kernel="stream")
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 1, 1, direct=True)
     got = host(x)
     assert_close(got, ref, F64_TOL, f"direct {name}")
     np.testing.assert_array_equal(got, ref)
 
 
-@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("sched", [(1, 3, 3), (2, 4, 4), (1, 1, 1), (1, 2, 1), (1, 1, 2)], ids=lambda s: "o%dL%dU%d" % s)
 @pytest.mark.parametrize("name", list(SMALL))
 def test_smooth_mixed(orc, ctx, cases, name, sched, kernel):
@@ -135,7 +137,7 @@ def test_smooth_mixed(orc, ctx, cases, name, sched, kernel):
     err = rel_err(got, ref64)
     say("  mixed rel err vs fp64 oracle", f"{err:.3e}")
     assert_close(got, ref64, MIXED_TOL, f"mixed {name} {sched}")
-    if kernel == "stream":
+    if kernel != "vector":
         np.testing.assert_array_equal(got, ref32)
     else:
         assert rel_err(got, ref32) <= 1e-6
@@ -153,7 +155,7 @@ def test_smooth_unscaled(orc, B, ctx, sched):
     b = W.rhs(A.n, 0)
     ref = orc.smooth_unscaled(A, c.Ls, c.U, b, np.zeros(A.n), outer, mL, mU)
     x = dev(np.zeros(A.n))
-    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU, kernel="stream")
+    ctx.ilu_smooth(c.Ad, c.F, dev(b), x, outer, mL, mU)
     got = host(x)
     np.testing.assert_array_equal(got, ref)
 
@@ -185,7 +187,7 @@ def test_analyze_levels(orc, B, ctx, cases, name):
         np.testing.assert_array_equal(rows, np.bincount(lev, minlength=depth))
 
 
-@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name", list(SMALL))
 def test_trisolve_iter(orc, B, ctx, cases, name, kernel):
     """m Richardson steps against the oracle, and m = depth (nilpotence) against
@@ -202,7 +204,7 @@ def test_trisolve_iter(orc, B, ctx, cases, name, kernel):
         exact = host(ctx.trisolve_direct(Td, B.SILU_LOWER if uplo == "L" else B.SILU_UPPER, B.SILU_UNIT, dev(rhs)))
         got = host(ctx.trisolve_iter(Td, dev(rhs), depth, kernel=kernel))
         assert_close(got, exact, F64_TOL, f"nilpotence {name} {uplo}")
-        if kernel == "stream":
+        if kernel != "vector":
             np.testing.assert_array_equal(got, exact)
 
 
@@ -237,7 +239,7 @@ def test_edge_diagonal_matrix_empty_factors(orc, B, ctx):
     np.testing.assert_allclose(host(x), b / d, rtol=1e-15)
 
 
-@pytest.mark.parametrize("kernel", ["stream", "vector"])
+@pytest.mark.parametrize("kernel", KERNELS)
 def test_edge_long_rows(orc, B, ctx, kernel):
     """Rows far longer than one LDS chunk of the CSR-stream kernel (several
     chunks per workgroup) next to empty rows."""
@@ -255,7 +257,7 @@ def test_edge_long_rows(orc, B, ctx, kernel):
     x = dev(np.zeros(n))
     ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 1, 3, 3, kernel=kernel)
     assert_close(host(x), ref, F64_TOL, "long rows")
-    if kernel == "stream":
+    if kernel != "vector":
         np.testing.assert_array_equal(host(x), ref)
 
 
@@ -307,3 +309,69 @@ def test_timing_stats(B, ctx, cases):
     assert total == 2 * (1 + 3 + 3)
     assert all(v["ms"] > 0 and v["bytes"] > 0 for v in st.values() if v["launches"])
     ctx.stats_reset()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_many_row_blocks_per_workgroup(orc, B, ctx, kernel):
+    """More row blocks than resident workgroups, so each workgroup of the
+    pipelined kernel walks a slab of blocks, with rows longer than one LDS
+    chunk scattered among short ones (strictly lower T, n = 400000)."""
+    say("many row blocks", kernel)
+    n = 400_000
+    rng = np.random.default_rng(11)
+    i = np.arange(n)
+    step = 1 + i % 7  # row i reads columns i-1-k*step, k < len_i
+    lens = rng.integers(0, 12, n)
+    for r in (5000, 123457, 300001, n - 1):  # rows longer than one LDS chunk
+        lens[r] = 2500 + r % 700
+        step[r] = 1
+    lens = np.where(i == 0, 0, np.minimum(lens, (i - 1) // step + 1))
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    row = np.repeat(i, lens)
+    k = np.arange(rp[-1]) - rp[row]
+    col = (row - 1 - (lens[row] - 1 - k) * step[row]).astype(np.int32)
+    assert col.min() >= 0 and np.all(col < row)
+    T = W.CSR(n, rp.astype(np.int32), col, -rng.random(rp[-1]) / 20.0)
+    Td = B.Csr.from_host(T)
+    rhs = W.rhs(n, 3)
+    for m in (1, 3):
+        ref = orc.richardson(T, rhs, m)
+        got = host(ctx.trisolve_iter(Td, dev(rhs), m, kernel=kernel))
+        assert_close(got, ref, F64_TOL, f"many blocks m={m}")
+        if kernel != "vector":
+            np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", ["vardens13_ilu1", "aniso11_ilut"])
+def test_level_graph_replays(orc, B, ctx, cases, name):
+    """The level sequence is captured once into a hipGraph and replayed: every
+    replay, with eager work and synchronizations in between, equals the
+    oracle's substitution and the plain-launch path bit for bit."""
+    import torch
+
+    say("graph replays", name)
+    c = cases[name]
+    n = c.A.n
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    for rep in range(4):
+        rhs = W.rhs(n, 20 + rep)
+        ref = orc.trisolve(c.Us, "U", True, rhs)
+        rd = dev(rhs)
+        ctx.trisolve_direct(c.F.Us, B.SILU_UPPER, B.SILU_UNIT, rd, out=out)
+        np.testing.assert_array_equal(host(out), ref)
+        junk = torch.randn(4096, device="cuda").cumsum(0)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk).all()
+        plain = ctx.trisolve_direct(c.F.Us, B.SILU_UPPER, B.SILU_UNIT, rd, graph=False)
+        np.testing.assert_array_equal(host(plain), ref)
+    b = W.rhs(n, 0)
+    x0 = W.rhs(n, 3)
+    ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, x0, 1, 0, 0, direct=True)
+    bd = dev(b)
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        x.copy_(dev(x0))
+        ctx.ilu_smooth(c.Ad, c.F, bd, x, 1, 1, 1, direct=True)
+        np.testing.assert_array_equal(host(x), ref)
+        torch.cuda.synchronize()

@@ -68,3 +68,14 @@ def test_rhs_seeded():
     assert np.array_equal(W.rhs(10, 0), W.rhs(10, 0))
     b = W.rhs(1000, 0)
     assert -1 <= b.min() and b.max() <= 1
+
+
+@pytest.mark.parametrize("N", [4, 7, 11])
+def test_permuted_fast_construction_equals_coo(N):
+    """The padded-table construction of the permuted operator equals a plain
+    COO assembly of the same draws, array for array."""
+    A = W.permuted_longrange7(N, seed=1)
+    B = W.permuted_longrange7(N, seed=1, coo=True)
+    assert np.array_equal(A.row_ptr, B.row_ptr)
+    assert np.array_equal(A.col, B.col)
+    assert np.array_equal(A.val, B.val)
