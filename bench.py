@@ -11,7 +11,8 @@ and reported in the same JSON line: the level-scheduled direct form (the same
 smoother with both triangular solves done by level-set substitution), the
 FP32-inner mixed form, a streaming-copy bandwidth calibration, the roofline of
 the dominant kernel from per-launch HIP events, and the CPU oracle timed on a
-bounded sample of the same operator.
+bounded sample of the same operator, and the serving stream (1,280 requests
+on 64 resident matrices, continuous batching vs one at a time).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -57,29 +58,6 @@ def time_steps(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def app_bytes(n, nnzA, nnzL, nnzU, outer, mL, mU, mixed=False):
-    """Algorithmic HBM bytes of one application (every CSR entry and dense vector
-    moved once per launch): value + 4-byte index per entry, 4 bytes per row
-    pointer, 8/4 bytes per vector element."""
-    vb = 4 if mixed else 8
-    ib = 4 if mixed else 8
-    res = 4 * (n + 1) + 12 * nnzA + 8 * n * 3  # x gather, b, r
-    if mL == 1:
-        res += 8 * n - 8 * n + (8 * n + ib * n) - 8 * n  # writes s (ib) and reads dinv instead of writing r
-    tot = res
-    for k in range(2, mL + 1):
-        b = 4 * (n + 1) + (vb + 4) * nnzL + ib * n + 8 * n  # gather y (ib), rhs r (fp64)
-        b += (8 * n + ib * n) if k == mL and mU >= 2 else (24 * n if k == mL else ib * n)
-        tot += b
-    for k in range(2, mU + 1):
-        b = 4 * (n + 1) + (vb + 4) * nnzU + ib * n + ib * n
-        b += 16 * n if k == mU else ib * n
-        tot += b
-    if mL == 1 and mU == 1:
-        tot += (8 + ib + 8) * n
-    return outer * tot
-
-
 def cpu_baseline(W, nsample=100, reps=None):
     """The oracle (plain C, one thread) on a bounded sample of the same operator:
     the 27-pt anisotropic operator on an nsample^3 grid, its own ILUT factors,
@@ -106,6 +84,44 @@ def cpu_baseline(W, nsample=100, reps=None):
     return per_app, work_sample, A.n, k
 
 
+def bench_serving(torch, B, ctx, arena_mb):
+    """1,280 smoother requests (1-4 outer x 3/3, FP64) on 64 resident
+    variable-density matrices, Poisson arrivals at 2000/s, served with continuous
+    batching under a workspace arena of `arena_mb`; then the same stream one
+    request at a time with ilu_smooth."""
+    from paper_2111_09512_amd import serve as S
+
+    t = time.perf_counter()
+    sides = S.pool_spec()
+    mats = S.build_pool(ctx, sides)
+    log(f"serving pool: {len(mats)} matrices, n from {min(m[2] for m in mats)} to {max(m[2] for m in mats)}, "
+        f"set-up {time.perf_counter() - t:.1f}s")
+    reqs = S.make_requests(mats)
+    server = B.Server(ctx, arena_bytes=arena_mb << 20, max_active=1024)
+    mids = [server.register(Ad, F) for (Ad, F, _) in mats]
+    # warm the batched kernel on a few requests, then reset x
+    S.run_batched(server, mids, reqs[:8], realtime=False)
+    for r in reqs:
+        r.x.zero_()
+    lat_b, span_b, steps = S.run_batched(server, mids, reqs)
+    xb = [r.x.clone() for r in reqs[:32]]
+    for r in reqs:
+        r.x.zero_()
+    lat_1, span_1 = S.run_one_at_a_time(ctx, mats, reqs)
+    same = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(xb)))
+    server.close()
+    res = {"requests": len(reqs), "matrices": len(mats), "arrival_rate_per_s": 2000.0, "arena_MB": arena_mb,
+           "batched": {"apps_per_s": len(reqs) / span_b, "makespan_s": span_b, "steps": steps,
+                       **S.percentiles(lat_b)},
+           "one_at_a_time": {"apps_per_s": len(reqs) / span_1, "makespan_s": span_1, **S.percentiles(lat_1)},
+           "results_identical": same}
+    log(f"serving: batched p50 {res['batched']['p50_ms']:.2f} ms p99 {res['batched']['p99_ms']:.2f} ms "
+        f"{res['batched']['apps_per_s']:.0f} apps/s; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
+        f"p99 {res['one_at_a_time']['p99_ms']:.2f} ms {res['one_at_a_time']['apps_per_s']:.0f} apps/s; "
+        f"identical={same}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,9 +129,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="aniso200", choices=sorted(WORKLOADS))
     ap.add_argument("--N", type=int, default=None, help="override grid side (testing only)")
-    ap.add_argument("--kernel", default=None, choices=[None, "stream", "vector"])
+    ap.add_argument("--kernel", default=None, choices=[None, "stream", "vector", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the smoother shards as block-Jacobi ILU "
@@ -169,31 +187,36 @@ def main():
     del src, dst
     log(f"stream copy {copy_gbps:.0f} GB/s")
 
-    # ---- FP64 iterative smoother: the timed steps (per-kernel events on) ----
-    for _ in range(args.warmup):
-        app_f64()
-    torch.cuda.synchronize()
-    ctx.stats_reset()
-    ctx.set_timing(True)
-    ms = time_steps(torch, app_f64, args.steps, 0)
-    ctx.set_timing(False)
-    st = ctx.stats()
+    def timed(fn, label):
+        """Warm up, then time the steps with per-launch HIP events on; returns
+        (ms per application, algorithmic bytes per application, per-kernel stats)."""
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ctx.stats_reset()
+        ctx.set_timing(True)
+        ms_ = time_steps(torch, fn, args.steps, 0)
+        ctx.set_timing(False)
+        st_ = {k: v for k, v in ctx.stats().items() if v["launches"]}
+        bytes_ = sum(v["bytes"] for v in st_.values()) / args.steps
+        log(f"{label}: {ms_:.3f} ms/app, {1e3 / ms_:.1f} apps/s, {bytes_ / (ms_ * 1e-3) / 1e9:.0f} GB/s algorithmic")
+        for k, v in st_.items():
+            log(f"  kernel {k}: {v['launches']} launches, {v['ms'] / v['launches'] * 1e3:.1f} us avg, "
+                f"{v['bytes'] / v['ms'] / 1e6:.0f} GB/s")
+        return ms_, bytes_, st_
+
+    # ---- FP64 iterative smoother: the timed steps ----
+    ms, bytes_app, st = timed(app_f64, "FP64 iter")
     x64 = x.clone()
     apps = 1e3 / ms
-    bytes_app = app_bytes(n, nnzA, nnzL, nnzU, outer, mL, mU)
     gbps = bytes_app / (ms * 1e-3) / 1e9
-    log(f"FP64 iter: {ms:.3f} ms/app, {apps:.1f} apps/s, {gbps:.0f} GB/s algorithmic")
-    for k, v in st.items():
-        log(f"  kernel {k}: {v['launches']} launches, {v['ms'] / max(v['launches'], 1) * 1e3:.1f} us avg, "
-            f"{v['bytes'] / max(v['ms'], 1e-12) / 1e6:.0f} GB/s")
-    dom = max(st.items(), key=lambda kv: kv[1]["ms"])
-    dname, dv = dom
+    dname, dv = max(st.items(), key=lambda kv: kv[1]["ms"])
     ach = dv["bytes"] / dv["launches"] / (dv["ms"] / dv["launches"] * 1e-3) / 1e9
 
     # ---- mixed form ----
-    ms_mixed = time_steps(torch, app_mixed, args.steps, args.warmup)
+    ms_mixed, bytes_mixed, st_mixed = timed(app_mixed, "mixed")
     mixed_err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-    log(f"mixed: {ms_mixed:.3f} ms/app, rel diff vs FP64 GPU {mixed_err:.2e}")
+    log(f"mixed: rel diff vs FP64 GPU {mixed_err:.2e}")
 
     # ---- direct (level-scheduled) form ----
     ms_direct = None
@@ -219,6 +242,11 @@ def main():
                          f"scaled to n=8M by matrix entries per application ({work_full}/{work_s})"}
         log(f"cpu oracle: {per_app * 1e3:.1f} ms/app on the sample -> {cpu_apps:.3f} apps/s at full size")
 
+    # ---- serving stream (continuous batching on 64 resident matrices) ----
+    serving = None
+    if not args.no_serving:
+        serving = bench_serving(torch, B, ctx, args.serving_arena_mb)
+
     out = {
         "metric": METRIC,
         "value": apps,
@@ -240,17 +268,21 @@ def main():
         "copy_GBps": copy_gbps,
         "mixed_apps_per_s": 1e3 / ms_mixed,
         "mixed_ms": ms_mixed,
-        "mixed_GBps": app_bytes(n, nnzA, nnzL, nnzU, outer, mL, mU, mixed=True) / (ms_mixed * 1e-3) / 1e9,
+        "mixed_GBps": bytes_mixed / (ms_mixed * 1e-3) / 1e9,
+        "mixed_bytes_per_app": bytes_mixed,
         "mixed_rel_diff_vs_f64": mixed_err,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,
         "direct_levels": depths,
-        "kernels": {k: {"launches": v["launches"], "avg_us": v["ms"] / max(v["launches"], 1) * 1e3,
-                        "GBps": v["bytes"] / max(v["ms"], 1e-12) / 1e6} for k, v in st.items()},
+        "kernels": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                        "GBps": v["bytes"] / v["ms"] / 1e6} for k, v in st.items()},
+        "kernels_mixed": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                              "GBps": v["bytes"] / v["ms"] / 1e6} for k, v in st_mixed.items()},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBPS, "traffic": None},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

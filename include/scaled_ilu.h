@@ -62,6 +62,7 @@ extern "C" {
 #define SILU_KERNEL_VECTOR 0x200  /* vector-CSR (lanes-per-row) sweep kernel                */
 #define SILU_KERNEL_BLOCKED 0x400 /* CSR-stream over a row-block partition                  */
 #define SILU_NO_GRAPH 0x800       /* level-scheduled solves: plain launches, no hipGraph     */
+#define SILU_INDEX32 0x1000       /* sweeps read the 32-bit col_idx, never 16-bit offsets    */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -149,6 +150,13 @@ int ilu_scale_factors(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, silu_
 /* ---- the smoother (eq. ILUsplit, Algorithm 2, eq. richard) -------------- */
 
 /*
+ * Column indices.  By default the first sweep over a matrix also builds, on
+ * the device, block-relative 16-bit column offsets when every column lies
+ * within 65,536 of its row block's base (banded factors do; a randomly
+ * permuted matrix does not), caches them in the context (2 bytes per entry,
+ * keyed by the matrix's pointers and sizes; the first use synchronizes once)
+ * and streams those instead of col_idx.  SILU_INDEX32 disables this.
+ *
  * `outer_sweeps` smoothing steps on x (in/out; x = 0 for a pure
  * preconditioner application):
  *   r = b - A x;  y = m_L Richardson steps on L y = r from y = 0;
@@ -212,6 +220,13 @@ int trisolve_iter(silu_ctx *ctx, const silu_csr *T, const double *dinv, const do
  * Synchronous. */
 int silu_analyze(silu_ctx *ctx, const silu_csr *T, int uplo, int32_t *depth, int32_t *rows_per_level);
 
+/* Drop every analysis the context cached for the matrix whose row_ptr or
+ * col_idx is given (level sets and their graphs, row-block partitions,
+ * 16-bit offsets).  Analyses are keyed by pointers and sizes, so call this
+ * before freeing a matrix or changing its pattern in place.  Synchronizes
+ * the context stream. */
+int silu_release(silu_ctx *ctx, const void *row_ptr, const void *col_idx);
+
 /* ---- measurement ------------------------------------------------------- */
 
 /*
@@ -236,6 +251,42 @@ int silu_stats_reset(silu_ctx *ctx);
  * bandwidth and to calibrate traffic counters.  bytes must be a multiple of
  * 16 and both pointers 16-byte aligned.  Asynchronous. */
 int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
+
+/* ---- serving: continuous batching on resident matrices ---------------- */
+
+/*
+ * A server keeps registered matrices (A and their factors) resident and runs
+ * smoother requests on them (each request: `outer` steps of ilu_smooth's
+ * iteration, FP64).  silu_server_step() first admits queued requests in
+ * arrival order while their workspace (silu_server_request_bytes: four
+ * n-vectors) fits in the caller's arena and fewer than max_active are
+ * running, then enqueues ONE batched launch that advances every active
+ * request by one sweep (residual, an L sweep or a U sweep), whatever sweep
+ * each is at; requests that arrive later join at the next step.  A request's
+ * workspace returns to the arena once the GPU has passed its last launch.
+ * Each row is summed in a fixed order by one lane, so a request's result is
+ * bit-identical to ilu_smooth on its own.  At most 4 steps are in flight.
+ *
+ * arena: device memory owned by the caller, 256-byte aligned, alive until
+ * silu_server_destroy.  b and x of a request: device FP64 [n], alive until
+ * poll reports it done; x is the initial guess and receives the result.
+ * m_L, m_U >= 1 but not both 1.  Errors: ARG, SHAPE, UNSUPPORTED (unscaled
+ * or non-FP64 factors), NOMEM (one request alone exceeds the arena), HIP
+ * (silu_server_last_hip_error).  A server is used by one host thread.
+ */
+typedef struct silu_server silu_server;
+int silu_server_create(silu_ctx *ctx, void *hip_stream, void *arena, size_t arena_bytes, int max_active,
+                       silu_server **server);
+int silu_server_destroy(silu_server *server);
+int silu_server_register(silu_server *server, const silu_csr *A, const silu_factors *F, int *matrix_id);
+int64_t silu_server_request_bytes(const silu_server *server, int matrix_id);
+int silu_server_submit(silu_server *server, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
+                       int64_t *ticket);
+/* One scheduling step (asynchronous; blocks only when 4 steps are in flight). */
+int silu_server_step(silu_server *server, int *n_active, int *n_queued);
+/* state: 0 queued, 1 running, 2 last sweep enqueued, 3 done (result in x). */
+int silu_server_poll(silu_server *server, int64_t ticket, int *state);
+int silu_server_last_hip_error(const silu_server *server);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -30,8 +31,9 @@ _lib = C.CDLL(LIB_PATH)
 SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
-SILU_NO_GRAPH = 0x800
-KERNELS = {None: 0, "blocked": SILU_KERNEL_BLOCKED, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR}
+SILU_NO_GRAPH, SILU_INDEX32 = 0x800, 0x1000
+KERNELS = {None: 0, "blocked": SILU_KERNEL_BLOCKED, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR,
+           "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1
 SILU_UNIT, SILU_NONUNIT = 0, 1
 
@@ -79,6 +81,7 @@ _sig = {
     "trisolve_direct": (C.c_int, [_P, C.POINTER(silu_csr), C.c_int, C.c_int, _P, _P, C.c_int]),
     "trisolve_iter": (C.c_int, [_P, C.POINTER(silu_csr), _P, _P, _P, C.c_int, C.c_int, _P, C.c_size_t]),
     "silu_analyze": (C.c_int, [_P, C.POINTER(silu_csr), C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "silu_release": (C.c_int, [_P, _P, _P]),
     "silu_set_timing": (C.c_int, [_P, C.c_int]),
     "silu_stats_collect": (C.c_int, [_P]),
     "silu_stats_get": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
@@ -90,6 +93,14 @@ _sig = {
     "silu_factor_ilut": (C.c_int, [C.POINTER(silu_host_csr), C.c_double, C.c_int, C.POINTER(silu_host_csr),
                                    C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
     "silu_host_csr_free": (None, [C.POINTER(silu_host_csr)]),
+    "silu_server_create": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int, C.POINTER(_P)]),
+    "silu_server_destroy": (C.c_int, [_P]),
+    "silu_server_register": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.POINTER(C.c_int)]),
+    "silu_server_request_bytes": (C.c_int64, [_P, C.c_int]),
+    "silu_server_submit": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64)]),
+    "silu_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "silu_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
+    "silu_server_last_hip_error": (C.c_int, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -188,6 +199,17 @@ class Context:
             raise SiluError(st, "silu_create")
         self._h = h
         self._ws = None
+        self._tracked = set()
+
+    def _track(self, *mats):
+        """Release the context's cached analyses of a matrix when its index
+        arrays are freed (they are keyed by pointer in the library)."""
+        for M in mats:
+            key = (M.row_ptr.data_ptr(), M.col_idx.data_ptr() if M.nnz else 0)
+            if key in self._tracked:
+                continue
+            self._tracked.add(key)
+            weakref.finalize(M.row_ptr, _release_cb, weakref.ref(self), key)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -250,6 +272,7 @@ class Context:
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws
+        self._track(A, F.Ls, F.Us)
         Ac, Fc = A.c(), F.c()
         self._check(_lib.ilu_smooth2(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags,
@@ -260,6 +283,7 @@ class Context:
                         validate: bool = False, graph: bool = True) -> torch.Tensor:
         _vec(rhs, T.n, "rhs")
         out = torch.empty_like(rhs) if out is None else out
+        self._track(T)
         Tc = T.c()
         self._check(_lib.trisolve_direct(self._h, C.byref(Tc), uplo, diag, C.c_void_p(rhs.data_ptr()),
                                          C.c_void_p(out.data_ptr()),
@@ -273,6 +297,7 @@ class Context:
         out = torch.empty_like(rhs) if out is None else out
         flags = KERNELS[kernel]
         ws = self.workspace(T.n, 0)
+        self._track(T)
         Tc = T.c()
         self._check(_lib.trisolve_iter(self._h, C.byref(Tc), C.c_void_p(_ptr(dinv)), C.c_void_p(rhs.data_ptr()),
                                        C.c_void_p(out.data_ptr()), m, flags, C.c_void_p(ws.data_ptr()),
@@ -281,6 +306,7 @@ class Context:
 
     def silu_analyze(self, T: Csr, uplo: int):
         depth = C.c_int32()
+        self._track(T)
         Tc = T.c()
         self._check(_lib.silu_analyze(self._h, C.byref(Tc), uplo, C.byref(depth), None), "silu_analyze")
         rows = (C.c_int32 * max(depth.value, 1))()
@@ -311,6 +337,13 @@ class Context:
         nb = src.numel() * src.element_size()
         self._check(_lib.silu_stream_copy(self._h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb),
                     "silu_stream_copy")
+
+
+def _release_cb(ctx_ref, key):
+    ctx = ctx_ref()
+    if ctx is not None and getattr(ctx, "_h", None):
+        _lib.silu_release(ctx._h, C.c_void_p(key[0]), C.c_void_p(key[1] or None))
+        ctx._tracked.discard(key)
 
 
 def _vec(t: torch.Tensor, n: int, what: str):
@@ -383,3 +416,71 @@ def factor(A, kind: str, params: dict) -> tuple[HostCsr, HostCsr]:
     if kind == "ilut":
         return factor_ilut(A, params["tau"], params["p"])
     raise KeyError(kind)
+
+
+# --------------------------------------------------------------------------
+# serving (continuous batching on resident matrices)
+# --------------------------------------------------------------------------
+
+class Server:
+    """Wraps a silu_server.  The arena (device workspace budget) is a torch
+    tensor owned here; registered matrices and request vectors are kept
+    referenced until the server is closed, so the device pointers stay valid."""
+
+    QUEUED, RUNNING, LAUNCHED, DONE = 0, 1, 2, 3
+
+    def __init__(self, ctx: Context, arena_bytes: int, max_active: int = 256):
+        self.ctx = ctx
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        st = _lib.silu_server_create(ctx._h, C.c_void_p(ctx.stream.cuda_stream), C.c_void_p(self.arena.data_ptr()),
+                                     arena_bytes, max_active, C.byref(h))
+        if st:
+            raise SiluError(st, "silu_server_create")
+        self._h = h
+        self._keep = []
+        self._req = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.silu_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, where):
+        if st:
+            raise SiluError(st, where, hip=int(_lib.silu_server_last_hip_error(self._h)))
+
+    def register(self, A: Csr, F: Factors) -> int:
+        mid = C.c_int()
+        Ac, Fc = A.c(), F.c()
+        self._check(_lib.silu_server_register(self._h, C.byref(Ac), C.byref(Fc), C.byref(mid)), "silu_server_register")
+        self._keep.append((A, F))
+        return mid.value
+
+    def request_bytes(self, mid: int) -> int:
+        return int(_lib.silu_server_request_bytes(self._h, mid))
+
+    def submit(self, mid: int, b: torch.Tensor, x: torch.Tensor, outer: int, m_L: int, m_U: int) -> int:
+        t = C.c_int64()
+        self._check(_lib.silu_server_submit(self._h, mid, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), outer,
+                                            m_L, m_U, C.byref(t)), "silu_server_submit")
+        self._req[t.value] = (b, x)
+        return t.value
+
+    def step(self) -> tuple[int, int]:
+        a, q = C.c_int(), C.c_int()
+        self._check(_lib.silu_server_step(self._h, C.byref(a), C.byref(q)), "silu_server_step")
+        return a.value, q.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int()
+        self._check(_lib.silu_server_poll(self._h, ticket, C.byref(st)), "silu_server_poll")
+        if st.value == self.DONE:
+            self._req.pop(ticket, None)
+        return st.value

@@ -26,6 +26,7 @@ namespace {
 
 struct LevelInfo {
     int32_t *d_perm = nullptr;
+    int lanes = 1;                  // lanes per row of the level kernel
     std::vector<int32_t> level_ptr; // [depth + 1], host
     std::vector<int64_t> level_nnz; // off-diagonal entries per level, host
     int depth = 0;
@@ -38,6 +39,14 @@ struct Partition {
     int nblk = 0;
 };
 using PartKey = std::tuple<const void *, int64_t, int64_t, int>;
+
+// 16-bit block-relative column offsets of one matrix for one rows-per-block.
+struct Compressed {
+    uint16_t *d = nullptr;
+    int shift = 0;
+    bool ok = false;
+};
+using CompKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
 
 // A captured level sequence: one kernel node per level.
 using GraphKey = std::tuple<const void *, const void *, const void *, const void *, const void *, const void *,
@@ -59,6 +68,7 @@ struct silu_ctx {
     int32_t *d_flags = nullptr; // [4] device status words
     std::map<LevelKey, LevelInfo> levels;
     std::map<PartKey, Partition> parts;
+    std::map<CompKey, Compressed> comp;
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr; // private, default priority, for graph capture
     bool timing = false;
@@ -176,14 +186,14 @@ struct Ws {
 
 size_t ws_vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
 
-double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift)
+double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift, double ib)
 {
     double vb = 8, xb = 8, rb = 8, ob = 8;
     if (p == Prec::MIX_RES) ob = 4;
     if (p == Prec::MIX_L) vb = xb = ob = 4;
     if (p == Prec::MIX_U) vb = xb = rb = ob = 4;
     if (p == Prec::MIX_L1) vb = ob = 4;
-    double b = 4.0 * (double)(n + 1) + (double)nnz * (vb + 4.0) + (double)n * (xb + rb);
+    double b = 4.0 * (double)(n + 1) + (double)nnz * (vb + ib) + (double)n * (xb + rb);
     switch (epi) {
     case EPI_STORE: b += n * ob; break;
     case EPI_SCALE: b += n * (8.0 + ob); break;
@@ -238,9 +248,50 @@ int get_partition(silu_ctx *c, const silu_csr *M, int cap, int rmax, Partition *
     return SILU_OK;
 }
 
+// Block-relative 16-bit column offsets, made on first use on the device (one
+// synchronous read of the offset range) and cached per matrix; ok = false
+// when some offset does not fit 16 bits.
+int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, Compressed **out)
+{
+    CompKey key{M->row_ptr, M->col_idx, M->n_rows, M->nnz, rpb};
+    auto it = c->comp.find(key);
+    if (it != c->comp.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    Compressed C;
+    HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
+    HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
+    HIPCHK(c, launch_offset_range((int)M->n_rows, M->row_ptr, M->col_idx, rpb, c->d_flags, c->stream));
+    int32_t range[2];
+    HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (range[0] <= range[1] && (int64_t)range[1] - (int64_t)range[0] <= 65535) {
+        HIPCHK(c, hipMalloc(&C.d, (size_t)M->nnz * sizeof(uint16_t)));
+        C.shift = range[0];
+        hipError_t e = launch_compress16((int)M->n_rows, M->row_ptr, M->col_idx, rpb, C.shift, C.d, c->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(C.d);
+            return hip_fail(c, e);
+        }
+        C.ok = true;
+    }
+    *out = &c->comp.emplace(key, C).first->second;
+    return SILU_OK;
+}
+
 int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
           const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift)
 {
+    if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
+        Compressed *C = nullptr;
+        int st = get_compressed(c, N, g.rows_per_block, &C);
+        if (st) return st;
+        if (C->ok) {
+            g.off16 = C->d;
+            g.shift = C->shift;
+        }
+    }
     if (g.kind == SweepKernel::BLOCKED) {
         Partition *P = nullptr;
         int st = get_partition(c, N, g.cap, RB_RMAX, &P);
@@ -260,7 +311,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     a.dinv = dinv;
     a.x = x;
     a.dshift = dshift;
-    const double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr);
+    const double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, g.off16 ? 2.0 : 4.0);
     return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
 
@@ -306,6 +357,12 @@ int get_levels(silu_ctx *c, const silu_csr *T, int uplo, LevelInfo **out)
         info.level_nnz[(size_t)lev[(size_t)i]] += off;
     }
     for (int32_t l = 0; l < depth; l++) info.level_ptr[(size_t)l + 1] += info.level_ptr[(size_t)l];
+    {
+        int64_t off = 0;
+        for (int32_t l = 0; l < depth; l++) off += info.level_nnz[(size_t)l];
+        const double mean = n > 0 ? (double)off / (double)n : 0.0;
+        info.lanes = mean <= 2.0 ? 1 : (mean <= 6.0 ? 4 : (mean <= 12.0 ? 8 : (mean <= 24.0 ? 16 : 32)));
+    }
     std::vector<int32_t> perm((size_t)n), fill(info.level_ptr.begin(), info.level_ptr.end() - 1);
     for (int64_t i = 0; i < n; i++) perm[(size_t)fill[(size_t)lev[(size_t)i]]++] = (int32_t)i;
     HIPCHK(c, hipMalloc(&info.d_perm, (size_t)n * 4));
@@ -324,7 +381,7 @@ hipError_t enqueue_levels(const LevelArgs &a, const LevelInfo *li, int unit, hip
 {
     for (int l = 0; l < li->depth; l++) {
         const int start = li->level_ptr[(size_t)l], count = li->level_ptr[(size_t)l + 1] - start;
-        hipError_t e = launch_level(a, unit, start, count, s, nullptr);
+        hipError_t e = launch_level(a, unit, li->lanes, start, count, s, nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -391,7 +448,7 @@ int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const do
         if (s_out) bytes += count * 16.0;
         if (xupd) bytes += count * 16.0;
         int st = timed_launch(c, bytes, [&](const char **nm) {
-            return launch_level(a, unit, start, count, c->stream, nm);
+            return launch_level(a, unit, li->lanes, start, count, c->stream, nm);
         });
         if (st) return st;
     }
@@ -439,6 +496,7 @@ int silu_destroy(silu_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->levels) (void)hipFree(kv.second.d_perm);
     for (auto &kv : c->parts) (void)hipFree(kv.second.d_blk);
+    for (auto &kv : c->comp) (void)hipFree(kv.second.d);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
@@ -689,6 +747,46 @@ int silu_analyze(silu_ctx *c, const silu_csr *T, int uplo, int32_t *depth, int32
     *depth = li->depth;
     if (rows_per_level)
         for (int l = 0; l < li->depth; l++) rows_per_level[l] = li->level_ptr[(size_t)l + 1] - li->level_ptr[(size_t)l];
+    return SILU_OK;
+}
+
+int silu_release(silu_ctx *c, const void *row_ptr, const void *col_idx)
+{
+    if (!c) return SILU_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream)); // nothing queued may still use what is dropped
+    for (auto it = c->levels.begin(); it != c->levels.end();) {
+        if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
+            const LevelInfo *li = &it->second;
+            for (auto g = c->graphs.begin(); g != c->graphs.end();) {
+                if (std::get<0>(g->first) == li) {
+                    (void)hipGraphExecDestroy(g->second);
+                    g = c->graphs.erase(g);
+                } else {
+                    ++g;
+                }
+            }
+            (void)hipFree(it->second.d_perm);
+            it = c->levels.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = c->parts.begin(); it != c->parts.end();) {
+        if (std::get<0>(it->first) == row_ptr) {
+            (void)hipFree(it->second.d_blk);
+            it = c->parts.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = c->comp.begin(); it != c->comp.end();) {
+        if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
+            (void)hipFree(it->second.d);
+            it = c->comp.erase(it);
+        } else {
+            ++it;
+        }
+    }
     return SILU_OK;
 }
 

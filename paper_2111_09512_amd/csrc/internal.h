@@ -55,10 +55,27 @@ struct SweepGeom {
     int cap = RB_CAP;             // BLOCKED: entries per row block
     const int32_t *blk = nullptr; // BLOCKED: device (row start, entry start) pairs [nblk + 1]
     int nblk = 0;
+    bool allow16 = false;             // STREAM: may use 16-bit block-relative column offsets
+    const uint16_t *off16 = nullptr;  // STREAM: offsets (col = r0 + shift + off16[e]) when available
+    int shift = 0;
 };
+
+// Block-relative 16-bit column offsets for the CSR-stream kernel with `rpb`
+// rows per workgroup.  offset_range writes min and max of col - r0(block) over
+// all entries into range[0], range[1] (initialised to INT_MAX, INT_MIN);
+// compress16 writes off16[e] = col - r0(block) - shift.
+hipError_t launch_offset_range(int n, const int32_t *rp, const int32_t *col, int rpb, int32_t *range, hipStream_t s);
+hipError_t launch_compress16(int n, const int32_t *rp, const int32_t *col, int rpb, int shift, uint16_t *off16,
+                             hipStream_t s);
 
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name);
+
+// Batched FP64 CSR-stream sweeps (serving): d_ops[i] is one request's sweep,
+// d_first[i] its first workgroup (ceil(n_i / rpb) workgroups each), total the
+// sum.  Both arrays live in device memory.
+hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
+                              hipStream_t s);
 
 struct LevelArgs {
     const int32_t *perm; // rows ordered by level
@@ -71,7 +88,9 @@ struct LevelArgs {
     double *s_out;
     double *xupd;       // optional: xupd += out
 };
-hipError_t launch_level(const LevelArgs &a, int unit, int start, int count, hipStream_t s, const char **name);
+// lanes: 1 (one lane per row, sequential row sum) or 4/8/16/32 lanes per row.
+hipError_t launch_level(const LevelArgs &a, int unit, int lanes, int start, int count, hipStream_t s,
+                        const char **name);
 
 hipError_t launch_scale_rows(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, int32_t *Usrp,
                              int32_t *Uscol, double *Usval, double *d, double *dinv, float *Us32, int noscale,

@@ -74,9 +74,48 @@ __global__ void __launch_bounds__(256) k_finite_check(int n, const double *__res
     if (i < n && !isfinite(x[i])) atomicMin(&flags[2], i);
 }
 
-// One level of a level-scheduled substitution: each lane finishes one row
-// whose dependencies all lie in earlier levels.  The row sum runs in
-// ascending column order, like a sequential substitution.
+// One level of a level-scheduled substitution with K lanes per row: every
+// row of the level depends only on rows of earlier levels.  Lanes take the
+// row's entries round-robin, so the loads of a row are in flight together;
+// the partial sums are combined with cross-lane shuffles (the stored
+// diagonal, held by one lane, is combined exactly as a sum with zeros).
+template <int UNIT, int K>
+__global__ void __launch_bounds__(256) k_level_vec(LevelArgs a, int start, int count)
+{
+    const int slot = (int)((blockIdx.x * blockDim.x + threadIdx.x) / K);
+    const int lane = (int)threadIdx.x & (K - 1);
+    const bool live = slot < count;
+    int i = 0;
+    double sum = 0.0, dii = 0.0;
+    if (live) {
+        i = a.perm[start + slot];
+        const int p1 = a.rp[i + 1];
+#pragma unroll 2
+        for (int p = a.rp[i] + lane; p < p1; p += K) {
+            const int j = a.col[p];
+            const double v = a.val[p];
+            if (j == i)
+                dii = v;
+            else
+                sum = sum + v * a.out[j];
+        }
+    }
+#pragma unroll
+    for (int off = K / 2; off > 0; off >>= 1) {
+        sum = sum + __shfl_xor(sum, off, K);
+        if (!UNIT) dii = dii + __shfl_xor(dii, off, K);
+    }
+    if (live && lane == 0) {
+        double v = a.rhs[i] - sum;
+        if (!UNIT) v = v / dii;
+        a.out[i] = v;
+        if (a.s_out) a.s_out[i] = a.dinv[i] * v;
+        if (a.xupd) a.xupd[i] = a.xupd[i] + v;
+    }
+}
+
+// One level, one lane per row, the row summed in ascending column order like
+// a sequential substitution (bit-identical to it; used for short rows).
 template <int UNIT>
 __global__ void __launch_bounds__(256) k_level(LevelArgs a, int start, int count)
 {
@@ -131,6 +170,34 @@ __global__ void __launch_bounds__(256) k_copy16(const u32x4 *__restrict__ src, u
     for (; i < n16; i += bd) dst[i] = src[i];
 }
 
+__global__ void __launch_bounds__(256) k_offset_range(int n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col, int rpb, int32_t *range)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int r0 = (i / rpb) * rpb;
+    int lo = INT32_MAX, hi = INT32_MIN;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int o = col[p] - r0;
+        lo = min(lo, o);
+        hi = max(hi, o);
+    }
+    if (lo <= hi) {
+        atomicMin(&range[0], lo);
+        atomicMax(&range[1], hi);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_compress16(int n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col, int rpb, int shift,
+                                                    uint16_t *__restrict__ off16)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int base = (i / rpb) * rpb + shift;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) off16[p] = (uint16_t)(col[p] - base);
+}
+
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 } // namespace
@@ -176,14 +243,31 @@ hipError_t launch_finite_check(int n, const double *x, int32_t *flags, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_level(const LevelArgs &a, int unit, int start, int count, hipStream_t s, const char **name)
+template <int UNIT, int K>
+void go_level(const LevelArgs &a, int start, int count, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_level_vec<UNIT, K>), dim3(blocks_for((int64_t)count * K, 256)), dim3(256), 0, s, a, start,
+                       count);
+}
+
+hipError_t launch_level(const LevelArgs &a, int unit, int lanes, int start, int count, hipStream_t s,
+                        const char **name)
 {
     if (name) *name = "level_f64";
     if (count <= 0) return hipSuccess;
-    if (unit)
-        hipLaunchKernelGGL(k_level<1>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count);
-    else
-        hipLaunchKernelGGL(k_level<0>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count);
+    switch (lanes * 2 + (unit ? 1 : 0)) {
+    case 1 * 2 + 1: hipLaunchKernelGGL(k_level<1>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count); break;
+    case 1 * 2: hipLaunchKernelGGL(k_level<0>, dim3(blocks_for(count, 256)), dim3(256), 0, s, a, start, count); break;
+    case 4 * 2 + 1: go_level<1, 4>(a, start, count, s); break;
+    case 4 * 2: go_level<0, 4>(a, start, count, s); break;
+    case 8 * 2 + 1: go_level<1, 8>(a, start, count, s); break;
+    case 8 * 2: go_level<0, 8>(a, start, count, s); break;
+    case 16 * 2 + 1: go_level<1, 16>(a, start, count, s); break;
+    case 16 * 2: go_level<0, 16>(a, start, count, s); break;
+    case 32 * 2 + 1: go_level<1, 32>(a, start, count, s); break;
+    case 32 * 2: go_level<0, 32>(a, start, count, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -191,6 +275,21 @@ hipError_t launch_scale_copy(int n, const double *rhs, const double *dinv, doubl
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scale_copy, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rhs, dinv, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_offset_range(int n, const int32_t *rp, const int32_t *col, int rpb, int32_t *range, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_offset_range, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, rpb, range);
+    return hipGetLastError();
+}
+
+hipError_t launch_compress16(int n, const int32_t *rp, const int32_t *col, int rpb, int shift, uint16_t *off16,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compress16, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, rpb, shift, off16);
     return hipGetLastError();
 }
 

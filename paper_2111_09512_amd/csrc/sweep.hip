@@ -108,8 +108,12 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
 // CSR-stream: RPB rows per workgroup of BLOCK lanes (RPB <= BLOCK); products
 // staged in LDS in chunks of CAP entries.
 // ---------------------------------------------------------------------------
-template <class T, int BLOCK, int RPB, int CAP>
-__global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
+// With C16 the column of entry e is r0 + shift + off16[e] (block-relative
+// 16-bit offsets, built once per matrix when every offset fits): 2 bytes of
+// index per entry instead of 4.
+template <class T, int BLOCK, int RPB, int CAP, bool C16>
+__device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const uint16_t *__restrict__ off16,
+                                            int shift)
 {
     using VT = typename T::VT;
     using XT = typename T::XT;
@@ -119,7 +123,6 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
     __shared__ AT prod[CAP];
     __shared__ int32_t srp[RPB + 1];
 
-    const int blk = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
     const int r0 = blk * RPB;
     const int nr = min(RPB, a.n - r0);
     const int tid = (int)threadIdx.x;
@@ -141,8 +144,10 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
     for (int c0 = e0; c0 < e1; c0 += CAP) {
         const int c1 = min(c0 + CAP, e1);
 #pragma unroll 4
-        for (int e = c0 + tid; e < c1; e += BLOCK)
-            prod[e - c0] = (AT)__builtin_nontemporal_load(&val[e]) * (AT)xin[__builtin_nontemporal_load(&col[e])];
+        for (int e = c0 + tid; e < c1; e += BLOCK) {
+            const int j = C16 ? r0 + shift + (int)__builtin_nontemporal_load(&off16[e]) : __builtin_nontemporal_load(&col[e]);
+            prod[e - c0] = (AT)__builtin_nontemporal_load(&val[e]) * (AT)xin[j];
+        }
         __syncthreads();
         const int lo = max(mylo, c0), hi = min(myhi, c1);
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
@@ -153,6 +158,37 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
         const AT t = (AT)((const RT *)a.rhs)[row] - sum;
         epilogue<T>(a, row, t);
     }
+}
+
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
+{
+    stream_rows<T, BLOCK, RPB, CAP, false>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), nullptr, 0);
+}
+
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_stream16(SweepArgs a, const uint16_t *__restrict__ off16, int shift)
+{
+    stream_rows<T, BLOCK, RPB, CAP, true>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), off16, shift);
+}
+
+// Batched CSR-stream: one launch runs one sweep for each of `nops`
+// independent requests (different matrices, sizes and epilogues).  Op i owns
+// workgroups [first[i], first[i+1]); each workgroup finds its op by binary
+// search and runs exactly the single-request body, so a request's result does
+// not depend on what else shares the launch.
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch(const SweepArgs *__restrict__ ops,
+                                                              const int32_t *__restrict__ first, int nops)
+{
+    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = nops - 1; // largest i with first[i] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    stream_rows<T, BLOCK, RPB, CAP, false>(ops[lo], b - first[lo], nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,10 +301,13 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_vector(SweepArgs a)
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
-hipError_t go_stream(const SweepArgs &a, hipStream_t s)
+hipError_t go_stream(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 {
     const int grid = (a.n + RPB - 1) / RPB;
-    hipLaunchKernelGGL((k_sweep_stream<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a);
+    if (g.off16)
+        hipLaunchKernelGGL((k_sweep_stream16<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a, g.off16, g.shift);
+    else
+        hipLaunchKernelGGL((k_sweep_stream<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
@@ -299,9 +338,9 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
     }
     if (g.kind == SweepKernel::STREAM) {
         switch (g.rows_per_block) {
-        case 256: return go_stream<T, 256, 256, 1024>(a, s);
-        case 128: return go_stream<T, 256, 128, 1024>(a, s);
-        case 64: return go_stream<T, 256, 64, 2048>(a, s);
+        case 256: return go_stream<T, 256, 256, 1024>(g, a, s);
+        case 128: return go_stream<T, 256, 128, 1024>(g, a, s);
+        case 64: return go_stream<T, 256, 64, 2048>(g, a, s);
         default: return hipErrorInvalidValue;
         }
     }
@@ -313,6 +352,36 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
     case 64: return go_vector<T, 64>(a, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <class T>
+hipError_t dispatch_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
+                          hipStream_t s)
+{
+    if (nops <= 0 || total <= 0) return hipSuccess;
+    switch (rpb) {
+    case 256:
+        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 256, 1024>), dim3(total), dim3(256), 0, s, d_ops, d_first,
+                           nops);
+        break;
+    case 128:
+        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 128, 1024>), dim3(total), dim3(256), 0, s, d_ops, d_first,
+                           nops);
+        break;
+    case 64:
+        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 64, 2048>), dim3(total), dim3(256), 0, s, d_ops, d_first,
+                           nops);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+const char *kname16(Prec p)
+{
+    static const char *names[5] = {"sweep_stream16_f64", "sweep_stream16_mixres", "sweep_stream16_mixL",
+                                   "sweep_stream16_mixU", "sweep_stream16_mixL1"};
+    return names[(int)p];
 }
 
 const char *kname(Prec p, SweepKernel k)
@@ -336,6 +405,12 @@ static bool geom_override(SweepGeom &g)
     if (sscanf(e, "blocked:%d", &v) == 1 && (v == 1024 || v == 2048 || v == 4096)) {
         g.kind = SweepKernel::BLOCKED;
         g.cap = v;
+        return true;
+    }
+    if (sscanf(e, "stream16:%d", &v) == 1 && (v == 64 || v == 128 || v == 256)) {
+        g.kind = SweepKernel::STREAM;
+        g.rows_per_block = v;
+        g.allow16 = true;
         return true;
     }
     if (sscanf(e, "stream:%d", &v) == 1 && (v == 64 || v == 128 || v == 256)) {
@@ -372,12 +447,19 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     // workgroup with 256 of them, long rows take 64 so one LDS chunk holds them
     g.kind = SweepKernel::STREAM;
     g.rows_per_block = mean <= 8.0 ? 256 : (mean <= 16.0 ? 128 : 64);
+    g.allow16 = !(flags & 0x1000); // SILU_INDEX32 keeps 32-bit column indices
     return g;
+}
+
+hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
+                              hipStream_t s)
+{
+    return dispatch_batch<TF64>(rpb, d_ops, d_first, nops, total, s);
 }
 
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name)
 {
-    if (name) *name = kname(p, g.kind);
+    if (name) *name = (g.kind == SweepKernel::STREAM && g.off16) ? kname16(p) : kname(p, g.kind);
     switch (p) {
     case Prec::F64: return dispatch<TF64>(g, a, s);
     case Prec::MIX_RES: return dispatch<TMixRes>(g, a, s);

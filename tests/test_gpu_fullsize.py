@@ -46,7 +46,10 @@ def test_full_poisson32(orc, B, ctx):
         ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(c.A.n), wl.outer, wl.m_L, wl.m_U, direct=direct)
         x = dev(np.zeros(c.A.n))
         ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, direct=direct)
-        np.testing.assert_array_equal(host(x), ref)
+        if direct:
+            assert_close(host(x), ref, F64_TOL, "poisson32 direct")
+        else:
+            np.testing.assert_array_equal(host(x), ref)
     ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(c.A.n), wl.outer, wl.m_L, wl.m_U)
     x = dev(np.zeros(c.A.n))
     ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, mixed=True)
@@ -72,7 +75,7 @@ def test_full_vardens128_inner_sweep(orc, B, ctx):
     ref = orc.smooth(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), 1, 0, 0, direct=True)
     x.zero_()
     ctx.ilu_smooth(c.Ad, c.F, bd, x, 1, 1, 1, direct=True)
-    np.testing.assert_array_equal(host(x), ref)
+    assert_close(host(x), ref, F64_TOL, "vardens128 direct")
     # the unscaled variant on the same ILU(1) factors
     Fu = ctx.ilu_scale_factors(c.Ld, c.Ud, scale=False)
     ref = orc.smooth_unscaled(c.A, c.Ls, c.U, b, np.zeros(n), 1, 3, 3)

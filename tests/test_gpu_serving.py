@@ -1,0 +1,171 @@
+"""GPU tests of the serving form: continuous batching on resident matrices.
+
+Each request's result in the mix must equal the same request run alone
+(ilu_smooth) bit for bit, and the oracle's; admission respects the workspace
+arena; every request completes (no starvation), including requests that
+arrive while others are running."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2111_09512_amd import workloads as W
+from tests.gpu_common import dev, host, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    need_gpu()
+    from paper_2111_09512_amd import binding
+
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context()
+
+
+@pytest.fixture(scope="module")
+def pool(orc, B, ctx):
+    """Resident matrices of different sizes (ragged row counts included)."""
+    out = []
+    for j, N in enumerate((6, 9, 13, 16, 21)):
+        A = W.vardens7(N, seed_rho=5 + j, with_cuts=False)
+        Ls, U = orc.ilu0(A)
+        d, dinv, Us = orc.scale_rows(U)
+        Ad, Ld, Ud = B.Csr.from_host(A), B.Csr.from_host(Ls), B.Csr.from_host(U)
+        F = ctx.ilu_scale_factors(Ld, Ud)
+        out.append(dict(A=A, Ls=Ls, Us=Us, dinv=dinv, Ad=Ad, Ud=Ud, F=F))
+    torch.cuda.synchronize()
+    return out
+
+
+def _requests(pool, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(count):
+        mid = int(rng.integers(0, len(pool)))
+        n = pool[mid]["A"].n
+        outer = int(rng.integers(1, 5))
+        mL, mU = [(3, 3), (2, 4), (1, 3), (4, 1), (3, 2)][k % 5]
+        reqs.append(dict(mid=mid, b=W.rhs(n, 100 + k), x0=W.rhs(n, 500 + k) * (k % 2), outer=outer, mL=mL, mU=mU))
+    return reqs
+
+
+def _alone(ctx, pool, r):
+    p = pool[r["mid"]]
+    x = dev(r["x0"])
+    ctx.ilu_smooth(p["Ad"], p["F"], dev(r["b"]), x, r["outer"], r["mL"], r["mU"])
+    return host(x)
+
+
+def _drain(server, tickets, max_steps=100000):
+    left = set(tickets)
+    steps = 0
+    while left:
+        server.step()
+        steps += 1
+        for t in list(left):
+            if server.poll(t) == server.DONE:
+                left.discard(t)
+        assert steps < max_steps, "requests starved"
+    return steps
+
+
+def test_mix_equals_alone_and_oracle(orc, B, ctx, pool):
+    say("serving: mix vs alone")
+    reqs = _requests(pool, 60, seed=1)
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=64)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    xs, tickets = [], []
+    for r in reqs:
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+    _drain(server, tickets)
+    for i, r in enumerate(reqs):
+        got = host(xs[i])
+        np.testing.assert_array_equal(got, _alone(ctx, pool, r))
+        if i < 12:
+            p = pool[r["mid"]]
+            ref = orc.smooth(p["A"], p["Ls"], p["Us"], p["dinv"], r["b"], r["x0"], r["outer"], r["mL"], r["mU"])
+            np.testing.assert_array_equal(got, ref)
+    server.close()
+
+
+def test_admission_by_workspace_budget(B, ctx, pool):
+    """An arena that holds exactly two of the largest requests: never more
+    active than fit, and everything completes in order of arrival."""
+    say("serving: admission")
+    big = len(pool) - 1
+    server = B.Server(ctx, arena_bytes=1 << 30, max_active=1000)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    per = server.request_bytes(mids[big])
+    server.close()
+    server = B.Server(ctx, arena_bytes=2 * per, max_active=1000)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    n = pool[big]["A"].n
+    tickets, xs = [], []
+    for k in range(7):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        xs.append(x)
+        tickets.append(server.submit(mids[big], dev(W.rhs(n, k)), x, 2, 3, 3))
+    max_active = 0
+    finished_order = []
+    left = list(tickets)
+    while left:
+        active, queued = server.step()
+        max_active = max(max_active, active)
+        for t in list(left):
+            if server.poll(t) == server.DONE:
+                finished_order.append(t)
+                left.remove(t)
+    assert max_active <= 2
+    assert finished_order == sorted(finished_order)
+    with pytest.raises(B.SiluError) as e:  # one request larger than the whole arena
+        small = B.Server(ctx, arena_bytes=per // 2, max_active=4)
+        m = small.register(pool[big]["Ad"], pool[big]["F"])
+        small.submit(m, dev(W.rhs(n, 0)), xs[0], 1, 3, 3)
+    assert e.value.status == -6
+    server.close()
+
+
+def test_arrivals_while_running(B, ctx, pool):
+    """Requests submitted between steps join running ones; each still equals
+    its lone run."""
+    say("serving: staggered arrivals")
+    reqs = _requests(pool, 40, seed=7)
+    server = B.Server(ctx, arena_bytes=32 << 20, max_active=16)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    xs, tickets = [], []
+    for i, r in enumerate(reqs):
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+        for _ in range(i % 3):
+            server.step()
+    _drain(server, tickets)
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
+    server.close()
+
+
+def test_serving_errors(B, ctx, pool):
+    say("serving: errors")
+    server = B.Server(ctx, arena_bytes=8 << 20, max_active=4)
+    mid = server.register(pool[0]["Ad"], pool[0]["F"])
+    n = pool[0]["A"].n
+    b, x = dev(W.rhs(n, 0)), dev(np.zeros(n))
+    with pytest.raises(B.SiluError) as e:
+        server.submit(mid, b, x, 1, 1, 1)
+    assert e.value.status == -1
+    with pytest.raises(B.SiluError) as e:
+        server.submit(mid + 5, b, x, 1, 3, 3)
+    assert e.value.status == -1
+    Fu = ctx.ilu_scale_factors(pool[0]["F"].Ls, pool[0]["Ud"], scale=False)
+    with pytest.raises(B.SiluError) as e:
+        server.register(pool[0]["Ad"], Fu)
+    assert e.value.status == -8
+    server.close()
