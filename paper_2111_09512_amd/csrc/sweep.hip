@@ -104,9 +104,35 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
     }
 }
 
+// Epilogue with its operands loaded up front: aux = x_i (UPDATE) or dinv_i
+// (SCALE, SCALE_UPDATE); aux2 = x_i (SCALE_UPDATE).
+template <class T>
+__device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typename T::AT t, double aux, double aux2)
+{
+    using IT = typename T::IT;
+    using OT = typename T::OT;
+    const IT v = (IT)t;
+    switch (a.epi) {
+    case EPI_STORE:
+        ((OT *)a.out)[row] = (OT)v;
+        break;
+    case EPI_SCALE:
+        ((OT *)a.out)[row] = (OT)(aux * (double)v);
+        break;
+    case EPI_UPDATE:
+        a.x[row] = aux + (double)v;
+        break;
+    default: // EPI_SCALE_UPDATE
+        a.x[row] = aux2 + (double)(OT)(aux * (double)v);
+        break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CSR-stream: RPB rows per workgroup of BLOCK lanes (RPB <= BLOCK); products
-// staged in LDS in chunks of CAP entries.
+// staged in LDS in chunks of CAP entries.  The lane of each row loads the
+// row's rhs and epilogue operands together with the row pointers, so those
+// loads overlap the block's stream instead of following it.
 // ---------------------------------------------------------------------------
 // With C16 the column of entry e is r0 + shift + off16[e] (block-relative
 // 16-bit offsets, built once per matrix when every offset fits): 2 bytes of
@@ -126,6 +152,16 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
     const int r0 = blk * RPB;
     const int nr = min(RPB, a.n - r0);
     const int tid = (int)threadIdx.x;
+    RT rhs_v = (RT)0;
+    double aux = 0.0, aux2 = 0.0, dsh = 1.0;
+    if (tid < nr) {
+        const int row = r0 + tid;
+        rhs_v = ((const RT *)a.rhs)[row];
+        if (a.epi == EPI_UPDATE) aux = a.x[row];
+        if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
+        if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+        if (a.dshift) dsh = a.dshift[row];
+    }
     for (int t = tid; t <= nr; t += BLOCK) srp[t] = a.rp[r0 + t];
     __syncthreads();
 
@@ -139,7 +175,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
     if (tid < nr) {
         mylo = srp[tid];
         myhi = srp[tid + 1];
-        if (a.dshift) sum = (AT)((a.dshift[r0 + tid] - 1.0) * (double)xin[r0 + tid]);
+        if (a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[r0 + tid]);
     }
     for (int c0 = e0; c0 < e1; c0 += CAP) {
         const int c1 = min(c0 + CAP, e1);
@@ -153,11 +189,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
         __syncthreads();
     }
-    if (tid < nr) {
-        const int row = r0 + tid;
-        const AT t = (AT)((const RT *)a.rhs)[row] - sum;
-        epilogue<T>(a, row, t);
-    }
+    if (tid < nr) epilogue_pre<T>(a, r0 + tid, (AT)rhs_v - sum, aux, aux2);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
@@ -446,7 +478,7 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     // default (and SILU_KERNEL_STREAM): CSR-stream; short rows fill a
     // workgroup with 256 of them, long rows take 64 so one LDS chunk holds them
     g.kind = SweepKernel::STREAM;
-    g.rows_per_block = mean <= 8.0 ? 256 : (mean <= 16.0 ? 128 : 64);
+    g.rows_per_block = (mean <= 8.0 || mean > 24.0) ? 256 : (mean <= 16.0 ? 128 : 64);
     g.allow16 = !(flags & 0x1000); // SILU_INDEX32 keeps 32-bit column indices
     return g;
 }

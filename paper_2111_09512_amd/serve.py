@@ -54,22 +54,31 @@ def build_pool(ctx: B.Context, sides, density_seed0: int = 5):
     return mats
 
 
-def make_requests(mats, rhs_per_matrix: int = 20, rate: float = 2000.0, seed: int = 50, m: int = 3,
-                  max_outer: int = 4):
-    """All requests with their vectors resident on the device, in arrival order."""
+def request_plan(n_mat: int, rhs_per_matrix: int = 20, rate: float = 2000.0, seed: int = 50, max_outer: int = 4):
+    """The seeded request stream: (matrix id, rhs seed, outer steps, arrival time in s), in
+    arrival order.  Shuffled (matrix, rhs) pairs; exponential gaps of mean 1/rate."""
     rng = np.random.default_rng(seed)
-    order = [(mid, k) for mid in range(len(mats)) for k in range(rhs_per_matrix)]
+    order = [(mid, k) for mid in range(n_mat) for k in range(rhs_per_matrix)]
     perm = rng.permutation(len(order))
     gaps = rng.exponential(1.0 / rate, size=len(order))
     outers = rng.integers(1, max_outer + 1, size=len(order))
     t = np.cumsum(gaps)
-    reqs = []
+    plan = []
     for i, p in enumerate(perm):
         mid, k = order[p]
+        plan.append((mid, 1000 * mid + k, int(outers[i]), float(t[i])))
+    return plan
+
+
+def make_requests(mats, rhs_per_matrix: int = 20, rate: float = 2000.0, seed: int = 50, m: int = 3,
+                  max_outer: int = 4):
+    """All requests of the plan with their vectors resident on the device."""
+    reqs = []
+    for mid, bseed, outer, t in request_plan(len(mats), rhs_per_matrix, rate, seed, max_outer):
         n = mats[mid][2]
-        b = torch.from_numpy(W.rhs(n, 1000 * mid + k)).cuda()
+        b = torch.from_numpy(W.rhs(n, bseed)).cuda()
         x = torch.zeros(n, dtype=torch.float64, device="cuda")
-        reqs.append(Request(mid, b, x, int(outers[i]), m, m, float(t[i])))
+        reqs.append(Request(mid, b, x, outer, m, m, t))
     return reqs
 
 
