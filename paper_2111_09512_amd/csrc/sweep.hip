@@ -477,8 +477,10 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     }
     // default (and SILU_KERNEL_STREAM): CSR-stream; short rows fill a
     // workgroup with 256 of them, long rows take 64 so one LDS chunk holds them
+    // FP64 factor rows of 9-24 entries stream best 64-128 rows at a time;
+    // short rows, long rows and the FP32-value sweeps (SILU_MIXED) with 256
     g.kind = SweepKernel::STREAM;
-    g.rows_per_block = (mean <= 8.0 || mean > 24.0) ? 256 : (mean <= 16.0 ? 128 : 64);
+    g.rows_per_block = (mean <= 8.0 || mean > 24.0 || (flags & 0x2)) ? 256 : (mean <= 16.0 ? 128 : 64);
     g.allow16 = !(flags & 0x1000); // SILU_INDEX32 keeps 32-bit column indices
     return g;
 }
