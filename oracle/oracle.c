@@ -480,6 +480,81 @@ int orc_scale_rows(int n, const int *Urp, const int *Ucol, const double *Uval,
     return ORC_OK;
 }
 
+/* =========================================================================
+ * Row/column scaling of the U factor (Section 5.1, eq. rowcolScale:
+ * L D_r U D_c x = b, the Richardson iteration running on D_r U D_c, which
+ * has a unit diagonal).  The paper names Ruiz scaling (Table 2) without a
+ * formula; the reading here: `iters` Ruiz steps on U in the max norm,
+ *   r_i = 1/sqrt(max_j |u^_ij|), c_j = 1/sqrt(max_i |u^_ij|),
+ *   d_r <- d_r * r, d_c <- d_c * c, with u^_ij = (|u_ij| * d_r,i) * d_c,j,
+ * starting from d_r = d_c = 1; then the row factor is replaced so that the
+ * diagonal is exactly the unit one the paper requires, d_r,i = 1/(u_ii d_c,i),
+ * and the strictly upper part of U^ = D_r U D_c is written,
+ * u^_ij = (u_ij * d_r,i) * d_c,j.  Us_rp/col/val as in orc_scale_rows.
+ * dr_ruiz (optional, may be NULL) receives the row factors before the
+ * unit-diagonal step.
+ * ========================================================================= */
+int orc_scale_rowcol(int n, const int *Urp, const int *Ucol, const double *Uval, int iters,
+                     double *dr, double *dc, double *dr_ruiz, int *Us_rp, int *Us_col, double *Us_val,
+                     int *bad_row)
+{
+    double *cm = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *r = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    *bad_row = -1;
+    if (!cm || !r) {
+        free(cm);
+        free(r);
+        return ORC_NOMEM;
+    }
+    for (int i = 0; i < n; i++) {
+        if (Urp[i + 1] <= Urp[i] || Ucol[Urp[i]] != i) {
+            *bad_row = i;
+            free(cm);
+            free(r);
+            return ORC_PATTERN;
+        }
+        double uii = Uval[Urp[i]];
+        if (uii == 0.0 || !isfinite(uii)) {
+            *bad_row = i;
+            free(cm);
+            free(r);
+            return ORC_ZERO_PIVOT;
+        }
+        dr[i] = 1.0;
+        dc[i] = 1.0;
+    }
+    for (int it = 0; it < iters; it++) {
+        for (int j = 0; j < n; j++) cm[j] = 0.0;
+        for (int i = 0; i < n; i++) {
+            double rm = 0.0;
+            for (int p = Urp[i]; p < Urp[i + 1]; p++) {
+                double a = (fabs(Uval[p]) * dr[i]) * dc[Ucol[p]];
+                if (a > rm) rm = a;
+                if (a > cm[Ucol[p]]) cm[Ucol[p]] = a;
+            }
+            r[i] = 1.0 / sqrt(rm);
+        }
+        for (int i = 0; i < n; i++) dr[i] = dr[i] * r[i];
+        for (int j = 0; j < n; j++) dc[j] = dc[j] * (1.0 / sqrt(cm[j]));
+    }
+    if (dr_ruiz)
+        for (int i = 0; i < n; i++) dr_ruiz[i] = dr[i];
+    long long o = 0;
+    Us_rp[0] = 0;
+    for (int i = 0; i < n; i++) {
+        dr[i] = 1.0 / (Uval[Urp[i]] * dc[i]);
+        for (int p = Urp[i] + 1; p < Urp[i + 1]; p++) {
+            Us_col[o] = Ucol[p];
+            Us_val[o] = (Uval[p] * dr[i]) * dc[Ucol[p]];
+            o++;
+        }
+        Us_rp[i + 1] = (int)o;
+    }
+    free(cm);
+    free(r);
+    return ORC_OK;
+}
+
 /* y = N x, each row summed from 0.0 in ascending column order. */
 void orc_spmv(int n, const int *rp, const int *col, const double *val, const double *x, double *y)
 {
@@ -663,6 +738,48 @@ void orc_smooth_mixed(int n, const int *Arp, const int *Acol, const double *Aval
         for (int i = 0; i < n; i++) rf[i] = (float)(dinv[i] * (double)y[i]);
         orc_richardson_f32(n, Urp, Ucol, Uval, rf, mU, z, tmp);
         for (int i = 0; i < n; i++) x[i] = x[i] + (double)z[i];
+    }
+}
+
+/* =========================================================================
+ * The smoother with row/column-scaled U (eq. rowcolScale): U z = y is solved
+ * as U^ v = D_r y, z = D_c v, on U^ = D_r U D_c (unit diagonal; Us holds its
+ * strict upper part):
+ *   r = b - A x;  y = m_L steps on L y = r;  s = d_r * y;
+ *   v = m_U steps on U^ v = s;  x = x + d_c * v.
+ * mode 0: FP64 Richardson.  mode 1: the two Richardson loops in FP32 as in
+ * orc_smooth_mixed, s = (float)(d_r * (double)y), x = x + d_c * (double)v.
+ * mode 2: both solves by substitution.
+ * ws: 5n doubles; fws: 4n floats (mode 1 only, else may be NULL).
+ * ========================================================================= */
+void orc_smooth_rowcol(int n, const int *Arp, const int *Acol, const double *Aval,
+                       const int *Lrp, const int *Lcol, const double *Lval,
+                       const int *Urp, const int *Ucol, const double *Uval, const double *dr, const double *dc,
+                       const double *b, double *x, int outer, int mL, int mU, int mode, double *ws, float *fws)
+{
+    double *r = ws, *y = ws + n, *s = ws + 2 * (size_t)n, *v = ws + 3 * (size_t)n, *tmp = ws + 4 * (size_t)n;
+    int bad;
+    for (int it = 0; it < outer; it++) {
+        orc_residual(n, Arp, Acol, Aval, b, x, r);
+        if (mode == 1) {
+            float *rf = fws, *yf = fws + n, *vf = fws + 2 * (size_t)n, *tf = fws + 3 * (size_t)n;
+            for (int i = 0; i < n; i++) rf[i] = (float)r[i];
+            orc_richardson_f32(n, Lrp, Lcol, Lval, rf, mL, yf, tf);
+            for (int i = 0; i < n; i++) rf[i] = (float)(dr[i] * (double)yf[i]);
+            orc_richardson_f32(n, Urp, Ucol, Uval, rf, mU, vf, tf);
+            for (int i = 0; i < n; i++) x[i] = x[i] + dc[i] * (double)vf[i];
+            continue;
+        }
+        if (mode == 2)
+            orc_trisolve(n, Lrp, Lcol, Lval, 0, 1, r, y, &bad);
+        else
+            orc_richardson(n, Lrp, Lcol, Lval, r, mL, y, tmp);
+        for (int i = 0; i < n; i++) s[i] = dr[i] * y[i];
+        if (mode == 2)
+            orc_trisolve(n, Urp, Ucol, Uval, 1, 1, s, v, &bad);
+        else
+            orc_richardson(n, Urp, Ucol, Uval, s, mU, v, tmp);
+        for (int i = 0; i < n; i++) x[i] = x[i] + dc[i] * v[i];
     }
 }
 

@@ -58,6 +58,12 @@ def lib():
                                C.POINTER(_OrcCSR), C.POINTER(C.c_int)]
         L.orc_scale_rows.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _i32p, _i32p, _f64p,
                                      C.POINTER(C.c_int)]
+        L.orc_scale_rowcol.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p, _f64p, _i32p, _i32p,
+                                       _f64p, C.POINTER(C.c_int)]
+        L.orc_smooth_rowcol.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p,
+                                        _f64p, _f64p, _f64p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, _f64p,
+                                        _f32p]
+        L.orc_smooth_rowcol.restype = None
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_spmv.restype = None
         L.orc_residual.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
@@ -193,6 +199,43 @@ def scale_rows(U):
     if st:
         raise OracleError(st, bad.value, "row scaling")
     return d, dinv, Mat(n, rp, col, val)
+
+
+def scale_rowcol(U, iters: int = 5):
+    """Row/column scaling U^ = D_r U D_c with a unit diagonal (Section 5.1, eq.
+    rowcolScale; Ruiz steps in the max norm, then d_r,i = 1/(u_ii d_c,i)).
+    Returns (dr, dc, Us_hat, dr_before_unit_diagonal)."""
+    U = _mat(U)
+    n = U.n
+    nnz = U.nnz - n
+    dr = np.empty(n)
+    dc = np.empty(n)
+    drr = np.empty(n)
+    rp = np.empty(n + 1, np.int32)
+    col = np.empty(max(nnz, 0), np.int32)
+    val = np.empty(max(nnz, 0))
+    bad = C.c_int(-1)
+    st = lib().orc_scale_rowcol(n, U.row_ptr, U.col, U.val, int(iters), dr, dc, drr, rp, col, val, C.byref(bad))
+    if st:
+        raise OracleError(st, bad.value, "row/column scaling")
+    return dr, dc, Mat(n, rp, col, val), drr
+
+
+def smooth_rowcol(A, Ls, Us_hat, dr, dc, b, x0, outer: int, mL: int, mU: int, mixed: bool = False,
+                  direct: bool = False):
+    """Smoother with the row/column-scaled U (eq. rowcolScale): s = d_r * y,
+    m_U steps on U^ v = s, x += d_c * v.  mixed: FP32 Richardson loops;
+    direct: both solves by substitution."""
+    A, Ls, Us_hat = _mat(A), _mat(Ls), _mat(Us_hat)
+    n = A.n
+    x = np.array(x0, dtype=np.float64, copy=True)
+    ws = np.empty(5 * n)
+    fws = np.empty(4 * n, np.float32)
+    mode = 2 if direct else (1 if mixed else 0)
+    lib().orc_smooth_rowcol(n, A.row_ptr, A.col, A.val, Ls.row_ptr, Ls.col, Ls.val, Us_hat.row_ptr, Us_hat.col,
+                            Us_hat.val, np.ascontiguousarray(dr, np.float64), np.ascontiguousarray(dc, np.float64),
+                            np.ascontiguousarray(b, np.float64), x, int(outer), int(mL), int(mU), mode, ws, fws)
+    return x
 
 
 def spmv(N, x):
