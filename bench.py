@@ -9,7 +9,8 @@ fused D^{-1}, U sweeps with fused x update, twice).  `value` is FP64 smoother
 applications per second with every input resident in HBM.  In the same run,
 and reported in the same JSON line: the level-scheduled direct form (the same
 smoother with both triangular solves done by level-set substitution), the
-FP32-inner mixed form, a streaming-copy bandwidth calibration, the roofline of
+FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, a
+streaming-copy bandwidth calibration, the roofline of
 the dominant kernel from per-launch HIP events, and the CPU oracle timed on a
 bounded sample of the same operator, and the serving stream (1,280 requests
 on 64 resident matrices, continuous batching vs one at a time).
@@ -152,6 +153,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-rowcol", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -237,6 +239,22 @@ def main():
     mixed_err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
     log(f"mixed: rel diff vs FP64 GPU {mixed_err:.2e}")
 
+    # ---- row/column (Ruiz) scaled factors: same sweeps, column factor in the last update ----
+    rowcol = None
+    if not args.no_rowcol:
+        Frc = ctx.ilu_scale_factors_rowcol(Ld, Ud, 5)
+
+        def app_rowcol():
+            x.zero_()
+            ctx.ilu_smooth(Ad, Frc, bvec, x, outer, mL, mU, kernel=kern, ws=ws)
+
+        ms_rc, bytes_rc, _ = timed(app_rowcol, "rowcol")
+        rc_err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        log(f"rowcol: rel diff vs row-scaled FP64 {rc_err:.2e}")
+        rowcol = {"apps_per_s": 1e3 / ms_rc, "ms": ms_rc, "GBps": bytes_rc / (ms_rc * 1e-3) / 1e9,
+                  "bytes_per_app": bytes_rc, "ruiz_iters": 5, "rel_diff_vs_row_scaling": rc_err}
+        del Frc
+
     # ---- direct (level-scheduled) form ----
     ms_direct = None
     depths = None
@@ -293,6 +311,7 @@ def main():
         "mixed_GBps": bytes_mixed / (ms_mixed * 1e-3) / 1e9,
         "mixed_bytes_per_app": bytes_mixed,
         "mixed_rel_diff_vs_f64": mixed_err,
+        "rowcol": rowcol,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,

@@ -88,11 +88,17 @@ typedef struct {
  *            ilu_scale_factors into caller-allocated arrays: row_ptr [n+1],
  *            col_idx and val [nnz(U) - n].  With SILU_NO_SCALING, Us holds
  *            the strictly upper part of U itself.
+ *            After ilu_scale_factors_rowcol, Us holds the strictly upper part
+ *            of U^ = D_r U D_c (eq. rowcolScale) instead.
  *   d        diag(U) [n] (eq. extractD)
- *   dinv     1 / diag(U) [n]
+ *   dinv     the row factor applied to y before the U solve [n]:
+ *            1 / diag(U) after row scaling, d_r after row/column scaling
  *   Ls_val32 optional FP32 copy of Ls.val (round to nearest even), or NULL
  *   Us_val32 optional FP32 copy of Us.val, or NULL
- *   scaled   1 after row scaling, 0 with SILU_NO_SCALING
+ *   scaled   1 after row scaling, 0 with SILU_NO_SCALING, 2 after
+ *            row/column scaling
+ *   dc       column factors d_c [n] (scaled == 2: the smoother adds d_c * v
+ *            to x, v the U^ iterate), else ignored (may be NULL)
  */
 typedef struct {
     silu_csr Ls;
@@ -102,6 +108,7 @@ typedef struct {
     float *Ls_val32;
     float *Us_val32;
     int32_t scaled;
+    double *dc;
 } silu_factors;
 
 typedef struct silu_ctx silu_ctx;
@@ -147,6 +154,31 @@ int silu_workspace_size(silu_ctx *ctx, int64_t n, int flags, size_t *bytes);
  */
 int ilu_scale_factors(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags);
 
+/* ---- setup: row/column scaling (Section 5.1, eq. rowcolScale) ------------ */
+
+/*
+ * The paper's second scaling: the Richardson loop on U runs on
+ * U^ = D_r U D_c, which has a unit diagonal, and U z = y is solved as
+ * U^ v = D_r y, z = D_c v.  The paper names Ruiz scaling (Table 2) without
+ * further detail; this library's reading:
+ *   d_r = d_c = 1; then `ruiz_iters` times, with a_ij = (|u_ij| d_r,i) d_c,j,
+ *     d_r,i *= 1/sqrt(max_j a_ij),  d_c,j *= 1/sqrt(max_i a_ij)
+ *   (both maxima of a step from the same a); finally the unit diagonal fixes
+ *   the row factor, d_r,i = 1/(u_ii d_c,i), and u^_ij = (u_ij d_r,i) d_c,j.
+ * So U^ = D_c^{-1} (D^{-1} U) D_c: a diagonal similarity of the row-scaled
+ * factor, with the same truncated Neumann sums in exact arithmetic and a
+ * different departure from normality (eq. depB).
+ * Same arguments and ownership as ilu_scale_factors, plus F->dc [n] (caller
+ * allocated); writes F->Us (values of U^), F->d = diag(U), F->dinv = d_r,
+ * F->dc = d_c, F->scaled = 2, and the optional FP32 copies.
+ * ruiz_iters in [0, 100] (0: d_c = 1, which is the row scaling up to
+ * rounding).  Allocates 16 n bytes of temporary device memory for the call.
+ * Synchronous.  Errors: as ilu_scale_factors, and ARG for ruiz_iters out of
+ * range or F->dc == NULL; PATTERN also for a column index outside [0, n).
+ */
+int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, int ruiz_iters, silu_factors *F,
+                             int flags);
+
 /* ---- the smoother (eq. ILUsplit, Algorithm 2, eq. richard) -------------- */
 
 /*
@@ -161,6 +193,8 @@ int ilu_scale_factors(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, silu_
  * preconditioner application):
  *   r = b - A x;  y = m_L Richardson steps on L y = r from y = 0;
  *   s = D^{-1} y;  z = m_U Richardson steps on U~ z = s from z = 0;  x += z.
+ * With row/column-scaled factors (F->scaled == 2): s = d_r * y, v = m_U
+ * steps on U^ v = s, x += d_c * v (and with SILU_MIXED, x += d_c * (double)v).
  * A: n x n FP64 CSR.  F: from ilu_scale_factors.  b, x: FP64 [n].
  * flags: SILU_DIRECT replaces both Richardson loops by level-scheduled
  * substitution (m_L, m_U ignored); SILU_MIXED runs the two Richardson loops on
@@ -171,8 +205,8 @@ int ilu_scale_factors(silu_ctx *ctx, const silu_csr *L, const silu_csr *U, silu_
  * unscaled Richardson iteration z <- y - (U - I) z (FP64 only).
  * ws: workspace of at least silu_workspace_size(ctx, n, flags) bytes.
  * Asynchronous on the context stream (unless CHECK_FINITE / VALIDATE).
- * Errors: ARG (null, outer_sweeps < 1, m_L < 1 or m_U < 1 in ITER mode),
- * SHAPE, NOMEM (ws_bytes too small), UNSUPPORTED (MIXED without FP32 copies,
+ * Errors: ARG (null, outer_sweeps < 1, m_L < 1 or m_U < 1 in ITER mode,
+ * F->scaled == 2 without F->dc), SHAPE, NOMEM (ws_bytes too small), UNSUPPORTED (MIXED without FP32 copies,
  * MIXED or DIRECT with unscaled factors), PATTERN (with VALIDATE), NONFINITE,
  * HIP.
  */
@@ -270,8 +304,9 @@ int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
  * arena: device memory owned by the caller, 256-byte aligned, alive until
  * silu_server_destroy.  b and x of a request: device FP64 [n], alive until
  * poll reports it done; x is the initial guess and receives the result.
- * m_L, m_U >= 1 but not both 1.  Errors: ARG, SHAPE, UNSUPPORTED (unscaled
- * or non-FP64 factors), NOMEM (one request alone exceeds the arena), HIP
+ * m_L, m_U >= 1 but not both 1.  Row-scaled and row/column-scaled factors
+ * are both served.  Errors: ARG, SHAPE, UNSUPPORTED (unscaled or non-FP64
+ * factors), NOMEM (one request alone exceeds the arena), HIP
  * (silu_server_last_hip_error).  A server is used by one host thread.
  */
 typedef struct silu_server silu_server;

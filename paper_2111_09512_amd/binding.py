@@ -53,7 +53,7 @@ class silu_csr(C.Structure):
 class silu_factors(C.Structure):
     _fields_ = [
         ("Ls", silu_csr), ("Us", silu_csr), ("d", C.c_void_p), ("dinv", C.c_void_p),
-        ("Ls_val32", C.c_void_p), ("Us_val32", C.c_void_p), ("scaled", C.c_int32),
+        ("Ls_val32", C.c_void_p), ("Us_val32", C.c_void_p), ("scaled", C.c_int32), ("dc", C.c_void_p),
     ]
 
 
@@ -74,6 +74,8 @@ _sig = {
     "silu_status_string": (C.c_char_p, [C.c_int]),
     "silu_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int, C.POINTER(C.c_size_t)]),
     "ilu_scale_factors": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
+    "ilu_scale_factors_rowcol": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_csr), C.c_int,
+                                           C.POINTER(silu_factors), C.c_int]),
     "ilu_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int,
                              _P, C.c_size_t]),
     "ilu_smooth2": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
@@ -172,15 +174,16 @@ class Factors:
     dinv: torch.Tensor
     Ls_val32: torch.Tensor | None
     Us_val32: torch.Tensor | None
-    scaled: bool
+    scaled: int  # 0 unscaled, 1 row scaling, 2 row/column scaling
+    dc: torch.Tensor | None = None  # column factors (scaled == 2)
 
     def c(self) -> silu_factors:
         return silu_factors(self.Ls.c(), self.Us.c(), _ptr(self.d), _ptr(self.dinv), _ptr(self.Ls_val32),
-                            _ptr(self.Us_val32), 1 if self.scaled else 0)
+                            _ptr(self.Us_val32), int(self.scaled), _ptr(self.dc))
 
     def nbytes(self) -> int:
         ts = [self.Ls.row_ptr, self.Ls.col_idx, self.Ls.val, self.Us.row_ptr, self.Us.col_idx, self.Us.val, self.d,
-              self.dinv, self.Ls_val32, self.Us_val32]
+              self.dinv, self.Ls_val32, self.Us_val32, self.dc]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
@@ -239,8 +242,8 @@ class Context:
         return self._ws
 
     # ---- setup ----
-    def ilu_scale_factors(self, L: Csr, U: Csr, fp32: bool = False, scale: bool = True,
-                          validate: bool = False) -> Factors:
+    @staticmethod
+    def _alloc_factors(L: Csr, U: Csr, fp32: bool, scaled: int) -> tuple[Factors, silu_factors]:
         n = U.n
         nnz_s = U.nnz - n
         dev = U.val.device
@@ -250,13 +253,28 @@ class Context:
         F = Factors(L, Us, torch.empty(n, dtype=torch.float64, device=dev),
                     torch.empty(n, dtype=torch.float64, device=dev),
                     torch.empty(L.nnz, dtype=torch.float32, device=dev) if fp32 else None,
-                    torch.empty(max(nnz_s, 0), dtype=torch.float32, device=dev) if fp32 else None, scale)
+                    torch.empty(max(nnz_s, 0), dtype=torch.float32, device=dev) if fp32 else None, scaled,
+                    torch.empty(n, dtype=torch.float64, device=dev) if scaled == 2 else None)
         Fc = F.c()
         Fc.Us = silu_csr(n, n, max(nnz_s, 0), Us.row_ptr.data_ptr(), _ptr(Us.col_idx) if nnz_s else None,
                          _ptr(Us.val) if nnz_s else None, SILU_F64)
+        return F, Fc
+
+    def ilu_scale_factors(self, L: Csr, U: Csr, fp32: bool = False, scale: bool = True,
+                          validate: bool = False) -> Factors:
+        F, Fc = self._alloc_factors(L, U, fp32, 1 if scale else 0)
         flags = (0 if scale else SILU_NO_SCALING) | (SILU_VALIDATE if validate else 0)
         Lc, Uc = L.c(), U.c()
         self._check(_lib.ilu_scale_factors(self._h, C.byref(Lc), C.byref(Uc), C.byref(Fc), flags), "ilu_scale_factors")
+        return F
+
+    def ilu_scale_factors_rowcol(self, L: Csr, U: Csr, ruiz_iters: int = 5, fp32: bool = False,
+                                 validate: bool = False) -> Factors:
+        """Row/column scaling U^ = D_r U D_c with a unit diagonal (F.dinv = d_r, F.dc = d_c)."""
+        F, Fc = self._alloc_factors(L, U, fp32, 2)
+        Lc, Uc = L.c(), U.c()
+        self._check(_lib.ilu_scale_factors_rowcol(self._h, C.byref(Lc), C.byref(Uc), int(ruiz_iters), C.byref(Fc),
+                                                  SILU_VALIDATE if validate else 0), "ilu_scale_factors_rowcol")
         return F
 
     # ---- the smoother ----

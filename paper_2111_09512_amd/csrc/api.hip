@@ -50,7 +50,7 @@ using CompKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
 
 // A captured level sequence: one kernel node per level.
 using GraphKey = std::tuple<const void *, const void *, const void *, const void *, const void *, const void *,
-                            const void *, const void *, const void *, int>;
+                            const void *, const void *, const void *, const void *, int>;
 
 struct Pending {
     int kid;
@@ -281,7 +281,8 @@ int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, Compressed **out)
 }
 
 int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
-          const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift)
+          const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift,
+          const double *dcol = nullptr)
 {
     if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
         Compressed *C = nullptr;
@@ -311,7 +312,10 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     a.dinv = dinv;
     a.x = x;
     a.dshift = dshift;
-    const double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, g.off16 ? 2.0 : 4.0);
+    const bool upd = epi == EPI_UPDATE || epi == EPI_SCALE_UPDATE;
+    a.dcol = upd ? dcol : nullptr;
+    double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, g.off16 ? 2.0 : 4.0);
+    if (a.dcol) bytes += 8.0 * (double)N->n_rows;
     return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
 
@@ -388,8 +392,9 @@ hipError_t enqueue_levels(const LevelArgs &a, const LevelInfo *li, int unit, hip
 }
 
 int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const double *rhs, double *out,
-               const double *dinv, double *s_out, double *xupd, bool graph)
+               const double *dinv, double *s_out, double *xupd, bool graph, const double *dcol = nullptr)
 {
+    const double xb = dcol ? 24.0 : 16.0; // bytes per row of the x update
     if (graph && li->depth > 1) {
         LevelArgs a;
         a.perm = li->d_perm;
@@ -401,7 +406,8 @@ int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const do
         a.dinv = dinv;
         a.s_out = s_out;
         a.xupd = xupd;
-        GraphKey key{li, T->row_ptr, T->col_idx, T->val, rhs, out, dinv, s_out, xupd, unit};
+        a.dcol = dcol;
+        GraphKey key{li, T->row_ptr, T->col_idx, T->val, rhs, out, dinv, s_out, xupd, dcol, unit};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
@@ -424,7 +430,7 @@ int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const do
             const int count = li->level_ptr[(size_t)l + 1] - li->level_ptr[(size_t)l];
             bytes += count * (4.0 + 8.0 + 8.0 + 8.0 + 8.0) + 12.0 * (double)li->level_nnz[(size_t)l];
             if (s_out) bytes += count * 16.0;
-            if (xupd) bytes += count * 16.0;
+            if (xupd) bytes += count * xb;
         }
         hipGraphExec_t ex = it->second;
         return timed_launch(c, bytes, [&](const char **nm) {
@@ -442,11 +448,12 @@ int run_levels(silu_ctx *c, const silu_csr *T, LevelInfo *li, int unit, const do
     a.dinv = dinv;
     a.s_out = s_out;
     a.xupd = xupd;
+    a.dcol = dcol;
     for (int l = 0; l < li->depth; l++) {
         const int start = li->level_ptr[(size_t)l], count = li->level_ptr[(size_t)l + 1] - start;
         double bytes = count * (4.0 + 8.0 + 8.0 + 8.0 + 8.0) + 12.0 * (double)li->level_nnz[(size_t)l];
         if (s_out) bytes += count * 16.0;
-        if (xupd) bytes += count * 16.0;
+        if (xupd) bytes += count * xb;
         int st = timed_launch(c, bytes, [&](const char **nm) {
             return launch_level(a, unit, li->lanes, start, count, c->stream, nm);
         });
@@ -544,9 +551,14 @@ int silu_workspace_size(silu_ctx *c, int64_t n, int flags, size_t *bytes)
     return SILU_OK;
 }
 
-int ilu_scale_factors(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags)
+namespace {
+
+// Shared part of both scalings: argument checks, then k_scale_rows (pattern
+// and pivot checks into the device flags, Us pattern, d, dinv and the row-
+// scaled or copied values) and the FP32 copy of L.  Asynchronous.
+int scale_begin(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags, bool noscale,
+                float *us32)
 {
-    if (!c || !L || !U || !F) return SILU_ERR_ARG;
     c->bad_row = -1;
     int st = check_square(U, SILU_F64);
     if (st) return st;
@@ -561,17 +573,21 @@ int ilu_scale_factors(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_fa
         if ((st = validate(c, L, -1))) return st;
         if ((st = validate(c, U, 2))) return st;
     }
-    const bool noscale = (flags & SILU_NO_SCALING) != 0;
     F->Ls = *L;
     F->Us.n_rows = F->Us.n_cols = n;
     F->Us.nnz = U->nnz - n;
     F->Us.dtype = SILU_F64;
-    F->scaled = noscale ? 0 : 1;
     HIPCHK(c, launch_init_flags(c->d_flags, 4, INT32_MAX, c->stream));
     HIPCHK(c, launch_scale_rows((int)n, U->row_ptr, U->col_idx, (const double *)U->val, F->Us.row_ptr,
-                                F->Us.col_idx, (double *)F->Us.val, F->d, F->dinv, F->Us_val32, noscale ? 1 : 0,
+                                F->Us.col_idx, (double *)F->Us.val, F->d, F->dinv, us32, noscale ? 1 : 0,
                                 (int32_t)(U->nnz - n), c->d_flags, c->stream));
     if (F->Ls_val32) HIPCHK(c, launch_to_f32(L->nnz, (const double *)L->val, F->Ls_val32, c->stream));
+    return SILU_OK;
+}
+
+// Wait for the set-up and turn the device flags into a status.
+int scale_end(silu_ctx *c)
+{
     int32_t h[4];
     HIPCHK(c, hipMemcpyAsync(h, c->d_flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -584,6 +600,51 @@ int ilu_scale_factors(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_fa
         return SILU_ERR_ZERO_PIVOT;
     }
     return SILU_OK;
+}
+
+} // namespace
+
+int ilu_scale_factors(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_factors *F, int flags)
+{
+    if (!c || !L || !U || !F) return SILU_ERR_ARG;
+    const bool noscale = (flags & SILU_NO_SCALING) != 0;
+    int st = scale_begin(c, L, U, F, flags, noscale, F->Us_val32);
+    if (st) return st;
+    F->scaled = noscale ? 0 : 1;
+    return scale_end(c);
+}
+
+int ilu_scale_factors_rowcol(silu_ctx *c, const silu_csr *L, const silu_csr *U, int ruiz_iters, silu_factors *F,
+                             int flags)
+{
+    if (!c || !L || !U || !F || !F->dc || ruiz_iters < 0 || ruiz_iters > 100 || (flags & SILU_NO_SCALING))
+        return SILU_ERR_ARG;
+    int st = scale_begin(c, L, U, F, flags, false, nullptr);
+    if (st) return st;
+    F->scaled = 2;
+    const int n = (int)U->n_rows;
+    if (n == 0) return scale_end(c);
+    // row maxima [n] doubles, then column maxima [n] as 64-bit patterns
+    void *tmp = nullptr;
+    HIPCHK(c, hipMalloc(&tmp, (size_t)n * 16));
+    double *rmax = (double *)tmp;
+    unsigned long long *cmax = (unsigned long long *)((char *)tmp + (size_t)n * 8);
+    const int32_t *Urp = U->row_ptr, *Ucol = U->col_idx;
+    const double *Uval = (const double *)U->val;
+    hipError_t e = launch_fill(n, F->dinv, 1.0, F->dc, 1.0, c->stream);
+    for (int it = 0; it < ruiz_iters && e == hipSuccess; it++) {
+        e = launch_fill(n, (double *)cmax, 0.0, nullptr, 0.0, c->stream); // +0.0 has the all-zero pattern
+        if (e == hipSuccess) e = launch_ruiz_max(n, Urp, Ucol, Uval, F->dinv, F->dc, rmax, cmax, c->d_flags, c->stream);
+        if (e == hipSuccess) e = launch_ruiz_scale(n, F->dinv, F->dc, rmax, cmax, c->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_rowcol_finish(n, Urp, Ucol, Uval, F->dc, F->dinv, (double *)F->Us.val, F->Us_val32,
+                                 (int32_t)(U->nnz - n), c->stream);
+    st = e == hipSuccess ? scale_end(c) : hip_fail(c, e);
+    if (e != hipSuccess) (void)hipStreamSynchronize(c->stream); // nothing may still use tmp
+    hipError_t ef = hipFree(tmp);
+    if (st == SILU_OK && ef != hipSuccess) st = hip_fail(c, ef);
+    return st;
 }
 
 int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
@@ -599,7 +660,7 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     if ((st = check_square(&F->Us, SILU_F64))) return st;
     const int64_t n = A->n_rows;
     if (F->Ls.n_rows != n || F->Us.n_rows != n) return SILU_ERR_SHAPE;
-    if (!F->dinv || (!F->scaled && !F->d)) return SILU_ERR_ARG;
+    if (!F->dinv || (!F->scaled && !F->d) || (F->scaled == 2 && !F->dc)) return SILU_ERR_ARG;
     if (mixed && ((F->Ls.nnz > 0 && !F->Ls_val32) || (F->Us.nnz > 0 && !F->Us_val32))) return SILU_ERR_UNSUPPORTED;
     if (!F->scaled && (mixed || direct)) return SILU_ERR_UNSUPPORTED;
     if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
@@ -616,6 +677,7 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     const SweepGeom gA = pick_geom(n, A->nnz, flags), gL = pick_geom(n, F->Ls.nnz, flags),
                     gU = pick_geom(n, F->Us.nnz, flags);
     const bool scaled = F->scaled != 0;
+    const double *dcol = F->scaled == 2 ? F->dc : nullptr; // row/column scaling: x += d_c * v
     const double *dshift = scaled ? nullptr : F->d;
     const Prec pL = mixed ? Prec::MIX_L : Prec::F64, pU = mixed ? Prec::MIX_U : Prec::F64;
     const void *Lval = mixed ? (const void *)F->Ls_val32 : F->Ls.val;
@@ -633,7 +695,8 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             if ((st = run_levels(c, &F->Ls, lL, 1, (const double *)r, (double *)tmp[0], F->dinv, (double *)s,
                                  nullptr, graph)))
                 return st;
-            if ((st = run_levels(c, &F->Us, lU, 1, (const double *)s, (double *)tmp[1], nullptr, nullptr, x, graph)))
+            if ((st = run_levels(c, &F->Us, lU, 1, (const double *)s, (double *)tmp[1], nullptr, nullptr, x, graph,
+                                 dcol)))
                 return st;
             continue;
         }
@@ -648,9 +711,9 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
         }
         if (st) return st;
         if (m_L == 1 && m_U == 1) {
-            st = timed_launch(c, 24.0 * (double)n, [&](const char **nm) {
+            st = timed_launch(c, (dcol ? 32.0 : 24.0) * (double)n, [&](const char **nm) {
                 *nm = "axpy";
-                return launch_axpy((int)n, s, mixed ? 1 : 0, x, c->stream);
+                return launch_axpy((int)n, s, mixed ? 1 : 0, dcol, x, c->stream);
             });
             if (st) return st;
             continue;
@@ -664,7 +727,7 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             // in the mixed form y_1 = (float) r is never stored: the first sweep gathers r and rounds it
             const Prec p = (mixed && k == 2) ? Prec::MIX_L1 : pL;
             st = sweep(c, p, gL, &F->Ls, Lval, cur, r, epi, (epi == EPI_SCALE || epi == EPI_STORE) ? out : nullptr,
-                       F->dinv, x, nullptr);
+                       F->dinv, x, nullptr, dcol);
             if (st) return st;
             cur = out;
         }
@@ -673,7 +736,8 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
         for (int k = 2; k <= m_U; k++) {
             const bool last = k == m_U;
             void *out = last ? nullptr : tmp[k & 1];
-            st = sweep(c, pU, gU, &F->Us, Uval, cur, s, last ? EPI_UPDATE : EPI_STORE, out, F->dinv, x, dshift);
+            st = sweep(c, pU, gU, &F->Us, Uval, cur, s, last ? EPI_UPDATE : EPI_STORE, out, F->dinv, x, dshift,
+                       dcol);
             if (st) return st;
             cur = out;
         }

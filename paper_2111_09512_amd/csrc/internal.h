@@ -13,9 +13,11 @@ namespace silu {
 enum Epi : int {
     EPI_STORE = 0,        // out_i = t_i
     EPI_SCALE = 1,        // out_i = dinv_i * t_i                  (s = D^{-1} y)
-    EPI_UPDATE = 2,       // x_i = x_i + t_i                       (x += z)
-    EPI_SCALE_UPDATE = 3  // x_i = x_i + (OT)(dinv_i * t_i)        (x += D^{-1} y when m_U = 1)
+    EPI_UPDATE = 2,       // x_i = x_i + c_i * t_i                 (x += z)
+    EPI_SCALE_UPDATE = 3  // x_i = x_i + c_i * (OT)(dinv_i * t_i)  (x += D^{-1} y when m_U = 1)
 };
+// c_i is the column factor d_c,i of the row/column scaling (SweepArgs::dcol),
+// or 1 (an exact multiplication) when dcol is null.
 
 // Precision of one sweep launch.
 enum class Prec : int {
@@ -45,6 +47,7 @@ struct SweepArgs {
     const double *dinv;   // EPI_SCALE / EPI_SCALE_UPDATE
     double *x;            // EPI_UPDATE / EPI_SCALE_UPDATE
     const double *dshift; // unscaled variant: adds (d_i - 1) * xin_i to the row sum (FP64 only)
+    const double *dcol = nullptr; // EPI_UPDATE / EPI_SCALE_UPDATE: column factors c_i, or null (c_i = 1)
 };
 
 // Kernel geometry for a sweep, picked from the mean row length.
@@ -86,7 +89,8 @@ struct LevelArgs {
     double *out;
     const double *dinv; // optional: s_out = dinv * out
     double *s_out;
-    double *xupd;       // optional: xupd += out
+    double *xupd;       // optional: xupd += out (xupd += dcol * out with dcol)
+    const double *dcol = nullptr;
 };
 // lanes: 1 (one lane per row, sequential row sum) or 4/8/16/32 lanes per row.
 hipError_t launch_level(const LevelArgs &a, int unit, int lanes, int start, int count, hipStream_t s,
@@ -96,7 +100,19 @@ hipError_t launch_scale_rows(int n, const int32_t *Urp, const int32_t *Ucol, con
                              int32_t *Uscol, double *Usval, double *d, double *dinv, float *Us32, int noscale,
                              int32_t us_nnz, int32_t *flags, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s);
-hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, double *x, hipStream_t s);
+// x_i += s_i, or x_i += dcol_i * s_i with dcol (row/column scaling)
+hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, const double *dcol, double *x, hipStream_t s);
+// Row/column scaling set-up (Ruiz steps in the max norm, then the unit
+// diagonal): fill, one max pass, one factor update, and the final write of
+// d_r and the strictly upper values of D_r U D_c.
+hipError_t launch_fill(int n, double *a, double va, double *b, double vb, hipStream_t s);
+hipError_t launch_ruiz_max(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, const double *dr,
+                           const double *dc, double *rmax, unsigned long long *cmax, int32_t *flags, hipStream_t s);
+hipError_t launch_ruiz_scale(int n, double *dr, double *dc, const double *rmax, const unsigned long long *cmax,
+                             hipStream_t s);
+hipError_t launch_rowcol_finish(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval,
+                                const double *dc, double *dr, double *Usval, float *Us32, int32_t us_nnz,
+                                hipStream_t s);
 hipError_t launch_init_flags(int32_t *flags, int count, int32_t value, hipStream_t s);
 hipError_t launch_finite_check(int n, const double *x, int32_t *flags, hipStream_t s);
 hipError_t launch_scale_copy(int n, const double *rhs, const double *dinv, double *out, hipStream_t s);

@@ -146,6 +146,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
     a.dinv = M.F.dinv;
     a.x = q.x;
     a.dshift = nullptr;
+    a.dcol = M.F.scaled == 2 ? M.F.dc : nullptr; // read by the update epilogues only
     a.out = nullptr;
     if (j == 0) { // residual
         a.rp = M.A.row_ptr;
@@ -276,6 +277,7 @@ int silu_server_register(silu_server *s, const silu_csr *A, const silu_factors *
         return SILU_ERR_SHAPE;
     if (A->dtype != SILU_F64 || F->Ls.dtype != SILU_F64 || F->Us.dtype != SILU_F64 || !F->dinv || !F->scaled)
         return SILU_ERR_UNSUPPORTED;
+    if (F->scaled == 2 && !F->dc) return SILU_ERR_ARG;
     s->mats.push_back({*A, *F});
     *matrix_id = (int)s->mats.size() - 1;
     return SILU_OK;

@@ -56,10 +56,86 @@ __global__ void __launch_bounds__(256) k_to_f32(int64_t n, const double *__restr
 }
 
 template <typename ST>
-__global__ void __launch_bounds__(256) k_axpy(int n, const ST *__restrict__ s, double *__restrict__ x)
+__global__ void __launch_bounds__(256) k_axpy(int n, const ST *__restrict__ s, const double *__restrict__ dcol,
+                                              double *__restrict__ x)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i < n) x[i] = x[i] + (double)s[i];
+    if (i < n) x[i] = x[i] + (dcol ? dcol[i] : 1.0) * (double)s[i];
+}
+
+// ---- row/column scaling of U (Section 5.1, eq. rowcolScale) ---------------
+// Ruiz steps in the max norm: with a_ij = (|u_ij| d_r,i) d_c,j, the row maxima
+// and column maxima of one step are taken from the same a, then
+// d_r,i *= 1/sqrt(row max), d_c,j *= 1/sqrt(column max).  Maxima are exact,
+// so the order in which rows meet a column does not change the result.
+__global__ void __launch_bounds__(256) k_fill2(int n, double *__restrict__ a, double va, double *__restrict__ b,
+                                               double vb)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    a[i] = va;
+    if (b) b[i] = vb;
+}
+
+// One lane per row; the column maxima are combined with 64-bit atomic max on
+// the bit patterns, which order like the values for non-negative doubles.  A
+// NaN never raises a maximum (like a strict > comparison), and a column index
+// outside [0, n) flags the row and is skipped.
+__global__ void __launch_bounds__(256) k_ruiz_max(int n, const int32_t *__restrict__ Urp,
+                                                  const int32_t *__restrict__ Ucol, const double *__restrict__ Uval,
+                                                  const double *__restrict__ dr, const double *__restrict__ dc,
+                                                  double *__restrict__ rmax, unsigned long long *cmax, int32_t *flags)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const double ri = dr[i];
+    double rm = 0.0;
+    for (int p = Urp[i]; p < Urp[i + 1]; ++p) {
+        const int j = Ucol[p];
+        if ((unsigned)j >= (unsigned)n) {
+            atomicMin(&flags[0], i);
+            continue;
+        }
+        const double v = (fabs(Uval[p]) * ri) * dc[j];
+        if (v > rm) rm = v;
+        if (v > 0.0) atomicMax(&cmax[j], (unsigned long long)__double_as_longlong(v));
+    }
+    rmax[i] = rm;
+}
+
+__global__ void __launch_bounds__(256) k_ruiz_scale(int n, double *__restrict__ dr, double *__restrict__ dc,
+                                                    const double *__restrict__ rmax,
+                                                    const unsigned long long *__restrict__ cmax)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    dr[i] = dr[i] * (1.0 / sqrt(rmax[i]));
+    dc[i] = dc[i] * (1.0 / sqrt(__longlong_as_double((long long)cmax[i])));
+}
+
+// The unit diagonal fixes the row factor, d_r,i = 1/(u_ii d_c,i); the strictly
+// upper values are u^_ij = (u_ij d_r,i) d_c,j.  Us row pointers and columns
+// were written by k_scale_rows; stores are bounded like there.
+__global__ void __launch_bounds__(256) k_rowcol_finish(int n, const int32_t *__restrict__ Urp,
+                                                       const int32_t *__restrict__ Ucol,
+                                                       const double *__restrict__ Uval, const double *__restrict__ dc,
+                                                       double *__restrict__ dr, double *__restrict__ Usval,
+                                                       float *__restrict__ Us32, int32_t us_nnz)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int p0 = Urp[i], p1 = Urp[i + 1];
+    if (p1 <= p0) return;
+    const double di = 1.0 / (Uval[p0] * dc[i]);
+    dr[i] = di;
+    int o = p0 - i;
+    for (int p = p0 + 1; p < p1; ++p, ++o) {
+        const int j = Ucol[p];
+        if (o < 0 || o >= us_nnz || (unsigned)j >= (unsigned)n) continue;
+        const double v = (Uval[p] * di) * dc[j];
+        Usval[o] = v;
+        if (Us32) Us32[o] = (float)v;
+    }
 }
 
 __global__ void k_init_flags(int32_t *flags, int count, int32_t value)
@@ -110,7 +186,7 @@ __global__ void __launch_bounds__(256) k_level_vec(LevelArgs a, int start, int c
         if (!UNIT) v = v / dii;
         a.out[i] = v;
         if (a.s_out) a.s_out[i] = a.dinv[i] * v;
-        if (a.xupd) a.xupd[i] = a.xupd[i] + v;
+        if (a.xupd) a.xupd[i] = a.xupd[i] + (a.dcol ? a.dcol[i] : 1.0) * v;
     }
 }
 
@@ -137,7 +213,7 @@ __global__ void __launch_bounds__(256) k_level(LevelArgs a, int start, int count
     if (!UNIT) v = v / dii;
     a.out[i] = v;
     if (a.s_out) a.s_out[i] = a.dinv[i] * v;
-    if (a.xupd) a.xupd[i] = a.xupd[i] + v;
+    if (a.xupd) a.xupd[i] = a.xupd[i] + (a.dcol ? a.dcol[i] : 1.0) * v;
 }
 
 __global__ void __launch_bounds__(256) k_scale_copy(int n, const double *__restrict__ rhs,
@@ -220,13 +296,49 @@ hipError_t launch_to_f32(int64_t n, const double *src, float *dst, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, double *x, hipStream_t s)
+hipError_t launch_axpy(int n, const void *s_vec, int s_is_f32, const double *dcol, double *x, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     if (s_is_f32)
-        hipLaunchKernelGGL(k_axpy<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const float *)s_vec, x);
+        hipLaunchKernelGGL(k_axpy<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const float *)s_vec, dcol,
+                           x);
     else
-        hipLaunchKernelGGL(k_axpy<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const double *)s_vec, x);
+        hipLaunchKernelGGL(k_axpy<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, (const double *)s_vec, dcol,
+                           x);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int n, double *a, double va, double *b, double vb, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill2, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a, va, b, vb);
+    return hipGetLastError();
+}
+
+hipError_t launch_ruiz_max(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, const double *dr,
+                           const double *dc, double *rmax, unsigned long long *cmax, int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ruiz_max, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, Urp, Ucol, Uval, dr, dc, rmax, cmax,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_ruiz_scale(int n, double *dr, double *dc, const double *rmax, const unsigned long long *cmax,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ruiz_scale, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, dr, dc, rmax, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowcol_finish(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval,
+                                const double *dc, double *dr, double *Usval, float *Us32, int32_t us_nnz,
+                                hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowcol_finish, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, Urp, Ucol, Uval, dc, dr, Usval,
+                       Us32, us_nnz);
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 //
 // One launch computes, for every row i of a CSR matrix N,
 //     t_i = rhs_i - sum_j N_ij xin_j
-// and applies an epilogue (store t, store D^{-1} t, x += t, x += D^{-1} t).
+// and applies an epilogue (store t, store D^{-1} t, x += t, x += D^{-1} t;
+// the updates optionally scaled by the column factors of a row/column scaling).
 // With N = A and rhs = b this is the residual r = b - A x (eq. ILUsplit);
 // with N = the strictly triangular part of a unit factor it is one Richardson
 // step y_k = rhs - N y_{k-1} (eq. richard; Algorithm 2).  The diagonal scaling
@@ -88,6 +89,7 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
     using IT = typename T::IT;
     using OT = typename T::OT;
     const IT v = (IT)t;
+    const double c = a.dcol ? a.dcol[row] : 1.0; // column factor; 1.0 * v is exact
     switch (a.epi) {
     case EPI_STORE:
         ((OT *)a.out)[row] = (OT)v;
@@ -96,18 +98,20 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
         ((OT *)a.out)[row] = (OT)(a.dinv[row] * (double)v);
         break;
     case EPI_UPDATE:
-        a.x[row] = a.x[row] + (double)v;
+        a.x[row] = a.x[row] + c * (double)v;
         break;
     default: // EPI_SCALE_UPDATE
-        a.x[row] = a.x[row] + (double)(OT)(a.dinv[row] * (double)v);
+        a.x[row] = a.x[row] + c * (double)(OT)(a.dinv[row] * (double)v);
         break;
     }
 }
 
 // Epilogue with its operands loaded up front: aux = x_i (UPDATE) or dinv_i
-// (SCALE, SCALE_UPDATE); aux2 = x_i (SCALE_UPDATE).
+// (SCALE, SCALE_UPDATE); aux2 = x_i (SCALE_UPDATE); c = the column factor
+// (UPDATE, SCALE_UPDATE; 1.0 without one).
 template <class T>
-__device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typename T::AT t, double aux, double aux2)
+__device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typename T::AT t, double aux, double aux2,
+                                             double c)
 {
     using IT = typename T::IT;
     using OT = typename T::OT;
@@ -120,10 +124,10 @@ __device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typena
         ((OT *)a.out)[row] = (OT)(aux * (double)v);
         break;
     case EPI_UPDATE:
-        a.x[row] = aux + (double)v;
+        a.x[row] = aux + c * (double)v;
         break;
     default: // EPI_SCALE_UPDATE
-        a.x[row] = aux2 + (double)(OT)(aux * (double)v);
+        a.x[row] = aux2 + c * (double)(OT)(aux * (double)v);
         break;
     }
 }
@@ -153,13 +157,14 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
     const int nr = min(RPB, a.n - r0);
     const int tid = (int)threadIdx.x;
     RT rhs_v = (RT)0;
-    double aux = 0.0, aux2 = 0.0, dsh = 1.0;
+    double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
     if (tid < nr) {
         const int row = r0 + tid;
         rhs_v = ((const RT *)a.rhs)[row];
         if (a.epi == EPI_UPDATE) aux = a.x[row];
         if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
         if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+        if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
         if (a.dshift) dsh = a.dshift[row];
     }
     for (int t = tid; t <= nr; t += BLOCK) srp[t] = a.rp[r0 + t];
@@ -189,7 +194,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
         __syncthreads();
     }
-    if (tid < nr) epilogue_pre<T>(a, r0 + tid, (AT)rhs_v - sum, aux, aux2);
+    if (tid < nr) epilogue_pre<T>(a, r0 + tid, (AT)rhs_v - sum, aux, aux2, cf);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>

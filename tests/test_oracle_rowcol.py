@@ -1,5 +1,5 @@
 """Pins for the oracle's row/column scaling of U (Section 5.1, eq.
-rowcolScale; Table 1's Ruiz column) and the smoother built on it (CPU only).
+rowcolScale; Table 1's last column, named Ruiz scaling in Table 2) and the smoother built on it (CPU only).
 
 The scaling reading: Ruiz steps in the max norm give D_c; the row factor is
 then fixed by the unit diagonal the paper requires, d_r,i = 1/(u_ii d_c,i).
