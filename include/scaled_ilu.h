@@ -62,7 +62,9 @@ extern "C" {
 #define SILU_KERNEL_VECTOR 0x200  /* vector-CSR (lanes-per-row) sweep kernel                */
 #define SILU_KERNEL_BLOCKED 0x400 /* CSR-stream over a row-block partition                  */
 #define SILU_NO_GRAPH 0x800       /* level-scheduled solves: plain launches, no hipGraph     */
-#define SILU_INDEX32 0x1000       /* sweeps read the 32-bit col_idx, never 16-bit offsets    */
+#define SILU_INDEX32 0x1000       /* sweeps read the 32-bit col_idx, never 16-bit codes      */
+#define SILU_NO_WINDOW 0x2000     /* sweeps never stage the iterate window in LDS            */
+#define SILU_WINDOW 0x4000        /* sweeps stage the window wherever it fits                */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -182,12 +184,20 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
 /* ---- the smoother (eq. ILUsplit, Algorithm 2, eq. richard) -------------- */
 
 /*
- * Column indices.  By default the first sweep over a matrix also builds, on
- * the device, block-relative 16-bit column offsets when every column lies
- * within 65,536 of its row block's base (banded factors do; a randomly
- * permuted matrix does not), caches them in the context (2 bytes per entry,
- * keyed by the matrix's pointers and sizes; the first use synchronizes once)
- * and streams those instead of col_idx.  SILU_INDEX32 disables this.
+ * Column indices.  The sweeps stream a 16-bit code per entry instead of
+ * col_idx when the matrix allows it, built on the device by the first sweep
+ * over a matrix and cached in the context (2 bytes per entry, keyed by the
+ * matrix's pointers and sizes; the first use synchronizes a few times):
+ *  - offsets (preferred): when every block-relative offset col - r0 (r0 =
+ *    the first row of the entry's row block) lies within a span of 65,536,
+ *    the code is the offset;
+ *  - windowed: else when the distinct offsets that occur number at most
+ *    3072 (a wide stencil operator), each workgroup stages the iterate
+ *    values at those offsets into LDS and the code is the LDS slot;
+ *    SILU_WINDOW prefers this mode wherever it fits;
+ *  - else (a randomly permuted matrix) col_idx itself.
+ * Every mode computes the same products in the same order (same bits).
+ * SILU_NO_WINDOW keeps to offsets; SILU_INDEX32 always reads col_idx.
  *
  * `outer_sweeps` smoothing steps on x (in/out; x = 0 for a pure
  * preconditioner application):

@@ -31,8 +31,11 @@ _lib = C.CDLL(LIB_PATH)
 SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
-SILU_NO_GRAPH, SILU_INDEX32 = 0x800, 0x1000
+SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
+# None / "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
+# "win": the LDS window wherever it fits; "stream16": offsets at most; "stream32": col_idx always
 KERNELS = {None: 0, "blocked": SILU_KERNEL_BLOCKED, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR,
+           "win": SILU_KERNEL_STREAM | SILU_WINDOW, "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW,
            "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1
 SILU_UNIT, SILU_NONUNIT = 0, 1

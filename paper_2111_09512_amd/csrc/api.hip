@@ -42,11 +42,25 @@ using PartKey = std::tuple<const void *, int64_t, int64_t, int>;
 
 // 16-bit block-relative column offsets of one matrix for one rows-per-block.
 struct Compressed {
-    uint16_t *d = nullptr;
+    uint16_t *d = nullptr;   // 16-bit offsets (OFF16)
     int shift = 0;
     bool ok = false;
+    uint16_t *slot = nullptr; // LDS slot codes (windowed), or null
+    int32_t *wo = nullptr;    // windowed: block-relative offset of each slot
+    int lw = 0;
+    bool win_tried = false;
+    int range_hi = 0; // largest block-relative offset (shift is the smallest)
 };
 using CompKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
+
+void free_compressed(Compressed &C)
+{
+    (void)hipFree(C.d);
+    (void)hipFree(C.slot);
+    (void)hipFree(C.wo);
+    C.d = C.slot = nullptr;
+    C.wo = nullptr;
+}
 
 // A captured level sequence: one kernel node per level.
 using GraphKey = std::tuple<const void *, const void *, const void *, const void *, const void *, const void *,
@@ -251,32 +265,87 @@ int get_partition(silu_ctx *c, const silu_csr *M, int cap, int rmax, Partition *
 // Block-relative 16-bit column offsets, made on first use on the device (one
 // synchronous read of the offset range) and cached per matrix; ok = false
 // when some offset does not fit 16 bits.
-int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, Compressed **out)
+// win_policy: 0 never build the window codes, 1 only when 16-bit offsets do
+// not fit, 2 always try.
+int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, int win_policy, Compressed **out)
 {
     CompKey key{M->row_ptr, M->col_idx, M->n_rows, M->nnz, rpb};
     auto it = c->comp.find(key);
+    Compressed *C = nullptr;
+    int32_t range[2] = {INT32_MAX, INT32_MIN};
     if (it != c->comp.end()) {
-        *out = &it->second;
-        return SILU_OK;
-    }
-    Compressed C;
-    HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
-    HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
-    HIPCHK(c, launch_offset_range((int)M->n_rows, M->row_ptr, M->col_idx, rpb, c->d_flags, c->stream));
-    int32_t range[2];
-    HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (range[0] <= range[1] && (int64_t)range[1] - (int64_t)range[0] <= 65535) {
-        HIPCHK(c, hipMalloc(&C.d, (size_t)M->nnz * sizeof(uint16_t)));
-        C.shift = range[0];
-        hipError_t e = launch_compress16((int)M->n_rows, M->row_ptr, M->col_idx, rpb, C.shift, C.d, c->stream);
-        if (e != hipSuccess) {
-            (void)hipFree(C.d);
-            return hip_fail(c, e);
+        C = &it->second;
+        if (win_policy == 0 || (win_policy == 1 && C->ok) || C->win_tried) {
+            *out = C;
+            return SILU_OK;
         }
-        C.ok = true;
+        range[0] = C->shift;
+        range[1] = C->range_hi;
+    } else {
+        HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
+        HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
+        HIPCHK(c, launch_offset_range((int)M->n_rows, M->row_ptr, M->col_idx, rpb, c->d_flags, c->stream));
+        HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        Compressed fresh;
+        fresh.shift = range[0];
+        fresh.range_hi = range[1];
+        if (range[0] <= range[1] && (int64_t)range[1] - (int64_t)range[0] <= 65535) {
+            HIPCHK(c, hipMalloc(&fresh.d, (size_t)M->nnz * sizeof(uint16_t)));
+            hipError_t e = launch_compress16((int)M->n_rows, M->row_ptr, M->col_idx, rpb, fresh.shift, fresh.d,
+                                             c->stream);
+            if (e != hipSuccess) {
+                (void)hipFree(fresh.d);
+                return hip_fail(c, e);
+            }
+            fresh.ok = true;
+        }
+        C = &c->comp.emplace(key, fresh).first->second;
     }
-    *out = &c->comp.emplace(key, C).first->second;
+    *out = C;
+    if (win_policy == 0 || (win_policy == 1 && C->ok)) return SILU_OK;
+    // windowed codes: number the offsets that occur; worth it only when they are few
+    C->win_tried = true;
+    const int64_t span = (int64_t)range[1] - (int64_t)range[0] + 1;
+    if (range[0] > range[1] || span > (int64_t)1 << 24) return SILU_OK;
+    uint8_t *d_used = nullptr;
+    const int64_t span8 = (span + 7) / 8; // cleared as doubles (+0.0 is all zero bits) by a fill kernel
+    HIPCHK(c, hipMalloc(&d_used, (size_t)span8 * 8));
+    hipError_t e = launch_fill((int)span8, (double *)d_used, 0.0, nullptr, 0.0, c->stream);
+    if (e == hipSuccess)
+        e = launch_mark_offsets((int)M->n_rows, M->row_ptr, M->col_idx, rpb, range[0], d_used, c->stream);
+    std::vector<uint8_t> used((size_t)span);
+    if (e == hipSuccess) e = hipMemcpyAsync(used.data(), d_used, (size_t)span, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_used);
+    if (e != hipSuccess) return hip_fail(c, e);
+    std::vector<int32_t> slot_of((size_t)span, -1), wo;
+    for (int64_t t = 0; t < span; t++) {
+        if (!used[(size_t)t]) continue;
+        if ((int)wo.size() >= WIN_MAX_SLOTS) return SILU_OK; // too many: keep the other modes
+        slot_of[(size_t)t] = (int32_t)wo.size();
+        wo.push_back((int32_t)(t + range[0]));
+    }
+    if (wo.empty()) return SILU_OK;
+    int32_t *d_slot_of = nullptr;
+    HIPCHK(c, hipMalloc(&d_slot_of, (size_t)span * 4));
+    e = hipMemcpyAsync(d_slot_of, slot_of.data(), (size_t)span * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMalloc(&C->wo, wo.size() * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(C->wo, wo.data(), wo.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMalloc(&C->slot, (size_t)M->nnz * sizeof(uint16_t));
+    if (e == hipSuccess)
+        e = launch_encode_slots((int)M->n_rows, M->row_ptr, M->col_idx, rpb, range[0], d_slot_of, C->slot,
+                                c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream); // the host tables go out of scope
+    (void)hipFree(d_slot_of);
+    if (e != hipSuccess) {
+        (void)hipFree(C->wo);
+        (void)hipFree(C->slot);
+        C->wo = nullptr;
+        C->slot = nullptr;
+        return hip_fail(c, e);
+    }
+    C->lw = (int)wo.size();
     return SILU_OK;
 }
 
@@ -286,9 +355,14 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
 {
     if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
         Compressed *C = nullptr;
-        int st = get_compressed(c, N, g.rows_per_block, &C);
+        const int policy = !g.allow_win ? 0 : (g.prefer_win ? 2 : 1);
+        int st = get_compressed(c, N, g.rows_per_block, policy, &C);
         if (st) return st;
-        if (C->ok) {
+        if (policy && C->lw > 0 && (g.prefer_win || !C->ok)) {
+            g.slot16 = C->slot;
+            g.wo = C->wo;
+            g.lw = C->lw;
+        } else if (C->ok) {
             g.off16 = C->d;
             g.shift = C->shift;
         }
@@ -314,7 +388,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     a.dshift = dshift;
     const bool upd = epi == EPI_UPDATE || epi == EPI_SCALE_UPDATE;
     a.dcol = upd ? dcol : nullptr;
-    double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, g.off16 ? 2.0 : 4.0);
+    double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, (g.off16 || g.lw) ? 2.0 : 4.0);
     if (a.dcol) bytes += 8.0 * (double)N->n_rows;
     return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
@@ -503,7 +577,7 @@ int silu_destroy(silu_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &kv : c->levels) (void)hipFree(kv.second.d_perm);
     for (auto &kv : c->parts) (void)hipFree(kv.second.d_blk);
-    for (auto &kv : c->comp) (void)hipFree(kv.second.d);
+    for (auto &kv : c->comp) free_compressed(kv.second);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
@@ -845,7 +919,7 @@ int silu_release(silu_ctx *c, const void *row_ptr, const void *col_idx)
     }
     for (auto it = c->comp.begin(); it != c->comp.end();) {
         if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
-            (void)hipFree(it->second.d);
+            free_compressed(it->second);
             it = c->comp.erase(it);
         } else {
             ++it;

@@ -61,6 +61,11 @@ struct SweepGeom {
     bool allow16 = false;             // STREAM: may use 16-bit block-relative column offsets
     const uint16_t *off16 = nullptr;  // STREAM: offsets (col = r0 + shift + off16[e]) when available
     int shift = 0;
+    bool allow_win = false;           // STREAM: may stage the iterate window in LDS
+    bool prefer_win = false;          // STREAM: window even where 16-bit offsets fit
+    const uint16_t *slot16 = nullptr; // STREAM, windowed: LDS slot of each entry's iterate value
+    const int32_t *wo = nullptr;      // STREAM, windowed: block-relative offset of each slot [lw]
+    int lw = 0;
 };
 
 // Block-relative 16-bit column offsets for the CSR-stream kernel with `rpb`
@@ -70,6 +75,16 @@ struct SweepGeom {
 hipError_t launch_offset_range(int n, const int32_t *rp, const int32_t *col, int rpb, int32_t *range, hipStream_t s);
 hipError_t launch_compress16(int n, const int32_t *rp, const int32_t *col, int rpb, int shift, uint16_t *off16,
                              hipStream_t s);
+// Windowed CSR-stream: the block-relative offsets o = col - r0(block) that
+// occur anywhere in the matrix, numbered in increasing order, are the LDS
+// slots of every workgroup's staged iterate window.  mark_offsets sets
+// used[o - lo]; encode_slots writes code[e] = slot_of[o - lo].
+hipError_t launch_mark_offsets(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, uint8_t *used,
+                               hipStream_t s);
+hipError_t launch_encode_slots(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, const int32_t *slot_of,
+                               uint16_t *code, hipStream_t s);
+// Largest window (LDS slots) the windowed sweep stages per workgroup.
+constexpr int WIN_MAX_SLOTS = 3072;
 
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name);

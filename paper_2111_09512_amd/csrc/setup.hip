@@ -250,18 +250,49 @@ __global__ void __launch_bounds__(256) k_offset_range(int n, const int32_t *__re
                                                       const int32_t *__restrict__ col, int rpb, int32_t *range)
 {
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n) return;
-    const int r0 = (i / rpb) * rpb;
     int lo = INT32_MAX, hi = INT32_MIN;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        const int o = col[p] - r0;
-        lo = min(lo, o);
-        hi = max(hi, o);
+    if (i < n) {
+        const int r0 = (i / rpb) * rpb;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int o = col[p] - r0;
+            lo = min(lo, o);
+            hi = max(hi, o);
+        }
     }
-    if (lo <= hi) {
+    // one atomic pair per wave
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+    }
+    if ((threadIdx.x & 63) == 0 && lo <= hi) {
         atomicMin(&range[0], lo);
         atomicMax(&range[1], hi);
     }
+}
+
+// used[col - r0(block) - lo] = 1 for every entry (all writers store the same
+// byte, so the races are benign).
+__global__ void __launch_bounds__(256) k_mark_offsets(int n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col, int rpb, int lo,
+                                                      uint8_t *__restrict__ used)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int base = (i / rpb) * rpb + lo;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) used[col[p] - base] = 1;
+}
+
+// code[e] = slot_of[col - r0(block) - lo]: the LDS slot that holds the entry's
+// iterate value in the windowed sweep.
+__global__ void __launch_bounds__(256) k_encode_slots(int n, const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col, int rpb, int lo,
+                                                      const int32_t *__restrict__ slot_of, uint16_t *__restrict__ code)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int base = (i / rpb) * rpb + lo;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) code[p] = (uint16_t)slot_of[col[p] - base];
 }
 
 __global__ void __launch_bounds__(256) k_compress16(int n, const int32_t *__restrict__ rp,
@@ -394,6 +425,22 @@ hipError_t launch_offset_range(int n, const int32_t *rp, const int32_t *col, int
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_offset_range, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, rpb, range);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_offsets(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, uint8_t *used,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_offsets, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, rpb, lo, used);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_slots(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, const int32_t *slot_of,
+                               uint16_t *code, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_encode_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, rpb, lo, slot_of, code);
     return hipGetLastError();
 }
 

@@ -138,12 +138,20 @@ __device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typena
 // row's rhs and epilogue operands together with the row pointers, so those
 // loads overlap the block's stream instead of following it.
 // ---------------------------------------------------------------------------
-// With C16 the column of entry e is r0 + shift + off16[e] (block-relative
-// 16-bit offsets, built once per matrix when every offset fits): 2 bytes of
-// index per entry instead of 4.
-template <class T, int BLOCK, int RPB, int CAP, bool C16>
-__device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const uint16_t *__restrict__ off16,
-                                            int shift)
+// Index modes of an entry's iterate value:
+//   IDX32:  xin[col[e]]                                   (4 bytes of index)
+//   OFF16:  xin[r0 + shift + off16[e]], block-relative 16-bit offsets (2 bytes)
+//   WIN:    xs[code[e]], the block's iterate window staged in LDS (2 bytes)
+// WIN: the block-relative offsets o = col - r0 that occur anywhere in the
+// matrix are numbered 0..lw-1 (wo[t] = the offset of slot t); every workgroup
+// first copies xin[r0 + wo[t]] into LDS slot t with unit-stride loads, so the
+// entry stream's gathers hit LDS instead of going through the vector memory
+// pipeline one 8-byte word at a time.  Banded factors use a few hundred slots.
+enum IdxMode : int { IDX32 = 0, OFF16 = 1, WIN = 2 };
+
+template <class T, int BLOCK, int RPB, int CAP, int MODE>
+__device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const uint16_t *__restrict__ code, int shift,
+                                            const int32_t *__restrict__ wo, int lw)
 {
     using VT = typename T::VT;
     using XT = typename T::XT;
@@ -152,10 +160,13 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
     static_assert(RPB <= BLOCK && CAP % BLOCK == 0, "geometry");
     __shared__ AT prod[CAP];
     __shared__ int32_t srp[RPB + 1];
+    extern __shared__ double lds_window[]; // WIN: XT xs[lw] (dynamic size)
 
     const int r0 = blk * RPB;
     const int nr = min(RPB, a.n - r0);
     const int tid = (int)threadIdx.x;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    XT *xs = (XT *)lds_window;
     RT rhs_v = (RT)0;
     double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
     if (tid < nr) {
@@ -168,11 +179,16 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         if (a.dshift) dsh = a.dshift[row];
     }
     for (int t = tid; t <= nr; t += BLOCK) srp[t] = a.rp[r0 + t];
+    if (MODE == WIN) {
+        for (int t = tid; t < lw; t += BLOCK) {
+            const int j = r0 + wo[t];
+            xs[t] = (unsigned)j < (unsigned)a.n ? xin[j] : (XT)0;
+        }
+    }
     __syncthreads();
 
     const VT *__restrict__ val = (const VT *)a.val;
     const int32_t *__restrict__ col = a.col;
-    const XT *__restrict__ xin = (const XT *)a.xin;
     const int e0 = srp[0], e1 = srp[nr];
 
     AT sum = (AT)0;
@@ -186,8 +202,14 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         const int c1 = min(c0 + CAP, e1);
 #pragma unroll 4
         for (int e = c0 + tid; e < c1; e += BLOCK) {
-            const int j = C16 ? r0 + shift + (int)__builtin_nontemporal_load(&off16[e]) : __builtin_nontemporal_load(&col[e]);
-            prod[e - c0] = (AT)__builtin_nontemporal_load(&val[e]) * (AT)xin[j];
+            XT xv;
+            if (MODE == WIN)
+                xv = xs[__builtin_nontemporal_load(&code[e])];
+            else if (MODE == OFF16)
+                xv = xin[r0 + shift + (int)__builtin_nontemporal_load(&code[e])];
+            else
+                xv = xin[__builtin_nontemporal_load(&col[e])];
+            prod[e - c0] = (AT)__builtin_nontemporal_load(&val[e]) * (AT)xv;
         }
         __syncthreads();
         const int lo = max(mylo, c0), hi = min(myhi, c1);
@@ -200,13 +222,21 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
 {
-    stream_rows<T, BLOCK, RPB, CAP, false>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), nullptr, 0);
+    stream_rows<T, BLOCK, RPB, CAP, IDX32>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), nullptr, 0, nullptr, 0);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_stream16(SweepArgs a, const uint16_t *__restrict__ off16, int shift)
 {
-    stream_rows<T, BLOCK, RPB, CAP, true>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), off16, shift);
+    stream_rows<T, BLOCK, RPB, CAP, OFF16>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), off16, shift, nullptr,
+                                           0);
+}
+
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_win(SweepArgs a, const uint16_t *__restrict__ code,
+                                                     const int32_t *__restrict__ wo, int lw)
+{
+    stream_rows<T, BLOCK, RPB, CAP, WIN>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), code, 0, wo, lw);
 }
 
 // Batched CSR-stream: one launch runs one sweep for each of `nops`
@@ -225,7 +255,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch(const SweepArgs *_
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stream_rows<T, BLOCK, RPB, CAP, false>(ops[lo], b - first[lo], nullptr, 0);
+    stream_rows<T, BLOCK, RPB, CAP, IDX32>(ops[lo], b - first[lo], nullptr, 0, nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,7 +371,10 @@ template <class T, int BLOCK, int RPB, int CAP>
 hipError_t go_stream(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 {
     const int grid = (a.n + RPB - 1) / RPB;
-    if (g.off16)
+    if (g.slot16 && g.lw > 0 && g.lw <= WIN_MAX_SLOTS)
+        hipLaunchKernelGGL((k_sweep_win<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK),
+                           (size_t)g.lw * sizeof(typename T::XT), s, a, g.slot16, g.wo, g.lw);
+    else if (g.off16)
         hipLaunchKernelGGL((k_sweep_stream16<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a, g.off16, g.shift);
     else
         hipLaunchKernelGGL((k_sweep_stream<T, BLOCK, RPB, CAP>), dim3(grid), dim3(BLOCK), 0, s, a);
@@ -421,6 +454,13 @@ const char *kname16(Prec p)
     return names[(int)p];
 }
 
+const char *kname_win(Prec p)
+{
+    static const char *names[5] = {"sweep_win_f64", "sweep_win_mixres", "sweep_win_mixL", "sweep_win_mixU",
+                                   "sweep_win_mixL1"};
+    return names[(int)p];
+}
+
 const char *kname(Prec p, SweepKernel k)
 {
     static const char *names[3][5] = {
@@ -433,7 +473,7 @@ const char *kname(Prec p, SweepKernel k)
 } // namespace
 
 // SILU_SWEEP_GEOM (tuning override, read per call): "blocked:CAP",
-// "stream:RPB" or "vector:LANES".
+// "stream:RPB", "stream16:RPB", "win:RPB" or "vector:LANES".
 static bool geom_override(SweepGeom &g)
 {
     const char *e = getenv("SILU_SWEEP_GEOM");
@@ -448,6 +488,14 @@ static bool geom_override(SweepGeom &g)
         g.kind = SweepKernel::STREAM;
         g.rows_per_block = v;
         g.allow16 = true;
+        return true;
+    }
+    if (sscanf(e, "win:%d", &v) == 1 && (v == 64 || v == 128 || v == 256)) {
+        g.kind = SweepKernel::STREAM;
+        g.rows_per_block = v;
+        g.allow16 = true;
+        g.allow_win = true;
+        g.prefer_win = true;
         return true;
     }
     if (sscanf(e, "stream:%d", &v) == 1 && (v == 64 || v == 128 || v == 256)) {
@@ -487,6 +535,10 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     g.kind = SweepKernel::STREAM;
     g.rows_per_block = (mean <= 8.0 || mean > 24.0 || (flags & 0x2)) ? 256 : (mean <= 16.0 ? 128 : 64);
     g.allow16 = !(flags & 0x1000); // SILU_INDEX32 keeps 32-bit column indices
+    // the LDS window where 16-bit offsets do not fit (wide stencils), or when
+    // asked for (SILU_WINDOW); SILU_NO_WINDOW: 16-bit offsets at most
+    g.allow_win = !(flags & 0x1000) && !(flags & 0x2000);
+    g.prefer_win = g.allow_win && (flags & 0x4000);
     return g;
 }
 
@@ -498,7 +550,12 @@ hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_
 
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name)
 {
-    if (name) *name = (g.kind == SweepKernel::STREAM && g.off16) ? kname16(p) : kname(p, g.kind);
+    if (name) {
+        if (g.kind == SweepKernel::STREAM && g.slot16 && g.lw > 0)
+            *name = kname_win(p);
+        else
+            *name = (g.kind == SweepKernel::STREAM && g.off16) ? kname16(p) : kname(p, g.kind);
+    }
     switch (p) {
     case Prec::F64: return dispatch<TF64>(g, a, s);
     case Prec::MIX_RES: return dispatch<TMixRes>(g, a, s);

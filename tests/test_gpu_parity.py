@@ -27,7 +27,7 @@ def ctx(B):
     return B.Context()
 
 
-KERNELS = [None, "stream32", "blocked", "vector"]  # None: the default (CSR-stream, 16-bit offsets where they fit)
+KERNELS = [None, "win", "stream16", "stream32", "blocked", "vector"]  # None: the default (CSR-stream, 16-bit offsets or the LDS window where they fit)
 
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
