@@ -58,13 +58,14 @@ extern "C" {
 #define SILU_CHECK_FINITE 0x4 /* ilu_smooth: after the step, scan x (synchronous)          */
 #define SILU_VALIDATE 0x8     /* check CSR structure first (synchronous; copies to host)   */
 #define SILU_NO_SCALING 0x10  /* ilu_scale_factors: keep U's values (the unscaled variant) */
-#define SILU_KERNEL_STREAM 0x100  /* CSR-stream sweep kernel (the default)                   */
+#define SILU_KERNEL_STREAM 0x100  /* CSR-stream sweep kernel (instead of the sliced default)   */
 #define SILU_KERNEL_VECTOR 0x200  /* vector-CSR (lanes-per-row) sweep kernel                */
 #define SILU_KERNEL_BLOCKED 0x400 /* CSR-stream over a row-block partition                  */
 #define SILU_NO_GRAPH 0x800       /* level-scheduled solves: plain launches, no hipGraph     */
 #define SILU_INDEX32 0x1000       /* sweeps read the 32-bit col_idx, never 16-bit codes      */
 #define SILU_NO_WINDOW 0x2000     /* sweeps never stage the iterate window in LDS            */
 #define SILU_WINDOW 0x4000        /* sweeps stage the window wherever it fits                */
+#define SILU_CODE16 0x8000        /* sliced sweeps: no diagonal table (16-bit codes or wider) */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -184,10 +185,27 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
 /* ---- the smoother (eq. ILUsplit, Algorithm 2, eq. richard) -------------- */
 
 /*
- * Column indices.  The sweeps stream a 16-bit code per entry instead of
- * col_idx when the matrix allows it, built on the device by the first sweep
- * over a matrix and cached in the context (2 bytes per entry, keyed by the
- * matrix's pointers and sizes; the first use synchronizes a few times):
+ * Layout the sweeps read.  By default the first sweep over a matrix (A, Ls,
+ * Us, and the FP32 value arrays in the mixed form) builds on the device a
+ * sliced copy of it and caches it in the context: 64-row slices (one
+ * wavefront each), entry k of every row of a slice stored contiguously,
+ * short rows padded to the slice's longest with value 0 at the row's last
+ * column, and a column code per slot -- 1 byte (an index into the table of
+ * the matrix's distinct diagonals col - row, when there are at most 256: a
+ * stencil operator and its ILU factors), else 2 bytes (slice-relative offset,
+ * when it fits), else the 4-byte column.  Each row's products are still added
+ * in ascending column order, so finite results are bit-identical to the
+ * row-by-row definition; a padded slot adds +0.0.  The first use synchronizes
+ * a few times.  The copy holds the VALUES as they were at that first sweep:
+ * a caller that changes a matrix's values in place afterwards must call
+ * silu_release(ctx, row_ptr, col_idx) first (ilu_scale_factors does this for
+ * the factors it writes; the Python binding does it whenever a tensor's
+ * version changes).  SILU_CODE16 skips the diagonal table; SILU_INDEX32 keeps
+ * 4-byte columns.
+ *
+ * With SILU_KERNEL_STREAM the sweeps read the CSR arrays themselves
+ * (CSR-stream), with a 16-bit code per entry when the matrix allows it, also
+ * built on the first sweep and cached (2 bytes per entry, structure only):
  *  - offsets (preferred): when every block-relative offset col - r0 (r0 =
  *    the first row of the entry's row block) lies within a span of 65,536,
  *    the code is the offset;
@@ -196,7 +214,6 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
  *    values at those offsets into LDS and the code is the LDS slot;
  *    SILU_WINDOW prefers this mode wherever it fits;
  *  - else (a randomly permuted matrix) col_idx itself.
- * Every mode computes the same products in the same order (same bits).
  * SILU_NO_WINDOW keeps to offsets; SILU_INDEX32 always reads col_idx.
  *
  * `outer_sweeps` smoothing steps on x (in/out; x = 0 for a pure
@@ -264,11 +281,11 @@ int trisolve_iter(silu_ctx *ctx, const silu_csr *T, const double *dinv, const do
  * Synchronous. */
 int silu_analyze(silu_ctx *ctx, const silu_csr *T, int uplo, int32_t *depth, int32_t *rows_per_level);
 
-/* Drop every analysis the context cached for the matrix whose row_ptr or
+/* Drop everything the context cached for the matrix whose row_ptr or
  * col_idx is given (level sets and their graphs, row-block partitions,
- * 16-bit offsets).  Analyses are keyed by pointers and sizes, so call this
- * before freeing a matrix or changing its pattern in place.  Synchronizes
- * the context stream. */
+ * 16-bit codes, sliced copies).  The caches are keyed by pointers and sizes,
+ * so call this before freeing a matrix, or changing its pattern or (for the
+ * sliced copies) its values in place.  Synchronizes the context stream. */
 int silu_release(silu_ctx *ctx, const void *row_ptr, const void *col_idx);
 
 /* ---- measurement ------------------------------------------------------- */

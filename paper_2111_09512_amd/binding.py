@@ -32,11 +32,14 @@ SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
-# None / "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
+SILU_CODE16 = 0x8000
+# None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
+# "sliced16": no diagonal table; "sliced32": 4-byte columns;
+# "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
 # "win": the LDS window wherever it fits; "stream16": offsets at most; "stream32": col_idx always
-KERNELS = {None: 0, "blocked": SILU_KERNEL_BLOCKED, "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR,
-           "win": SILU_KERNEL_STREAM | SILU_WINDOW, "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW,
-           "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
+KERNELS = {None: 0, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
+           "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR, "win": SILU_KERNEL_STREAM | SILU_WINDOW,
+           "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW, "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1
 SILU_UNIT, SILU_NONUNIT = 0, 1
 
@@ -206,16 +209,29 @@ class Context:
         self._h = h
         self._ws = None
         self._tracked = set()
+        self._versions = {}
 
-    def _track(self, *mats):
-        """Release the context's cached analyses of a matrix when its index
-        arrays are freed (they are keyed by pointer in the library)."""
-        for M in mats:
+    def _track(self, *mats, values=()):
+        """The library caches analyses and sliced copies of a matrix keyed by
+        its pointers: release them when its arrays are freed, and when a value
+        array (the matrix's own, or an extra one such as an FP32 copy) has been
+        changed in place since the last call (torch's version counter)."""
+        for k, M in enumerate(mats):
             key = (M.row_ptr.data_ptr(), M.col_idx.data_ptr() if M.nnz else 0)
+            vals = [M.val] + [v for v in (values[k] if k < len(values) else ()) if v is not None]
+            vers = tuple((v.data_ptr(), v._version) for v in vals)
             if key in self._tracked:
+                seen = dict(self._versions.get(key, ()))
+                if any(seen.get(ptr, ver) != ver for ptr, ver in vers):  # changed in place
+                    _lib.silu_release(self._h, C.c_void_p(key[0]), C.c_void_p(key[1] or None))
+                self._versions[key] = vers
                 continue
             self._tracked.add(key)
-            weakref.finalize(M.row_ptr, _release_cb, weakref.ref(self), key)
+            self._versions[key] = vers
+            ref = weakref.ref(self)
+            weakref.finalize(M.row_ptr, _release_cb, ref, key)
+            for v in vals:
+                weakref.finalize(v, _release_cb, ref, key)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -293,7 +309,7 @@ class Context:
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws
-        self._track(A, F.Ls, F.Us)
+        self._track(A, F.Ls, F.Us, values=((), (F.Ls_val32,), (F.Us_val32,)))
         Ac, Fc = A.c(), F.c()
         self._check(_lib.ilu_smooth2(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags,
@@ -362,9 +378,10 @@ class Context:
 
 def _release_cb(ctx_ref, key):
     ctx = ctx_ref()
-    if ctx is not None and getattr(ctx, "_h", None):
+    if ctx is not None and getattr(ctx, "_h", None) and key in ctx._tracked:
         _lib.silu_release(ctx._h, C.c_void_p(key[0]), C.c_void_p(key[1] or None))
         ctx._tracked.discard(key)
+        ctx._versions.pop(key, None)
 
 
 def _vec(t: torch.Tensor, n: int, what: str):

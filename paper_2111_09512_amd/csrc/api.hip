@@ -53,6 +53,28 @@ struct Compressed {
 };
 using CompKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
 
+// Sliced-ELL copy of one matrix's values (and its codes), keyed by the
+// structure and value pointers, the sizes, the value size and the smallest
+// code width allowed.
+struct Sliced {
+    SlicedView v;
+    int32_t *sptr = nullptr, *sk = nullptr, *dtab = nullptr;
+    void *val = nullptr, *codes = nullptr;
+    int64_t masked_rows = 0;
+    bool ok = false;
+};
+using SlicedKey = std::tuple<const void *, const void *, const void *, int64_t, int64_t, int, int>;
+
+void free_sliced(Sliced &S)
+{
+    (void)hipFree(S.sptr);
+    (void)hipFree(S.sk);
+    (void)hipFree(S.dtab);
+    (void)hipFree(S.val);
+    (void)hipFree(S.codes);
+    S = Sliced();
+}
+
 void free_compressed(Compressed &C)
 {
     (void)hipFree(C.d);
@@ -83,6 +105,7 @@ struct silu_ctx {
     std::map<LevelKey, LevelInfo> levels;
     std::map<PartKey, Partition> parts;
     std::map<CompKey, Compressed> comp;
+    std::map<SlicedKey, Sliced> sliced;
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipStream_t capture_stream = nullptr; // private, default priority, for graph capture
     bool timing = false;
@@ -200,22 +223,31 @@ struct Ws {
 
 size_t ws_vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
 
-double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift, double ib)
+// Bytes of a sweep's epilogue (and of the unscaled variant's diagonal term).
+double epi_bytes(Prec p, int64_t n, int epi, bool dshift)
 {
-    double vb = 8, xb = 8, rb = 8, ob = 8;
-    if (p == Prec::MIX_RES) ob = 4;
-    if (p == Prec::MIX_L) vb = xb = ob = 4;
-    if (p == Prec::MIX_U) vb = xb = rb = ob = 4;
-    if (p == Prec::MIX_L1) vb = ob = 4;
-    double b = 4.0 * (double)(n + 1) + (double)nnz * (vb + ib) + (double)n * (xb + rb);
+    double ob = 8;
+    if (p == Prec::MIX_RES || p == Prec::MIX_L || p == Prec::MIX_U || p == Prec::MIX_L1) ob = 4;
+    double b = 0.0;
     switch (epi) {
-    case EPI_STORE: b += n * ob; break;
-    case EPI_SCALE: b += n * (8.0 + ob); break;
-    case EPI_UPDATE: b += n * 16.0; break;
-    default: b += n * 24.0; break;
+    case EPI_STORE: b = n * ob; break;
+    case EPI_SCALE: b = n * (8.0 + ob); break;
+    case EPI_UPDATE: b = n * 16.0; break;
+    default: b = n * 24.0; break;
     }
     if (dshift) b += 8.0 * n;
     return b;
+}
+
+// Algorithmic bytes of a CSR sweep: each entry (value + ib bytes of index)
+// and the row pointers read once, the gathered iterate and the rhs once.
+double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift, double ib)
+{
+    double vb = 8, xb = 8, rb = 8;
+    if (p == Prec::MIX_L) vb = xb = 4;
+    if (p == Prec::MIX_U) vb = xb = rb = 4;
+    if (p == Prec::MIX_L1) vb = 4;
+    return 4.0 * (double)(n + 1) + (double)nnz * (vb + ib) + (double)n * (xb + rb) + epi_bytes(p, n, epi, dshift);
 }
 
 // Row-block partition for the blocked CSR-stream kernel, made on first use
@@ -349,10 +381,158 @@ int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, int win_policy, Comp
     return SILU_OK;
 }
 
+// Build (once) the sliced-ELL copy of N with values `val` of `vbytes` bytes.
+// code_min: 1 allows the diagonal table, 2 starts at 16-bit offsets, 4 uses
+// columns.  *out->ok is false when the matrix has no entries or the copy
+// would not fit 32-bit slot indices (the caller then streams the CSR).
+int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced **out)
+{
+    SlicedKey key{N->row_ptr, N->col_idx, val, N->n_rows, N->nnz, vbytes, code_min};
+    auto it = c->sliced.find(key);
+    if (it != c->sliced.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    Sliced S;
+    const int n = (int)N->n_rows;
+    const int nslice = (n + 63) / 64;
+    auto store = [&]() {
+        *out = &c->sliced.emplace(key, S).first->second;
+        return SILU_OK;
+    };
+    if (N->nnz <= 0 || n <= 0) return store();
+    // per-slice K and mask bit, then slot offsets
+    HIPCHK(c, hipMalloc(&S.sk, (size_t)nslice * 4));
+    hipError_t e = launch_slice_meta(n, nslice, N->row_ptr, S.sk, c->stream);
+    std::vector<int32_t> sk((size_t)nslice), sptr((size_t)nslice);
+    if (e == hipSuccess) e = hipMemcpyAsync(sk.data(), S.sk, (size_t)nslice * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        free_sliced(S);
+        return hip_fail(c, e);
+    }
+    int64_t slots = 0;
+    for (int t = 0; t < nslice; t++) {
+        sptr[(size_t)t] = (int32_t)std::min<int64_t>(slots, INT32_MAX);
+        slots += (int64_t)(sk[(size_t)t] & 0x7fffffff) * 64;
+        if (sk[(size_t)t] < 0) S.masked_rows += 64;
+    }
+    // padding beyond 4x the entries (a few very long rows) is not worth the copy
+    if (slots + 64 > INT32_MAX || slots > 4 * N->nnz + 64 * (int64_t)nslice) {
+        free_sliced(S);
+        return store();
+    }
+    // column codes: the diagonal table when at most 256 distinct col - row
+    // occur, else 16-bit slice-relative offsets when they fit, else columns
+    int code = 4, lo = 0;
+    std::vector<int32_t> dtab, dmap;
+    int32_t range[2];
+    if (code_min <= 1) {
+        HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
+        HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
+        HIPCHK(c, launch_offset_range(n, N->row_ptr, N->col_idx, 1, c->d_flags, c->stream));
+        HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int64_t dlo = std::min<int64_t>(range[0], 0), dhi = std::max<int64_t>(range[1], 0);
+        const int64_t span = dhi - dlo + 1;
+        if (span <= (int64_t)1 << 24) {
+            uint8_t *d_used = nullptr;
+            const int64_t span8 = (span + 7) / 8;
+            HIPCHK(c, hipMalloc(&d_used, (size_t)span8 * 8));
+            e = launch_fill((int)span8, (double *)d_used, 0.0, nullptr, 0.0, c->stream);
+            if (e == hipSuccess) e = launch_mark_offsets(n, N->row_ptr, N->col_idx, 1, (int)dlo, d_used, c->stream);
+            std::vector<uint8_t> used((size_t)span);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(used.data(), d_used, (size_t)span, hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            (void)hipFree(d_used);
+            if (e != hipSuccess) {
+                free_sliced(S);
+                return hip_fail(c, e);
+            }
+            used[(size_t)(0 - dlo)] = 1; // the empty rows' padding reads diagonal 0
+            int64_t cnt = 0;
+            for (int64_t t = 0; t < span && cnt <= 256; t++) cnt += used[(size_t)t];
+            if (cnt <= 256) {
+                dmap.assign((size_t)span, 0);
+                for (int64_t t = 0; t < span; t++) {
+                    if (!used[(size_t)t]) continue;
+                    dmap[(size_t)t] = (int32_t)dtab.size();
+                    dtab.push_back((int32_t)(t + dlo));
+                }
+                code = 1;
+                lo = (int)dlo;
+            }
+        }
+    }
+    if (code == 4 && code_min <= 2) {
+        HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
+        HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
+        HIPCHK(c, launch_offset_range(n, N->row_ptr, N->col_idx, 64, c->d_flags, c->stream));
+        HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int64_t olo = std::min<int64_t>(range[0], 0), ohi = std::max<int64_t>(range[1], 63);
+        if (ohi - olo <= 65535) {
+            code = 2;
+            lo = (int)olo;
+        }
+    }
+    int32_t *d_dmap = nullptr;
+    e = hipMalloc(&S.sptr, (size_t)nslice * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.sptr, sptr.data(), (size_t)nslice * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMalloc(&S.val, (size_t)slots * (size_t)vbytes);
+    if (e == hipSuccess) e = hipMalloc(&S.codes, (size_t)slots * (size_t)code);
+    if (e == hipSuccess && code == 1) {
+        e = hipMalloc(&S.dtab, dtab.size() * 4);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.dtab, dtab.data(), dtab.size() * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMalloc(&d_dmap, dmap.size() * 4);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_dmap, dmap.data(), dmap.size() * 4, hipMemcpyHostToDevice, c->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_fill_sliced(n, nslice, N->row_ptr, N->col_idx, val, vbytes, S.sptr, S.sk, code, d_dmap, lo, S.val,
+                               S.codes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream); // the host tables go out of scope
+    (void)hipFree(d_dmap);
+    if (e != hipSuccess) {
+        free_sliced(S);
+        return hip_fail(c, e);
+    }
+    S.v.nslice = nslice;
+    S.v.code = code;
+    S.v.sptr = S.sptr;
+    S.v.sk = S.sk;
+    S.v.val = S.val;
+    S.v.codes = S.codes;
+    S.v.dtab = S.dtab;
+    S.v.ndiag = (int)dtab.size();
+    S.v.shift = lo;
+    S.v.slots = slots;
+    S.ok = true;
+    return store();
+}
+
 int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
           const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift,
           const double *dcol = nullptr)
 {
+    double sliced_bytes = -1.0;
+    if (g.kind == SweepKernel::SLICED) {
+        const int vbytes = (p == Prec::F64 || p == Prec::MIX_RES) ? 8 : 4;
+        Sliced *S = nullptr;
+        int st = get_sliced(c, N, val, vbytes, g.slice_code_min, &S);
+        if (st) return st;
+        if (S->ok) {
+            g.sl = S->v;
+            const double xb = (p == Prec::MIX_L || p == Prec::MIX_U) ? 4.0 : 8.0;
+            const double rb = p == Prec::MIX_U ? 4.0 : 8.0;
+            sliced_bytes = (double)S->v.slots * (vbytes + S->v.code) + 8.0 * S->v.nslice +
+                           8.0 * (double)S->masked_rows + (double)N->n_rows * (xb + rb) + 4.0 * S->v.ndiag;
+        } else {
+            g.kind = SweepKernel::STREAM; // no entries, or too large for the sliced copy
+        }
+    }
     if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
         Compressed *C = nullptr;
         const int policy = !g.allow_win ? 0 : (g.prefer_win ? 2 : 1);
@@ -389,6 +569,8 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     const bool upd = epi == EPI_UPDATE || epi == EPI_SCALE_UPDATE;
     a.dcol = upd ? dcol : nullptr;
     double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, (g.off16 || g.lw) ? 2.0 : 4.0);
+    if (sliced_bytes >= 0.0) // the sliced layout's own bytes: padded slots, codes, slice tables
+        bytes = sliced_bytes + epi_bytes(p, N->n_rows, epi, dshift != nullptr);
     if (a.dcol) bytes += 8.0 * (double)N->n_rows;
     return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
@@ -578,6 +760,7 @@ int silu_destroy(silu_ctx *c)
     for (auto &kv : c->levels) (void)hipFree(kv.second.d_perm);
     for (auto &kv : c->parts) (void)hipFree(kv.second.d_blk);
     for (auto &kv : c->comp) free_compressed(kv.second);
+    for (auto &kv : c->sliced) free_sliced(kv.second);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
@@ -647,6 +830,9 @@ int scale_begin(silu_ctx *c, const silu_csr *L, const silu_csr *U, silu_factors 
         if ((st = validate(c, L, -1))) return st;
         if ((st = validate(c, U, 2))) return st;
     }
+    // cached copies of earlier values in these arrays are stale from here on
+    if ((st = silu_release(c, F->Us.row_ptr, F->Us.col_idx))) return st;
+    if ((st = silu_release(c, L->row_ptr, L->col_idx))) return st;
     F->Ls = *L;
     F->Us.n_rows = F->Us.n_cols = n;
     F->Us.nnz = U->nnz - n;
@@ -921,6 +1107,14 @@ int silu_release(silu_ctx *c, const void *row_ptr, const void *col_idx)
         if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
             free_compressed(it->second);
             it = c->comp.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (auto it = c->sliced.begin(); it != c->sliced.end();) {
+        if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
+            free_sliced(it->second);
+            it = c->sliced.erase(it);
         } else {
             ++it;
         }

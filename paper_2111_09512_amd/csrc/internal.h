@@ -28,7 +28,24 @@ enum class Prec : int {
     MIX_L1 = 4   // first mixed L sweep: gathers y_1 = r from the FP64 residual, rounding each value to FP32
 };
 
-enum class SweepKernel : int { STREAM = 0, VECTOR = 1, BLOCKED = 2 };
+enum class SweepKernel : int { STREAM = 0, VECTOR = 1, BLOCKED = 2, SLICED = 3 };
+
+// Sliced-ELL copy of a CSR matrix (64-row slices, one wavefront per slice;
+// built once per matrix on the device and cached).  code: bytes per column
+// code -- 1 (index into the table of distinct diagonals col - row), 2
+// (slice-relative offset col - 64 s - shift) or 4 (the column).
+struct SlicedView {
+    int nslice = 0;
+    int code = 4;
+    const int32_t *sptr = nullptr; // [nslice] first slot of each slice
+    const int32_t *sk = nullptr;   // [nslice] K | bit 31 when rows must be masked
+    const void *val = nullptr;     // [slots] values (FP64 or FP32)
+    const void *codes = nullptr;   // [slots]
+    const int32_t *dtab = nullptr; // code 1: diagonal of each index [ndiag <= 256]
+    int ndiag = 0;
+    int shift = 0;                 // code 2
+    int64_t slots = 0;
+};
 
 // Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
 // and RB_CAP entries per workgroup (a longer row gets a workgroup alone).
@@ -63,6 +80,8 @@ struct SweepGeom {
     int shift = 0;
     bool allow_win = false;           // STREAM: may stage the iterate window in LDS
     bool prefer_win = false;          // STREAM: window even where 16-bit offsets fit
+    SlicedView sl;                    // SLICED: the sliced copy (attached by the caller)
+    int slice_code_min = 1;           // SLICED: narrowest column code allowed (1, 2 or 4 bytes)
     const uint16_t *slot16 = nullptr; // STREAM, windowed: LDS slot of each entry's iterate value
     const int32_t *wo = nullptr;      // STREAM, windowed: block-relative offset of each slot [lw]
     int lw = 0;
@@ -83,6 +102,11 @@ hipError_t launch_mark_offsets(int n, const int32_t *rp, const int32_t *col, int
                                hipStream_t s);
 hipError_t launch_encode_slots(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, const int32_t *slot_of,
                                uint16_t *code, hipStream_t s);
+// Sliced-ELL set-up: per-slice K and mask bit; fill values and codes.
+hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, hipStream_t s);
+hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,
+                              const int32_t *sptr, const int32_t *sk, int code, const int32_t *dmap, int lo,
+                              void *sval, void *scode, hipStream_t s);
 // Largest window (LDS slots) the windowed sweep stages per workgroup.
 constexpr int WIN_MAX_SLOTS = 3072;
 

@@ -307,6 +307,58 @@ __global__ void __launch_bounds__(256) k_compress16(int n, const int32_t *__rest
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
+// ---- sliced-ELL copies (64-row slices, one wavefront per slice) ------------
+// Slice s holds rows [64 s, 64 s + 64); slot (k, lane) of the slice is entry k
+// of row 64 s + lane, at index sptr[s] + 64 k + lane.  sk[s] = K (the longest
+// row of the slice), with bit 31 set when some row of the slice is empty or
+// past the end (those slices run with per-row lengths).
+__global__ void __launch_bounds__(256) k_slice_meta(int n, int nslice, const int32_t *__restrict__ rp,
+                                                    int32_t *__restrict__ sk)
+{
+    const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= nslice) return;
+    int K = 0;
+    bool masked = false;
+    for (int r = s * 64; r < s * 64 + 64; ++r) {
+        if (r >= n) {
+            masked = true;
+            break;
+        }
+        const int len = rp[r + 1] - rp[r];
+        K = max(K, len);
+        if (len == 0) masked = true;
+    }
+    sk[s] = K | (masked ? (int32_t)0x80000000 : 0);
+}
+
+// One lane per row (rows past n fill the last slice's padding).  A padded slot
+// repeats the row's last column with value 0 (an empty row: its own column),
+// so an unmasked sweep reads only columns the row reads anyway.  Codes: 1 =
+// u8 index into the diagonal table (dmap[col - row - dlo]), 2 = u16 offset
+// col - 64 s - shift, 4 = the int32 column.
+template <typename VT, int CODE>
+__global__ void __launch_bounds__(256) k_fill_sliced(int n, int nslice, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                     const int32_t *__restrict__ sptr, const int32_t *__restrict__ sk,
+                                                     const int32_t *__restrict__ dmap, int lo, VT *__restrict__ sval,
+                                                     void *__restrict__ scode)
+{
+    const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (r >= nslice * 64) return;
+    const int s = r >> 6, lane = r & 63;
+    const int K = sk[s] & 0x7fffffff;
+    const int p0 = r < n ? rp[r] : 0, len = r < n ? rp[r + 1] - p0 : 0;
+    const int last = len > 0 ? col[p0 + len - 1] : min(r, n - 1);
+    for (int k = 0; k < K; ++k) {
+        const int64_t p = (int64_t)sptr[s] + (int64_t)k * 64 + lane;
+        const int c = k < len ? col[p0 + k] : last;
+        sval[p] = k < len ? val[p0 + k] : (VT)0;
+        if (CODE == 1) ((uint8_t *)scode)[p] = (uint8_t)dmap[c - min(r, n - 1) - lo];
+        else if (CODE == 2) ((uint16_t *)scode)[p] = (uint16_t)(c - s * 64 - lo);
+        else ((int32_t *)scode)[p] = c;
+    }
+}
+
 } // namespace
 
 hipError_t launch_scale_rows(int n, const int32_t *Urp, const int32_t *Ucol, const double *Uval, int32_t *Usrp,
@@ -458,6 +510,36 @@ hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
     if (n16 == 0) return hipSuccess;
     const int grid = (int)std::min<size_t>((n16 + 1023) / 1024, 256 * 16);
     hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, s, (const u32x4 *)src, (u32x4 *)dst, n16);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, hipStream_t s)
+{
+    if (nslice <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slice_meta, dim3(blocks_for(nslice, 256)), dim3(256), 0, s, n, nslice, rp, sk);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,
+                              const int32_t *sptr, const int32_t *sk, int code, const int32_t *dmap, int lo,
+                              void *sval, void *scode, hipStream_t s)
+{
+    if (nslice <= 0) return hipSuccess;
+    const dim3 g(blocks_for((int64_t)nslice * 64, 256)), b(256);
+#define SILU_FILL(VT, C)                                                                                              \
+    hipLaunchKernelGGL((k_fill_sliced<VT, C>), g, b, 0, s, n, nslice, rp, col, (const VT *)val, sptr, sk, dmap, lo,     \
+                       (VT *)sval, scode)
+    if (val_bytes == 8) {
+        if (code == 1) SILU_FILL(double, 1);
+        else if (code == 2) SILU_FILL(double, 2);
+        else SILU_FILL(double, 4);
+    } else {
+        if (code == 1) SILU_FILL(float, 1);
+        else if (code == 2) SILU_FILL(float, 2);
+        else SILU_FILL(float, 4);
+    }
+#undef SILU_FILL
     return hipGetLastError();
 }
 

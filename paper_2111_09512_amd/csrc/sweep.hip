@@ -239,6 +239,84 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_win(SweepArgs a, const uint16_t
     stream_rows<T, BLOCK, RPB, CAP, WIN>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), code, 0, wo, lw);
 }
 
+// ---------------------------------------------------------------------------
+// Sliced-ELL: one wavefront per 64-row slice, lane = row.  Entry k of every
+// row of the slice is contiguous, so value and code loads are unit-stride
+// across the wave and neighbouring rows gather neighbouring iterate values;
+// each lane adds its row's products in ascending column order (the oracle's
+// order) in registers: no LDS staging of products and no barrier.  Slices
+// whose rows all have entries run without per-row lengths: a padded slot holds
+// value 0 at the row's last column, which adds +0.0 to the sum (a sum started
+// at +0.0 is never -0.0), so finite results are unchanged and a non-finite
+// value there already makes the row's sum non-finite.  Slices with an empty
+// row, or rows past the end, mask by the row lengths.
+// ---------------------------------------------------------------------------
+template <class T, int CODE, int WPB, int UNR>
+__global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    __shared__ int32_t dtab[256];
+    if (CODE == 1) {
+        for (int t = (int)threadIdx.x; t < s.ndiag; t += 64 * WPB) dtab[t] = s.dtab[t];
+        __syncthreads();
+    }
+    const int wave = xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * WPB + ((int)threadIdx.x >> 6);
+    if (wave >= s.nslice) return;
+    const int lane = (int)threadIdx.x & 63;
+    const int row = wave * 64 + lane;
+    const bool live = row < a.n;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    const VT *__restrict__ sval = (const VT *)s.val;
+
+    RT rhs_v = (RT)0;
+    double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
+    if (live) {
+        rhs_v = ((const RT *)a.rhs)[row];
+        if (a.epi == EPI_UPDATE) aux = a.x[row];
+        if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
+        if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+        if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
+        if (a.dshift) dsh = a.dshift[row];
+    }
+    const int kf = s.sk[wave];
+    const int K = kf & 0x7fffffff;
+    const int p0 = s.sptr[wave];
+    const int base = wave * 64 + s.shift;
+    AT sum = (AT)0;
+    if (live && a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[row]);
+
+    auto column = [&](int p) -> int {
+        if (CODE == 1) return row + dtab[__builtin_nontemporal_load(&((const uint8_t *)s.codes)[p])];
+        if (CODE == 2) return base + (int)__builtin_nontemporal_load(&((const uint16_t *)s.codes)[p]);
+        return __builtin_nontemporal_load(&((const int32_t *)s.codes)[p]);
+    };
+    if (kf >= 0) {
+#pragma unroll UNR
+        for (int k = 0; k < K; ++k) {
+            const int p = p0 + k * 64 + lane;
+            const VT v = __builtin_nontemporal_load(&sval[p]);
+            const int j = column(p);
+            sum = sum + (AT)v * (AT)xin[j];
+        }
+    } else {
+        const int len = live ? a.rp[row + 1] - a.rp[row] : 0;
+        const int safe = min(row, a.n - 1);
+#pragma unroll UNR
+        for (int k = 0; k < K; ++k) {
+            const int p = p0 + k * 64 + lane;
+            const VT v = __builtin_nontemporal_load(&sval[p]);
+            const int j = column(p);
+            const bool on = k < len;
+            const AT t = sum + (AT)v * (AT)xin[on ? j : safe];
+            sum = on ? t : sum;
+        }
+    }
+    if (live) epilogue_pre<T>(a, row, (AT)rhs_v - sum, aux, aux2, cf);
+}
+
 // Batched CSR-stream: one launch runs one sweep for each of `nops`
 // independent requests (different matrices, sizes and epilogues).  Op i owns
 // workgroups [first[i], first[i+1]); each workgroup finds its op by binary
@@ -406,6 +484,18 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         }
         return hipGetLastError();
     }
+    if (g.kind == SweepKernel::SLICED) {
+        constexpr int WPB = 4, UNR = 4;
+        if (g.sl.nslice <= 0) return hipErrorInvalidValue;
+        const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
+        switch (g.sl.code) {
+        case 1: hipLaunchKernelGGL((k_sweep_sliced<T, 1, WPB, UNR>), grid, block, 0, s, a, g.sl); break;
+        case 2: hipLaunchKernelGGL((k_sweep_sliced<T, 2, WPB, UNR>), grid, block, 0, s, a, g.sl); break;
+        case 4: hipLaunchKernelGGL((k_sweep_sliced<T, 4, WPB, UNR>), grid, block, 0, s, a, g.sl); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (g.kind == SweepKernel::STREAM) {
         switch (g.rows_per_block) {
         case 256: return go_stream<T, 256, 256, 1024>(g, a, s);
@@ -463,17 +553,18 @@ const char *kname_win(Prec p)
 
 const char *kname(Prec p, SweepKernel k)
 {
-    static const char *names[3][5] = {
+    static const char *names[4][5] = {
         {"sweep_stream_f64", "sweep_stream_mixres", "sweep_stream_mixL", "sweep_stream_mixU", "sweep_stream_mixL1"},
         {"sweep_vector_f64", "sweep_vector_mixres", "sweep_vector_mixL", "sweep_vector_mixU", "sweep_vector_mixL1"},
-        {"sweep_rb_f64", "sweep_rb_mixres", "sweep_rb_mixL", "sweep_rb_mixU", "sweep_rb_mixL1"}};
+        {"sweep_rb_f64", "sweep_rb_mixres", "sweep_rb_mixL", "sweep_rb_mixU", "sweep_rb_mixL1"},
+        {"sweep_sliced_f64", "sweep_sliced_mixres", "sweep_sliced_mixL", "sweep_sliced_mixU", "sweep_sliced_mixL1"}};
     return names[(int)k][(int)p];
 }
 
 } // namespace
 
 // SILU_SWEEP_GEOM (tuning override, read per call): "blocked:CAP",
-// "stream:RPB", "stream16:RPB", "win:RPB" or "vector:LANES".
+// "stream:RPB", "stream16:RPB", "win:RPB", "sliced:CODE" or "vector:LANES".
 static bool geom_override(SweepGeom &g)
 {
     const char *e = getenv("SILU_SWEEP_GEOM");
@@ -503,6 +594,12 @@ static bool geom_override(SweepGeom &g)
         g.rows_per_block = v;
         return true;
     }
+    if (sscanf(e, "sliced:%d", &v) == 1 && (v == 1 || v == 2 || v == 4)) {
+        g.kind = SweepKernel::SLICED;
+        g.rows_per_block = 64;
+        g.slice_code_min = v;
+        return true;
+    }
     if (sscanf(e, "vector:%d", &v) == 1 && v >= 4 && v <= 64 && (v & (v - 1)) == 0) {
         g.kind = SweepKernel::VECTOR;
         g.lanes = v;
@@ -528,7 +625,16 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
         g.lanes = mean <= 6.0 ? 4 : (mean <= 12.0 ? 8 : (mean <= 24.0 ? 16 : (mean <= 48.0 ? 32 : 64)));
         return g;
     }
-    // default (and SILU_KERNEL_STREAM): CSR-stream; short rows fill a
+    if (!(flags & 0x100)) { // default: sliced-ELL (the caller attaches the sliced copy, else falls back)
+        g.kind = SweepKernel::SLICED;
+        g.rows_per_block = (mean <= 8.0 || mean > 24.0 || (flags & 0x2)) ? 256 : (mean <= 16.0 ? 128 : 64);
+        g.allow16 = !(flags & 0x1000);
+        g.allow_win = !(flags & 0x1000) && !(flags & 0x2000);
+        g.prefer_win = false;
+        g.slice_code_min = (flags & 0x1000) ? 4 : ((flags & 0x8000) ? 2 : 1); // SILU_INDEX32, SILU_CODE16
+        return g;
+    }
+    // SILU_KERNEL_STREAM: CSR-stream; short rows fill a
     // workgroup with 256 of them, long rows take 64 so one LDS chunk holds them
     // FP64 factor rows of 9-24 entries stream best 64-128 rows at a time;
     // short rows, long rows and the FP32-value sweeps (SILU_MIXED) with 256

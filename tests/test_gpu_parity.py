@@ -27,7 +27,7 @@ def ctx(B):
     return B.Context()
 
 
-KERNELS = [None, "win", "stream16", "stream32", "blocked", "vector"]  # None: the default (CSR-stream, 16-bit offsets or the LDS window where they fit)
+KERNELS = [None, "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
 
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
@@ -412,3 +412,51 @@ def test_cached_analyses_follow_matrix_lifetime(orc, B, ctx):
         del Td
         gc.collect()
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["poisson17", "aniso11_ilut", "perm9"])
+def test_outer_convergence_counts(orc, B, ctx, cases, name):
+    """Repeated smoothing on the GPU reaches ||b - A x|| / ||b|| < 1e-8 (eq.
+    relres) in the same number of outer steps as the oracle, for the FP64 and
+    the FP32-inner forms, and the two forms need the same number of steps."""
+    say("outer convergence", name)
+    c = cases[name]
+    b = W.rhs(c.A.n, 0)
+    nb = np.linalg.norm(b)
+    counts = {}
+    for mixed in (False, True):
+        k_ref, _, hist = orc.smooth_until(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(c.A.n), 3, 3, 1e-8, 300, mixed=mixed)
+        assert k_ref <= 300
+        bd, x = dev(b), dev(np.zeros(c.A.n))
+        k = 0
+        while True:
+            ctx.ilu_smooth(c.Ad, c.F, bd, x, 1, 3, 3, mixed=mixed)
+            k += 1
+            rel = np.linalg.norm(orc.residual(c.A, b, host(x))) / nb
+            if rel < 1e-8 or k > 300:
+                break
+        assert k == k_ref, f"mixed={mixed}: GPU {k} steps, oracle {k_ref}"
+        counts[mixed] = k
+    assert counts[True] == counts[False]
+
+
+def test_values_changed_in_place(orc, B, ctx):
+    """The sliced copies hold values: changing A's or L's values in place is
+    seen by the next call (the binding releases the stale copies)."""
+    say("values changed in place")
+    A = W.vardens7(11, seed_rho=3)
+    Ls, U = orc.ilu0(A)
+    d, dinv, Us = orc.scale_rows(U)
+    Ad, Ld, Ud = B.Csr.from_host(A), B.Csr.from_host(Ls), B.Csr.from_host(U)
+    F = ctx.ilu_scale_factors(Ld, Ud)
+    b = W.rhs(A.n, 0)
+    x = dev(np.zeros(A.n))
+    ctx.ilu_smooth(Ad, F, dev(b), x, 1, 3, 3)
+    np.testing.assert_array_equal(host(x), orc.smooth(A, Ls, Us, dinv, b, np.zeros(A.n), 1, 3, 3))
+    Ad.val.mul_(2.0)  # in place on the device
+    Ld.val.mul_(0.5)
+    A2 = W.CSR(A.n, A.row_ptr, A.col, A.val * 2.0)
+    L2 = W.CSR(Ls.n, Ls.row_ptr, Ls.col, Ls.val * 0.5)
+    x = dev(np.zeros(A.n))
+    ctx.ilu_smooth(Ad, F, dev(b), x, 1, 3, 3)
+    np.testing.assert_array_equal(host(x), orc.smooth(A2, L2, Us, dinv, b, np.zeros(A.n), 1, 3, 3))

@@ -16,7 +16,7 @@ from tests.gpu_common import F64_TOL, MIXED_TOL, assert_close, dev, host, need_g
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = [None, "win", "stream16", "stream32", "blocked", "vector"]
+KERNELS = [None, "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]
 RUIZ = 5
 
 SMALL = {
