@@ -38,7 +38,7 @@ struct SlicedView {
     int nslice = 0;
     int code = 4;
     const int32_t *sptr = nullptr; // [nslice] first slot of each slice
-    const int32_t *sk = nullptr;   // [nslice] K | bit 31 when rows must be masked
+    const int32_t *sk = nullptr;   // [nslice] K rounded up to 4 | bit 31 when rows must be masked
     const void *val = nullptr;     // [slots] values (FP64 or FP32)
     const void *codes = nullptr;   // [slots]
     const int32_t *dtab = nullptr; // code 1: diagonal of each index [ndiag <= 256]

@@ -308,10 +308,14 @@ __global__ void __launch_bounds__(256) k_compress16(int n, const int32_t *__rest
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
 // ---- sliced-ELL copies (64-row slices, one wavefront per slice) ------------
-// Slice s holds rows [64 s, 64 s + 64); slot (k, lane) of the slice is entry k
-// of row 64 s + lane, at index sptr[s] + 64 k + lane.  sk[s] = K (the longest
-// row of the slice), with bit 31 set when some row of the slice is empty or
-// past the end (those slices run with per-row lengths).
+// Slice s holds rows [64 s, 64 s + 64) and K4 = (its longest row rounded up
+// to a multiple of 4) slots per row, in groups of four entries so that a lane
+// fetches a group with wide loads: within group q (entries 4q..4q+3 of every
+// row of the slice, 256 slots starting at sptr[s] + 256 q),
+//   FP64 values of entries 4q + 2h + {0,1} of lane l at 128 h + 2 l + {0,1}
+//   FP32 values and all codes of entry 4q + r of lane l at 4 l + r.
+// sk[s] = K4, with bit 31 set when some row of the slice is empty or past the
+// end (those slices run with per-row lengths).
 __global__ void __launch_bounds__(256) k_slice_meta(int n, int nslice, const int32_t *__restrict__ rp,
                                                     int32_t *__restrict__ sk)
 {
@@ -328,7 +332,14 @@ __global__ void __launch_bounds__(256) k_slice_meta(int n, int nslice, const int
         K = max(K, len);
         if (len == 0) masked = true;
     }
-    sk[s] = K | (masked ? (int32_t)0x80000000 : 0);
+    sk[s] = ((K + 3) & ~3) | (masked ? (int32_t)0x80000000 : 0);
+}
+
+__device__ __forceinline__ int64_t value_slot(int64_t base, int k, int lane, int vbytes)
+{
+    const int q = k >> 2, r = k & 3;
+    if (vbytes == 8) return base + 256 * q + 128 * (r >> 1) + 2 * lane + (r & 1);
+    return base + 256 * q + 4 * lane + r;
 }
 
 // One lane per row (rows past n fill the last slice's padding).  A padded slot
@@ -346,16 +357,17 @@ __global__ void __launch_bounds__(256) k_fill_sliced(int n, int nslice, const in
     const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (r >= nslice * 64) return;
     const int s = r >> 6, lane = r & 63;
-    const int K = sk[s] & 0x7fffffff;
+    const int K4 = sk[s] & 0x7fffffff;
     const int p0 = r < n ? rp[r] : 0, len = r < n ? rp[r + 1] - p0 : 0;
     const int last = len > 0 ? col[p0 + len - 1] : min(r, n - 1);
-    for (int k = 0; k < K; ++k) {
-        const int64_t p = (int64_t)sptr[s] + (int64_t)k * 64 + lane;
+    const int64_t base = sptr[s];
+    for (int k = 0; k < K4; ++k) {
         const int c = k < len ? col[p0 + k] : last;
-        sval[p] = k < len ? val[p0 + k] : (VT)0;
-        if (CODE == 1) ((uint8_t *)scode)[p] = (uint8_t)dmap[c - min(r, n - 1) - lo];
-        else if (CODE == 2) ((uint16_t *)scode)[p] = (uint16_t)(c - s * 64 - lo);
-        else ((int32_t *)scode)[p] = c;
+        sval[value_slot(base, k, lane, (int)sizeof(VT))] = k < len ? val[p0 + k] : (VT)0;
+        const int64_t pc = base + 256 * (k >> 2) + 4 * lane + (k & 3);
+        if (CODE == 1) ((uint8_t *)scode)[pc] = (uint8_t)dmap[c - min(r, n - 1) - lo];
+        else if (CODE == 2) ((uint16_t *)scode)[pc] = (uint16_t)(c - s * 64 - lo);
+        else ((int32_t *)scode)[pc] = c;
     }
 }
 

@@ -240,17 +240,24 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_win(SweepArgs a, const uint16_t
 }
 
 // ---------------------------------------------------------------------------
-// Sliced-ELL: one wavefront per 64-row slice, lane = row.  Entry k of every
-// row of the slice is contiguous, so value and code loads are unit-stride
-// across the wave and neighbouring rows gather neighbouring iterate values;
-// each lane adds its row's products in ascending column order (the oracle's
-// order) in registers: no LDS staging of products and no barrier.  Slices
-// whose rows all have entries run without per-row lengths: a padded slot holds
-// value 0 at the row's last column, which adds +0.0 to the sum (a sum started
-// at +0.0 is never -0.0), so finite results are unchanged and a non-finite
-// value there already makes the row's sum non-finite.  Slices with an empty
-// row, or rows past the end, mask by the row lengths.
+// Sliced-ELL: one wavefront per 64-row slice, lane = row.  The slots of a
+// slice come in groups of four entries per row (see the set-up kernels), so a
+// lane fetches a group with one 16-byte (FP64: two) value load and one code
+// load of 4, 8 or 16 bytes, all unit-stride across the wave; neighbouring
+// rows gather neighbouring iterate values.  Each lane adds its row's products
+// in ascending column order (the oracle's order) in registers: no LDS staging
+// of products and no barrier.  Slices whose rows all have entries run without
+// per-row lengths: a padded slot holds value 0 at the row's last column, which
+// adds +0.0 to the sum (a sum started at +0.0 is never -0.0), so finite
+// results are unchanged and a non-finite value there already makes the row's
+// sum non-finite.  Slices with an empty row, or rows past the end, mask by
+// the row lengths.
 // ---------------------------------------------------------------------------
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
 template <class T, int CODE, int WPB, int UNR>
 __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
 {
@@ -269,7 +276,6 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
     const int row = wave * 64 + lane;
     const bool live = row < a.n;
     const XT *__restrict__ xin = (const XT *)a.xin;
-    const VT *__restrict__ sval = (const VT *)s.val;
 
     RT rhs_v = (RT)0;
     double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
@@ -282,36 +288,72 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
         if (a.dshift) dsh = a.dshift[row];
     }
     const int kf = s.sk[wave];
-    const int K = kf & 0x7fffffff;
-    const int p0 = s.sptr[wave];
+    const int G = (kf & 0x7fffffff) >> 2; // groups of four entries
+    const int p0 = s.sptr[wave];          // a multiple of 256
     const int base = wave * 64 + s.shift;
     AT sum = (AT)0;
     if (live && a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[row]);
+    const int len = kf >= 0 ? 4 * G : (live ? a.rp[row + 1] - a.rp[row] : 0);
+    const int safe = min(row, a.n - 1);
 
-    auto column = [&](int p) -> int {
-        if (CODE == 1) return row + dtab[__builtin_nontemporal_load(&((const uint8_t *)s.codes)[p])];
-        if (CODE == 2) return base + (int)__builtin_nontemporal_load(&((const uint16_t *)s.codes)[p]);
-        return __builtin_nontemporal_load(&((const int32_t *)s.codes)[p]);
+    // the four entries of group q: values v[0..3], columns j[0..3]
+    auto group = [&](int q, VT *v, int *j) {
+        if (sizeof(VT) == 8) {
+            const f64x2 *pv = (const f64x2 *)s.val + (p0 >> 1) + 128 * q + lane;
+            const f64x2 lo2 = __builtin_nontemporal_load(pv), hi2 = __builtin_nontemporal_load(pv + 64);
+            v[0] = (VT)lo2.x;
+            v[1] = (VT)lo2.y;
+            v[2] = (VT)hi2.x;
+            v[3] = (VT)hi2.y;
+        } else {
+            const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)s.val + (p0 >> 2) + 64 * q + lane);
+            v[0] = (VT)v4.x;
+            v[1] = (VT)v4.y;
+            v[2] = (VT)v4.z;
+            v[3] = (VT)v4.w;
+        }
+        const int pc = (p0 >> 2) + 64 * q + lane;
+        if (CODE == 1) {
+            const unsigned c = __builtin_nontemporal_load((const unsigned *)s.codes + pc);
+            j[0] = row + dtab[c & 0xffu];
+            j[1] = row + dtab[(c >> 8) & 0xffu];
+            j[2] = row + dtab[(c >> 16) & 0xffu];
+            j[3] = row + dtab[c >> 24];
+        } else if (CODE == 2) {
+            const u32x2 c = __builtin_nontemporal_load((const u32x2 *)s.codes + pc);
+            j[0] = base + (int)(c.x & 0xffffu);
+            j[1] = base + (int)(c.x >> 16);
+            j[2] = base + (int)(c.y & 0xffffu);
+            j[3] = base + (int)(c.y >> 16);
+        } else {
+            const i32x4 c = __builtin_nontemporal_load((const i32x4 *)s.codes + pc);
+            j[0] = c.x;
+            j[1] = c.y;
+            j[2] = c.z;
+            j[3] = c.w;
+        }
     };
     if (kf >= 0) {
 #pragma unroll UNR
-        for (int k = 0; k < K; ++k) {
-            const int p = p0 + k * 64 + lane;
-            const VT v = __builtin_nontemporal_load(&sval[p]);
-            const int j = column(p);
-            sum = sum + (AT)v * (AT)xin[j];
+        for (int q = 0; q < G; ++q) {
+            VT v[4];
+            int j[4];
+            group(q, v, j);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sum = sum + (AT)v[r] * (AT)xin[j[r]];
         }
     } else {
-        const int len = live ? a.rp[row + 1] - a.rp[row] : 0;
-        const int safe = min(row, a.n - 1);
 #pragma unroll UNR
-        for (int k = 0; k < K; ++k) {
-            const int p = p0 + k * 64 + lane;
-            const VT v = __builtin_nontemporal_load(&sval[p]);
-            const int j = column(p);
-            const bool on = k < len;
-            const AT t = sum + (AT)v * (AT)xin[on ? j : safe];
-            sum = on ? t : sum;
+        for (int q = 0; q < G; ++q) {
+            VT v[4];
+            int j[4];
+            group(q, v, j);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool on = 4 * q + r < len;
+                const AT t = sum + (AT)v[r] * (AT)xin[on ? j[r] : safe];
+                sum = on ? t : sum;
+            }
         }
     }
     if (live) epilogue_pre<T>(a, row, (AT)rhs_v - sum, aux, aux2, cf);
@@ -485,7 +527,7 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         return hipGetLastError();
     }
     if (g.kind == SweepKernel::SLICED) {
-        constexpr int WPB = 4, UNR = 4;
+        constexpr int WPB = 4, UNR = 2;
         if (g.sl.nslice <= 0) return hipErrorInvalidValue;
         const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
         switch (g.sl.code) {
