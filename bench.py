@@ -154,6 +154,7 @@ def main():
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rowcol", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -235,9 +236,12 @@ def main():
     ach = dv["bytes"] / dv["launches"] / (dv["ms"] / dv["launches"] * 1e-3) / 1e9
 
     # ---- mixed form ----
-    ms_mixed, bytes_mixed, st_mixed = timed(app_mixed, "mixed")
-    mixed_err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-    log(f"mixed: rel diff vs FP64 GPU {mixed_err:.2e}")
+    ms_mixed = bytes_mixed = mixed_err = None
+    st_mixed = {}
+    if not args.no_mixed:
+        ms_mixed, bytes_mixed, st_mixed = timed(app_mixed, "mixed")
+        mixed_err = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        log(f"mixed: rel diff vs FP64 GPU {mixed_err:.2e}")
 
     # ---- row/column (Ruiz) scaled factors: same sweeps, column factor in the last update ----
     rowcol = None
@@ -306,9 +310,9 @@ def main():
         "hbm_GBps": gbps,
         "bytes_per_app": bytes_app,
         "copy_GBps": copy_gbps,
-        "mixed_apps_per_s": 1e3 / ms_mixed,
+        "mixed_apps_per_s": (1e3 / ms_mixed) if ms_mixed else None,
         "mixed_ms": ms_mixed,
-        "mixed_GBps": bytes_mixed / (ms_mixed * 1e-3) / 1e9,
+        "mixed_GBps": (bytes_mixed / (ms_mixed * 1e-3) / 1e9) if ms_mixed else None,
         "mixed_bytes_per_app": bytes_mixed,
         "mixed_rel_diff_vs_f64": mixed_err,
         "rowcol": rowcol,
