@@ -783,6 +783,78 @@ void orc_smooth_rowcol(int n, const int *Arp, const int *Acol, const double *Ava
     }
 }
 
+/* =========================================================================
+ * Polynomial Gauss-Seidel smoother (Section 2: the polynomial smoother the
+ * ILU smoother is compared with).  Gauss-Seidel's (D + L)^{-1}, with D the
+ * diagonal and L the strictly lower part of A, is written (I + D^{-1}L)^{-1}
+ * D^{-1} and the inverse replaced by a truncated Neumann series:
+ *   x <- x + sum_{j<m} (-D^{-1} L)^j D^{-1} (b - A x)      (m terms).
+ * orc_gs_split: Gs = D^{-1} L (strictly lower CSR, g_ij = a_ij / a_ii, one
+ * division each; Gs_col/Gs_val need room for nnz(A) entries) and
+ * dinv_i = 1 / a_ii.  Errors: PATTERN (a row without its diagonal),
+ * ZERO_PIVOT (a_ii == 0 or not finite).
+ * ========================================================================= */
+int orc_gs_split(int n, const int *Arp, const int *Acol, const double *Aval, int *Gs_rp, int *Gs_col,
+                 double *Gs_val, double *dinv, int *bad_row)
+{
+    int o = 0;
+    *bad_row = -1;
+    Gs_rp[0] = 0;
+    for (int i = 0; i < n; i++) {
+        double aii = 0.0;
+        int has = 0;
+        for (int p = Arp[i]; p < Arp[i + 1]; p++)
+            if (Acol[p] == i) {
+                aii = Aval[p];
+                has = 1;
+            }
+        if (!has) {
+            *bad_row = i;
+            return ORC_PATTERN;
+        }
+        if (aii == 0.0 || !isfinite(aii)) {
+            *bad_row = i;
+            return ORC_ZERO_PIVOT;
+        }
+        dinv[i] = 1.0 / aii;
+        for (int p = Arp[i]; p < Arp[i + 1]; p++) {
+            if (Acol[p] >= i) continue;
+            Gs_col[o] = Acol[p];
+            Gs_val[o] = Aval[p] / aii;
+            o++;
+        }
+        Gs_rp[i + 1] = o;
+    }
+    return ORC_OK;
+}
+
+/* The smoother, `outer` steps on x (in/out):
+ *   r = b - A x;  s = dinv * r;  y = m Richardson steps on (I + Gs) y = s;
+ *   x = x + y.
+ * mixed = 1: r stays FP64 and is rounded to FP32, s = (float)(dinv *
+ * (double)(float)r), the Richardson loop runs in FP32 on FP32 copies of the
+ * Gs values (as in orc_smooth_mixed), x = x + (double)y.
+ * ws: 3n doubles; fws: 3n floats (mixed only, else may be NULL). */
+void orc_gs_smooth(int n, const int *Arp, const int *Acol, const double *Aval, const int *Grp, const int *Gcol,
+                   const double *Gval, const double *dinv, const double *b, double *x, int outer, int m, int mixed,
+                   double *ws, float *fws)
+{
+    double *r = ws, *y = ws + n, *tmp = ws + 2 * (size_t)n;
+    for (int it = 0; it < outer; it++) {
+        orc_residual(n, Arp, Acol, Aval, b, x, r);
+        if (mixed) {
+            float *sf = fws, *yf = fws + n, *tf = fws + 2 * (size_t)n;
+            for (int i = 0; i < n; i++) sf[i] = (float)(dinv[i] * (double)(float)r[i]);
+            orc_richardson_f32(n, Grp, Gcol, Gval, sf, m, yf, tf);
+            for (int i = 0; i < n; i++) x[i] = x[i] + (double)yf[i];
+        } else {
+            for (int i = 0; i < n; i++) r[i] = dinv[i] * r[i];
+            orc_richardson(n, Grp, Gcol, Gval, r, m, y, tmp);
+            for (int i = 0; i < n; i++) x[i] = x[i] + y[i];
+        }
+    }
+}
+
 /* Euclidean norm, summed in index order. */
 double orc_nrm2(int n, const double *v)
 {

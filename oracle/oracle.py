@@ -64,6 +64,10 @@ def lib():
                                         _f64p, _f64p, _f64p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, _f64p,
                                         _f32p]
         L.orc_smooth_rowcol.restype = None
+        L.orc_gs_split.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, C.POINTER(C.c_int)]
+        L.orc_gs_smooth.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
+                                    C.c_int, C.c_int, C.c_int, _f64p, _f32p]
+        L.orc_gs_smooth.restype = None
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_spmv.restype = None
         L.orc_residual.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
@@ -235,6 +239,34 @@ def smooth_rowcol(A, Ls, Us_hat, dr, dc, b, x0, outer: int, mL: int, mU: int, mi
     lib().orc_smooth_rowcol(n, A.row_ptr, A.col, A.val, Ls.row_ptr, Ls.col, Ls.val, Us_hat.row_ptr, Us_hat.col,
                             Us_hat.val, np.ascontiguousarray(dr, np.float64), np.ascontiguousarray(dc, np.float64),
                             np.ascontiguousarray(b, np.float64), x, int(outer), int(mL), int(mU), mode, ws, fws)
+    return x
+
+
+def gs_split(A):
+    """Polynomial Gauss-Seidel set-up: (Gs = D^{-1} L strictly lower, dinv = 1/diag(A))."""
+    A = _mat(A)
+    n = A.n
+    rp = np.empty(n + 1, np.int32)
+    col = np.empty(max(A.nnz, 1), np.int32)
+    val = np.empty(max(A.nnz, 1))
+    dinv = np.empty(n)
+    bad = C.c_int(-1)
+    st = lib().orc_gs_split(n, A.row_ptr, A.col, A.val, rp, col, val, dinv, C.byref(bad))
+    if st:
+        raise OracleError(st, bad.value, "Gauss-Seidel split")
+    nnz = int(rp[-1])
+    return Mat(n, rp, col[:nnz].copy(), val[:nnz].copy()), dinv
+
+
+def gs_smooth(A, Gs, dinv, b, x0, outer: int, m: int, mixed: bool = False):
+    """Polynomial Gauss-Seidel smoother: x += sum_{j<m} (-D^{-1}L)^j D^{-1}(b - A x), `outer` times."""
+    A, Gs = _mat(A), _mat(Gs)
+    n = A.n
+    x = np.array(x0, dtype=np.float64, copy=True)
+    ws = np.empty(3 * n)
+    fws = np.empty(3 * n, np.float32)
+    lib().orc_gs_smooth(n, A.row_ptr, A.col, A.val, Gs.row_ptr, Gs.col, Gs.val, np.ascontiguousarray(dinv, np.float64),
+                        np.ascontiguousarray(b, np.float64), x, int(outer), int(m), int(bool(mixed)), ws, fws)
     return x
 
 
