@@ -9,8 +9,10 @@ fused D^{-1}, U sweeps with fused x update, twice).  `value` is FP64 smoother
 applications per second with every input resident in HBM.  In the same run,
 and reported in the same JSON line: the level-scheduled direct form (the same
 smoother with both triangular solves done by level-set substitution), the
-FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, a
-streaming-copy bandwidth calibration, the roofline of
+FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, the
+polynomial Gauss-Seidel smoother (time and residual after one application
+beside the ILU smoother's), a streaming-copy bandwidth calibration, the
+roofline of
 the dominant kernel from per-launch HIP events, and the CPU oracle timed on a
 bounded sample of the same operator, and the serving stream (1,280 requests
 on 64 resident matrices, continuous batching vs one at a time).
@@ -155,6 +157,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-rowcol", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-gs", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -259,6 +262,30 @@ def main():
                   "bytes_per_app": bytes_rc, "ruiz_iters": 5, "rel_diff_vs_row_scaling": rc_err}
         del Frc
 
+    # ---- polynomial Gauss-Seidel smoother (the paper's comparison smoother) ----
+    gs = None
+    if not args.no_gs:
+        import scipy.sparse as sp
+
+        G = ctx.gs_split(Ad)
+
+        def app_gs():
+            x.zero_()
+            ctx.gs_smooth(Ad, G, bvec, x, outer, mL, kernel=kern, ws=ws)
+
+        ms_gs, bytes_gs, _ = timed(app_gs, "gs")
+        # smoothing quality: relative residual after one application from x = 0 (host SpMV, measurement only)
+        Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(n, n))
+        bh = bvec.cpu().numpy()
+        nb = float(np.linalg.norm(bh))
+        res_gs = float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / nb)
+        res_ilu = float(np.linalg.norm(bh - Ah @ x64.cpu().numpy()) / nb)
+        log(f"gs: relative residual after one application {res_gs:.3e} (ILU smoother {res_ilu:.3e})")
+        gs = {"apps_per_s": 1e3 / ms_gs, "ms": ms_gs, "GBps": bytes_gs / (ms_gs * 1e-3) / 1e9,
+              "bytes_per_app": bytes_gs, "outer": outer, "terms": mL, "relres_after_one_app": res_gs,
+              "ilu_relres_after_one_app": res_ilu}
+        del G, Ah
+
     # ---- direct (level-scheduled) form ----
     ms_direct = None
     depths = None
@@ -316,6 +343,7 @@ def main():
         "mixed_bytes_per_app": bytes_mixed,
         "mixed_rel_diff_vs_f64": mixed_err,
         "rowcol": rowcol,
+        "gauss_seidel": gs,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,

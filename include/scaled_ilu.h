@@ -99,7 +99,7 @@ typedef struct {
  *   Ls_val32 optional FP32 copy of Ls.val (round to nearest even), or NULL
  *   Us_val32 optional FP32 copy of Us.val, or NULL
  *   scaled   1 after row scaling, 0 with SILU_NO_SCALING, 2 after
- *            row/column scaling
+ *            row/column scaling, 3 for the Gauss-Seidel split (gs_scale_split)
  *   dc       column factors d_c [n] (scaled == 2: the smoother adds d_c * v
  *            to x, v the U^ iterate), else ignored (may be NULL)
  */
@@ -242,6 +242,42 @@ int ilu_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const do
 /* Same with separate inner iteration counts for the L and the U factor. */
 int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
                 int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes);
+
+/* ---- polynomial Gauss-Seidel smoother (Section 2) ------------------------ */
+
+/*
+ * The polynomial smoother the paper compares the ILU smoother with:
+ * Gauss-Seidel's (D + L)^{-1} (D = diag(A), L = strictly lower part of A)
+ * written as (I + D^{-1}L)^{-1} D^{-1}, the inverse replaced by a truncated
+ * Neumann series of `terms` terms (terms = p + 1 for the paper's sum over
+ * j = 0..p):
+ *   x <- x + sum_{j<terms} (-D^{-1}L)^j D^{-1} (b - A x).
+ *
+ * gs_split_size: the number of strictly lower entries of A (synchronous).
+ * gs_scale_split: writes G->Ls = D^{-1} L (row_ptr [n+1], col_idx and val
+ * [that count], caller-allocated; g_ij = a_ij / a_ii, one IEEE division
+ * each), G->d = diag(A), G->dinv = 1 / diag(A), G->Ls_val32 if non-NULL (FP32
+ * copy), G->Us = an empty n x n matrix, G->scaled = 3.  Synchronous.
+ * Errors (both): ARG, SHAPE, PATTERN (a row of A without its diagonal),
+ * ZERO_PIVOT (a_ii == 0 or not finite; silu_bad_row gives the first row).
+ */
+int gs_split_size(silu_ctx *ctx, const silu_csr *A, int64_t *nnz_lower);
+int gs_scale_split(silu_ctx *ctx, const silu_csr *A, silu_factors *G, int flags);
+
+/*
+ * `outer_sweeps` steps of the smoother on x (in/out), each
+ *   s = D^{-1}(b - A x);  y = `terms` Richardson steps on (I + D^{-1}L) y = s
+ *   from y = 0 (the first is free);  x += y.
+ * G from gs_scale_split.  flags: SILU_MIXED runs the Richardson loop on
+ * G->Ls_val32 with FP32 iterates and accumulation (the residual is computed
+ * in FP64 and rounded to FP32 before the scaling; x += y in FP64);
+ * SILU_CHECK_FINITE, SILU_VALIDATE and the layout flags as for ilu_smooth.
+ * Workspace as for ilu_smooth.  Asynchronous.  Errors: ARG (nulls,
+ * outer_sweeps or terms < 1, SILU_DIRECT, G not from gs_scale_split), SHAPE,
+ * NOMEM, UNSUPPORTED (MIXED without the FP32 copy), PATTERN, NONFINITE, HIP.
+ */
+int gs_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *G, const double *b, double *x, int outer_sweeps,
+              int terms, int flags, void *ws, size_t ws_bytes);
 
 /* ---- triangular solves ------------------------------------------------- */
 

@@ -82,6 +82,10 @@ _sig = {
     "ilu_scale_factors": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
     "ilu_scale_factors_rowcol": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_csr), C.c_int,
                                            C.POINTER(silu_factors), C.c_int]),
+    "gs_split_size": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(C.c_int64)]),
+    "gs_scale_split": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
+    "gs_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int, _P,
+                            C.c_size_t]),
     "ilu_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int,
                              _P, C.c_size_t]),
     "ilu_smooth2": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
@@ -295,6 +299,41 @@ class Context:
         self._check(_lib.ilu_scale_factors_rowcol(self._h, C.byref(Lc), C.byref(Uc), int(ruiz_iters), C.byref(Fc),
                                                   SILU_VALIDATE if validate else 0), "ilu_scale_factors_rowcol")
         return F
+
+    # ---- polynomial Gauss-Seidel ----
+    def gs_split(self, A: Csr, fp32: bool = False, validate: bool = False) -> Factors:
+        """Gs = D^{-1} L (strictly lower part of A, row-scaled), d, dinv for gs_smooth."""
+        Ac = A.c()
+        cnt = C.c_int64()
+        self._check(_lib.gs_split_size(self._h, C.byref(Ac), C.byref(cnt)), "gs_split_size")
+        n, nnz, dev = A.n, cnt.value, A.val.device
+        Gs = Csr(torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(nnz, dtype=torch.int32, device=dev),
+                 torch.empty(nnz, dtype=torch.float64, device=dev))
+        empty = Csr(torch.zeros(n + 1, dtype=torch.int32, device=dev), torch.empty(0, dtype=torch.int32, device=dev),
+                    torch.empty(0, dtype=torch.float64, device=dev))
+        G = Factors(Gs, empty, torch.empty(n, dtype=torch.float64, device=dev),
+                    torch.empty(n, dtype=torch.float64, device=dev),
+                    torch.empty(nnz, dtype=torch.float32, device=dev) if fp32 else None, None, 3)
+        Gc = G.c()
+        self._check(_lib.gs_scale_split(self._h, C.byref(Ac), C.byref(Gc), SILU_VALIDATE if validate else 0),
+                    "gs_scale_split")
+        return G
+
+    def gs_smooth(self, A: Csr, G: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, terms: int,
+                  mixed: bool = False, check_finite: bool = False, validate: bool = False, kernel: str | None = None,
+                  ws: torch.Tensor | None = None) -> torch.Tensor:
+        """x <- x + sum_{j<terms} (-D^{-1}L)^j D^{-1}(b - A x), `outer_sweeps` times, in place."""
+        flags = ((SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) |
+                 (SILU_VALIDATE if validate else 0) | KERNELS[kernel])
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        ws = self.workspace(A.n, flags) if ws is None else ws
+        self._track(A, G.Ls, values=((), (G.Ls_val32,)))
+        Ac, Gc = A.c(), G.c()
+        self._check(_lib.gs_smooth(self._h, C.byref(Ac), C.byref(Gc), C.c_void_p(b.data_ptr()),
+                                   C.c_void_p(x.data_ptr()), outer_sweeps, terms, flags, C.c_void_p(ws.data_ptr()),
+                                   ws.numel()), "gs_smooth")
+        return x
 
     # ---- the smoother ----
     def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,

@@ -1012,6 +1012,141 @@ int ilu_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *F, const doub
     return ilu_smooth2(c, A, F, b, x, outer_sweeps, inner_iters, inner_iters, flags, ws, ws_bytes);
 }
 
+// ---- polynomial Gauss-Seidel smoother --------------------------------------
+namespace {
+
+// Strictly-lower counts of A's rows on the host (copied down), with the
+// pattern and pivot checks.
+int gs_counts(silu_ctx *c, const silu_csr *A, std::vector<int32_t> &counts)
+{
+    const int64_t n = A->n_rows;
+    counts.assign((size_t)n, 0);
+    if (n == 0) return SILU_OK;
+    int32_t *d_counts = nullptr;
+    HIPCHK(c, hipMalloc(&d_counts, (size_t)n * 4));
+    hipError_t e = launch_init_flags(c->d_flags, 4, INT32_MAX, c->stream);
+    if (e == hipSuccess)
+        e = launch_gs_count((int)n, A->row_ptr, A->col_idx, (const double *)A->val, d_counts, c->d_flags, c->stream);
+    int32_t h[4];
+    if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), d_counts, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, c->d_flags, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_counts);
+    if (e != hipSuccess) return hip_fail(c, e);
+    if (h[0] != INT32_MAX) {
+        c->bad_row = h[0];
+        return SILU_ERR_PATTERN;
+    }
+    if (h[1] != INT32_MAX) {
+        c->bad_row = h[1];
+        return SILU_ERR_ZERO_PIVOT;
+    }
+    return SILU_OK;
+}
+
+} // namespace
+
+int gs_split_size(silu_ctx *c, const silu_csr *A, int64_t *nnz_lower)
+{
+    if (!c || !A || !nnz_lower) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    std::vector<int32_t> counts;
+    if ((st = gs_counts(c, A, counts))) return st;
+    int64_t t = 0;
+    for (int32_t v : counts) t += v;
+    *nnz_lower = t;
+    return SILU_OK;
+}
+
+int gs_scale_split(silu_ctx *c, const silu_csr *A, silu_factors *G, int flags)
+{
+    if (!c || !A || !G) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    const int64_t n = A->n_rows;
+    if (!G->Ls.row_ptr || !G->d || !G->dinv) return SILU_ERR_ARG;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+    }
+    std::vector<int32_t> counts;
+    if ((st = gs_counts(c, A, counts))) return st;
+    std::vector<int32_t> rp((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; i++) rp[(size_t)i + 1] = rp[(size_t)i] + counts[(size_t)i];
+    const int64_t nnz = rp[(size_t)n];
+    if (nnz > 0 && (!G->Ls.col_idx || !G->Ls.val)) return SILU_ERR_ARG;
+    // cached copies of earlier values in the output arrays are stale from here on
+    if ((st = silu_release(c, G->Ls.row_ptr, G->Ls.col_idx))) return st;
+    G->Ls.n_rows = G->Ls.n_cols = n;
+    G->Ls.nnz = nnz;
+    G->Ls.dtype = SILU_F64;
+    G->Us.n_rows = G->Us.n_cols = n;
+    G->Us.nnz = 0;
+    G->Us.dtype = SILU_F64;
+    G->scaled = 3;
+    HIPCHK(c, hipMemcpyAsync(G->Ls.row_ptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_gs_fill((int)n, A->row_ptr, A->col_idx, (const double *)A->val, G->Ls.row_ptr, G->Ls.col_idx,
+                             (double *)G->Ls.val, G->d, G->dinv, G->Ls_val32, (int32_t)nnz, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream)); // rp goes out of scope
+    return SILU_OK;
+}
+
+int gs_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *G, const double *b, double *x, int outer_sweeps,
+              int terms, int flags, void *ws, size_t ws_bytes)
+{
+    if (!c || !A || !G || !b || !x || !ws) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    const bool mixed = (flags & SILU_MIXED) != 0;
+    if (outer_sweeps < 1 || terms < 1 || (flags & SILU_DIRECT)) return SILU_ERR_ARG;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    if ((st = check_square(&G->Ls, SILU_F64))) return st;
+    const int64_t n = A->n_rows;
+    if (G->Ls.n_rows != n) return SILU_ERR_SHAPE;
+    if (G->scaled != 3 || !G->dinv) return SILU_ERR_ARG;
+    if (mixed && G->Ls.nnz > 0 && !G->Ls_val32) return SILU_ERR_UNSUPPORTED;
+    if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
+    size_t need = 0;
+    silu_workspace_size(c, n, flags, &need);
+    if (ws_bytes < need) return SILU_ERR_NOMEM;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+        if ((st = validate(c, &G->Ls, -1))) return st;
+    }
+    Ws w{(char *)ws, ws_vec_bytes(n)};
+    void *s = w.slot(1), *tmp[2] = {w.slot(2), w.slot(3)};
+    const SweepGeom gA = pick_geom(n, A->nnz, flags), gG = pick_geom(n, G->Ls.nnz, flags);
+    const Prec pG = mixed ? Prec::MIX_U : Prec::F64;
+    const void *Gval = mixed ? (const void *)G->Ls_val32 : G->Ls.val;
+    for (int it = 0; it < outer_sweeps; it++) {
+        // s = D^{-1} (b - A x)  (mixed: the residual rounded to FP32, then scaled, in FP32)
+        st = sweep(c, mixed ? Prec::MIX_RES : Prec::F64, gA, A, A->val, x, b, EPI_SCALE, s, G->dinv, nullptr,
+                   nullptr);
+        if (st) return st;
+        if (terms == 1) {
+            st = timed_launch(c, 24.0 * (double)n, [&](const char **nm) {
+                *nm = "axpy";
+                return launch_axpy((int)n, s, mixed ? 1 : 0, nullptr, x, c->stream);
+            });
+            if (st) return st;
+            continue;
+        }
+        // y_1 = s;  y_k = s - Gs y_{k-1};  the last adds y to x
+        const void *cur = s;
+        for (int k = 2; k <= terms; k++) {
+            const bool last = k == terms;
+            void *out = last ? nullptr : tmp[k & 1];
+            st = sweep(c, pG, gG, &G->Ls, Gval, cur, s, last ? EPI_UPDATE : EPI_STORE, out, G->dinv, x, nullptr);
+            if (st) return st;
+            cur = out;
+        }
+    }
+    if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
+    return SILU_OK;
+}
+
 int trisolve_direct(silu_ctx *c, const silu_csr *T, int uplo, int diag, const double *rhs, double *out, int flags)
 {
     if (!c || !T || !rhs || !out || rhs == out) return SILU_ERR_ARG;

@@ -102,6 +102,13 @@ hipError_t launch_mark_offsets(int n, const int32_t *rp, const int32_t *col, int
                                hipStream_t s);
 hipError_t launch_encode_slots(int n, const int32_t *rp, const int32_t *col, int rpb, int lo, const int32_t *slot_of,
                                uint16_t *code, hipStream_t s);
+// Polynomial Gauss-Seidel set-up: strictly-lower counts (with pattern and
+// pivot flags), then Gs = D^{-1} L, d and dinv.
+hipError_t launch_gs_count(int n, const int32_t *rp, const int32_t *col, const double *val, int32_t *counts,
+                           int32_t *flags, hipStream_t s);
+hipError_t launch_gs_fill(int n, const int32_t *rp, const int32_t *col, const double *val, const int32_t *Grp,
+                          int32_t *Gcol, double *Gval, double *d, double *dinv, float *G32, int32_t gs_nnz,
+                          hipStream_t s);
 // Sliced-ELL set-up: per-slice K and mask bit; fill values and codes.
 hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, hipStream_t s);
 hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,

@@ -307,6 +307,60 @@ __global__ void __launch_bounds__(256) k_compress16(int n, const int32_t *__rest
 
 inline int blocks_for(int64_t n, int per) { return (int)((n + per - 1) / per); }
 
+// ---- polynomial Gauss-Seidel split: Gs = D^{-1} L, dinv = 1/diag(A) ---------
+// counts[i] = entries of row i left of the diagonal; flags[0] <- the first
+// row without a stored diagonal, flags[1] <- the first zero or non-finite one.
+__global__ void __launch_bounds__(256) k_gs_count(int n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  int32_t *__restrict__ counts, int32_t *flags)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    int c = 0;
+    bool has = false;
+    double aii = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = col[p];
+        if (j < i) ++c;
+        if (j == i) {
+            has = true;
+            aii = val[p];
+        }
+    }
+    counts[i] = c;
+    if (!has) atomicMin(&flags[0], i);
+    else if (!(aii != 0.0) || !isfinite(aii)) atomicMin(&flags[1], i);
+}
+
+// Row i of Gs: g_ij = a_ij / a_ii for j < i (one IEEE division each), at
+// Gs_rp[i]..; stores bounded by gs_nnz.
+__global__ void __launch_bounds__(256) k_gs_fill(int n, const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 const int32_t *__restrict__ Grp, int32_t *__restrict__ Gcol,
+                                                 double *__restrict__ Gval, double *__restrict__ d,
+                                                 double *__restrict__ dinv, float *__restrict__ G32, int32_t gs_nnz)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    double aii = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (col[p] == i) aii = val[p];
+    d[i] = aii;
+    dinv[i] = 1.0 / aii;
+    int o = Grp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = col[p];
+        if (j >= i) continue;
+        if (o >= 0 && o < gs_nnz) {
+            const double g = val[p] / aii;
+            Gcol[o] = j;
+            Gval[o] = g;
+            if (G32) G32[o] = (float)g;
+        }
+        ++o;
+    }
+}
+
 // ---- sliced-ELL copies (64-row slices, one wavefront per slice) ------------
 // Slice s holds rows [64 s, 64 s + 64) and K4 = (its longest row rounded up
 // to a multiple of 4) slots per row, in groups of four entries so that a lane
@@ -552,6 +606,25 @@ hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_
         else SILU_FILL(float, 4);
     }
 #undef SILU_FILL
+    return hipGetLastError();
+}
+
+
+hipError_t launch_gs_count(int n, const int32_t *rp, const int32_t *col, const double *val, int32_t *counts,
+                           int32_t *flags, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gs_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, val, counts, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_fill(int n, const int32_t *rp, const int32_t *col, const double *val, const int32_t *Grp,
+                          int32_t *Gcol, double *Gval, double *d, double *dinv, float *G32, int32_t gs_nnz,
+                          hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gs_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, rp, col, val, Grp, Gcol, Gval, d, dinv,
+                       G32, gs_nnz);
     return hipGetLastError();
 }
 
