@@ -896,6 +896,113 @@ int orc_smooth_until(int n, const int *Arp, const int *Acol, const double *Aval,
 }
 
 /* =========================================================================
+ * FGMRES(m) with the ILU smoother as right preconditioner (Section 6: the
+ * paper's Krylov solver is flexible GMRES [Saad03], stopped on the relative
+ * residual of eq. relres).  Arnoldi with modified Gram-Schmidt; the small
+ * least-squares problem is solved with Givens rotations, whose last entry
+ * |g_{j+1}| is the residual norm of the current iterate:
+ *   r0 = b - A x0, beta = ||r0||, v1 = r0 / beta, g = beta e1
+ *   for j = 1..m:
+ *     z_j = M^{-1} v_j            (one smoother call from z = 0: `outer`
+ *                                  steps of orc_smooth with m_L, m_U)
+ *     w = A z_j
+ *     for i = 1..j: h_ij = (w, v_i); w = w - h_ij v_i
+ *     h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}
+ *     apply the previous rotations to column j, make the new one, update g
+ *     stop when |g_{j+1}| / ||b|| < tol (or h_{j+1,j} == 0)
+ *   y = the solution of the triangular system H y = g;  x = x0 + sum_i y_i z_i
+ *   restart from x while not converged and fewer than max_iters steps.
+ * Dot products and norms are summed in index order.  hist[k] receives the
+ * relative residual estimate after k steps (hist[0] = ||b - A x0|| / ||b||);
+ * returns the number of steps taken.  ws: (2m + 7) n + (m + 1)(m + 4) doubles.
+ * ========================================================================= */
+static double orc_dot(int n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s = s + a[i] * b[i];
+    return s;
+}
+
+int orc_fgmres(int n, const int *Arp, const int *Acol, const double *Aval,
+               const int *Lrp, const int *Lcol, const double *Lval,
+               const int *Urp, const int *Ucol, const double *Uval, const double *dinv,
+               int outer, int mL, int mU, const double *b, double *x, int m, int max_iters, double tol,
+               double *hist, double *ws)
+{
+    const size_t N = (size_t)n;
+    double *V = ws;                          /* (m + 1) n */
+    double *Z = V + (size_t)(m + 1) * N;     /* m n */
+    double *w = Z + (size_t)m * N;           /* n */
+    double *sws = w + N;                     /* 5 n for the smoother */
+    double *H = sws + 5 * N;                 /* (m + 1) m, column-major: H[i + (m + 1) j] */
+    double *cs = H + (size_t)(m + 1) * m;    /* m */
+    double *sn = cs + m;                     /* m */
+    double *g = sn + m;                      /* m + 1 */
+    double *y = g + m + 1;                   /* m */
+    const double nb = orc_nrm2(n, b);
+    int k = 0;
+    orc_residual(n, Arp, Acol, Aval, b, x, V);
+    double beta = orc_nrm2(n, V);
+    hist[0] = beta / nb;
+    if (hist[0] < tol) return 0;
+    while (k < max_iters) {
+        for (int i = 0; i < n; i++) V[i] = V[i] / beta;
+        for (int i = 0; i <= m; i++) g[i] = 0.0;
+        g[0] = beta;
+        int j = 0, done = 0;
+        for (; j < m && k < max_iters; j++) {
+            double *vj = V + (size_t)j * N, *zj = Z + (size_t)j * N, *vn = V + (size_t)(j + 1) * N;
+            for (int i = 0; i < n; i++) zj[i] = 0.0;
+            orc_smooth(n, Arp, Acol, Aval, Lrp, Lcol, Lval, Urp, Ucol, Uval, dinv, vj, zj, outer, mL, mU, 0, sws);
+            orc_spmv(n, Arp, Acol, Aval, zj, w);
+            double *h = H + (size_t)(m + 1) * j;
+            for (int i = 0; i <= j; i++) {
+                const double *vi = V + (size_t)i * N;
+                h[i] = orc_dot(n, w, vi);
+                for (int t = 0; t < n; t++) w[t] = w[t] - h[i] * vi[t];
+            }
+            h[j + 1] = orc_nrm2(n, w);
+            if (h[j + 1] != 0.0)
+                for (int t = 0; t < n; t++) vn[t] = w[t] / h[j + 1];
+            /* previous rotations, then the new one */
+            for (int i = 0; i < j; i++) {
+                const double a = h[i], c = h[i + 1];
+                h[i] = cs[i] * a + sn[i] * c;
+                h[i + 1] = -sn[i] * a + cs[i] * c;
+            }
+            const double den = sqrt(h[j] * h[j] + h[j + 1] * h[j + 1]);
+            cs[j] = h[j] / den;
+            sn[j] = h[j + 1] / den;
+            h[j] = den;
+            h[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k++;
+            hist[k] = fabs(g[j + 1]) / nb;
+            if (hist[k] < tol || den == 0.0) {
+                done = 1;
+                j++;
+                break;
+            }
+        }
+        /* y = H^{-1} g (upper triangular, j x j), x = x + Z y */
+        for (int i = j - 1; i >= 0; i--) {
+            double t = g[i];
+            for (int c2 = i + 1; c2 < j; c2++) t = t - H[i + (size_t)(m + 1) * c2] * y[c2];
+            y[i] = t / H[i + (size_t)(m + 1) * i];
+        }
+        for (int i = 0; i < j; i++) {
+            const double *zi = Z + (size_t)i * N;
+            for (int t = 0; t < n; t++) x[t] = x[t] + y[i] * zi[t];
+        }
+        if (done) break;
+        orc_residual(n, Arp, Acol, Aval, b, x, V);
+        beta = orc_nrm2(n, V);
+    }
+    return k;
+}
+
+/* =========================================================================
  * Level sets of a triangular factor's elimination DAG (Section 4: level-set
  * scheduling).  level_i = 0 when row i depends on no other row, else
  * 1 + max level of the rows it reads.  uplo 0: lower (j < i), 1: upper.

@@ -68,6 +68,8 @@ def lib():
         L.orc_gs_smooth.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p,
                                     C.c_int, C.c_int, C.c_int, _f64p, _f32p]
         L.orc_gs_smooth.restype = None
+        L.orc_fgmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p,
+                                 C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int, C.c_int, C.c_double, _f64p, _f64p]
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_spmv.restype = None
         L.orc_residual.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
@@ -268,6 +270,21 @@ def gs_smooth(A, Gs, dinv, b, x0, outer: int, m: int, mixed: bool = False):
     lib().orc_gs_smooth(n, A.row_ptr, A.col, A.val, Gs.row_ptr, Gs.col, Gs.val, np.ascontiguousarray(dinv, np.float64),
                         np.ascontiguousarray(b, np.float64), x, int(outer), int(m), int(bool(mixed)), ws, fws)
     return x
+
+
+def fgmres(A, Ls, Us, dinv, b, x0, m: int, max_iters: int, tol: float, outer: int = 1, mL: int = 3, mU: int = 3):
+    """FGMRES(m) with the ILU smoother (outer steps x m_L/m_U from z = 0) as right
+    preconditioner, stopped when the relative residual estimate drops below tol
+    (eq. relres).  Returns (steps, x, history of relative residual estimates)."""
+    A, Ls, Us = _mat(A), _mat(Ls), _mat(Us)
+    n = A.n
+    x = np.array(x0, dtype=np.float64, copy=True)
+    ws = np.empty((2 * m + 7) * n + (m + 1) * (m + 4))
+    hist = np.zeros(max_iters + 1)
+    k = lib().orc_fgmres(n, A.row_ptr, A.col, A.val, Ls.row_ptr, Ls.col, Ls.val, Us.row_ptr, Us.col, Us.val,
+                         np.ascontiguousarray(dinv, np.float64), int(outer), int(mL), int(mU),
+                         np.ascontiguousarray(b, np.float64), x, int(m), int(max_iters), float(tol), hist, ws)
+    return k, x, hist[: k + 1].copy()
 
 
 def spmv(N, x):

@@ -1,0 +1,94 @@
+"""Pins for the oracle's FGMRES with the ILU smoother as right preconditioner
+(Section 6: flexible GMRES around the smoother; eq. relres stopping rule;
+eq. nbre reported).  CPU only.
+
+With the FP64 smoother started from zero the preconditioner is a fixed
+matrix P (column i = the smoother applied to e_i), so FGMRES after k steps
+is the minimal-residual iterate over x0 + P K_k(A P, r0): pinned by brute
+force on small matrices."""
+import numpy as np
+import pytest
+
+from paper_2111_09512_amd import workloads as W
+
+
+def _factors(orc, A, kind="ilu0", **kw):
+    if kind == "ilu0":
+        Ls, U = orc.ilu0(A)
+    else:
+        Ls, U = orc.iluk(A, kw["k"])
+    d, dinv, Us = orc.scale_rows(U)
+    return Ls, Us, dinv
+
+
+def _precond_matrix(orc, A, Ls, Us, dinv, outer, mL, mU):
+    n = A.n
+    P = np.empty((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        P[:, i] = orc.smooth(A, Ls, Us, dinv, e, np.zeros(n), outer, mL, mU)
+    return P
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 9])
+def test_minimal_residual_over_krylov_space(orc, k):
+    A = W.random_mmatrix(60, 0.08, seed=7, dominance=1.02)
+    Ls, Us, dinv = _factors(orc, A)
+    b, x0 = W.rhs(A.n, 1), W.rhs(A.n, 2) * 0.1
+    Ad = A.to_dense()
+    P = _precond_matrix(orc, A, Ls, Us, dinv, 1, 2, 2)
+    r0 = b - Ad @ x0
+    AP = Ad @ P
+    K = np.empty((A.n, k))
+    v = r0.copy()
+    for j in range(k):
+        K[:, j] = v / np.linalg.norm(v)
+        v = AP @ K[:, j]
+    c, *_ = np.linalg.lstsq(AP @ K, r0, rcond=None)
+    x_ref = x0 + P @ (K @ c)
+    res_ref = np.linalg.norm(r0 - AP @ (K @ c)) / np.linalg.norm(b)
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, x0, m=30, max_iters=k, tol=1e-300, outer=1, mL=2, mU=2)
+    assert steps == k
+    assert hist[k] == pytest.approx(res_ref, rel=1e-8)
+    np.testing.assert_allclose(x, x_ref, rtol=1e-8, atol=1e-10 * np.abs(x_ref).max())
+    true = np.linalg.norm(b - Ad @ x) / np.linalg.norm(b)
+    assert true == pytest.approx(hist[k], rel=1e-7)
+
+
+def test_exact_preconditioner_converges_in_one_step(orc):
+    """Tridiagonal: ILU(0) is the exact LU and enough Richardson steps make
+    the smoother exact, so P = A^{-1} and one FGMRES step solves."""
+    A = W.tridiag(20)
+    Ls, Us, dinv = _factors(orc, A)
+    b = W.rhs(A.n, 0)
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, np.zeros(A.n), m=10, max_iters=10, tol=1e-12, mL=20, mU=20)
+    assert steps == 1
+    np.testing.assert_allclose(x, np.linalg.solve(A.to_dense(), b), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("m", [30, 5])
+def test_converges_with_and_without_restarts(orc, m):
+    """The residual estimate is non-increasing (also across restarts) and the
+    true residual at the end agrees with it and is below tol."""
+    A = W.vardens7(8, seed_rho=3)
+    Ls, Us, dinv = _factors(orc, A, "iluk", k=1)
+    b = W.rhs(A.n, 0)
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, np.zeros(A.n), m=m, max_iters=300, tol=1e-8)
+    assert steps < 300 and hist[-1] < 1e-8
+    assert np.all(np.diff(hist) <= 1e-14)
+    true = np.linalg.norm(orc.residual(A, b, x)) / np.linalg.norm(b)
+    assert true < 1e-8 * 1.01
+    assert true == pytest.approx(hist[-1], rel=1e-4)
+    if m == 5:
+        full, _, _ = orc.fgmres(A, Ls, Us, dinv, b, np.zeros(A.n), m=30, max_iters=300, tol=1e-8)
+        assert steps >= full
+
+
+def test_initial_guess_already_converged(orc):
+    A = W.poisson7(4)
+    Ls, Us, dinv = _factors(orc, A)
+    xs = W.rhs(A.n, 3)
+    b = A.to_dense() @ xs
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, xs, m=10, max_iters=10, tol=1e-8)
+    assert steps == 0 and np.array_equal(x, xs)
