@@ -11,7 +11,8 @@ and reported in the same JSON line: the level-scheduled direct form (the same
 smoother with both triangular solves done by level-set substitution), the
 FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, the
 polynomial Gauss-Seidel smoother (time and residual after one application
-beside the ILU smoother's), a streaming-copy bandwidth calibration, the
+beside the ILU smoother's), FGMRES(30) with the smoother as preconditioner
+solved to 1e-8 (steps, time, NRBE), a streaming-copy bandwidth calibration, the
 roofline of
 the dominant kernel from per-launch HIP events, and the CPU oracle timed on a
 bounded sample of the same operator, and the serving stream (1,280 requests
@@ -158,6 +159,7 @@ def main():
     ap.add_argument("--no-rowcol", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-gs", action="store_true")
+    ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -286,6 +288,32 @@ def main():
               "ilu_relres_after_one_app": res_ilu}
         del G, Ah
 
+    # ---- FGMRES(30) with the smoother as right preconditioner, to 1e-8 (eq. relres) ----
+    krylov = None
+    if not args.no_krylov:
+        import scipy.sparse as sp
+
+        Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(n, n))
+        bh = bvec.cpu().numpy()
+        norm_a = ctx.norm2_estimate(Ad, iters=50)
+        krylov = {"restart": 30, "tol": 1e-8, "precond": "1 outer x 4/4 ILU smoother", "norm2_A_estimate": norm_a}
+        for label, mixed in (("fp64", False), ("mixed", True)):
+            x.zero_()
+            ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=5, tol=1e-8, outer=1, m_L=4, m_U=4, mixed=mixed)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=1e-8, outer=1, m_L=4, m_U=4,
+                                     mixed=mixed)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            relres = float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / np.linalg.norm(bh))
+            nrbe = ctx.nrbe(Ad, bvec, x, norm_a)
+            log(f"fgmres {label}: {steps} steps, {secs * 1e3:.1f} ms, true relres {relres:.2e}, NRBE {nrbe:.2e}")
+            krylov[label] = {"steps": steps, "seconds": secs, "ms_per_step": secs * 1e3 / max(steps, 1),
+                             "relres": relres, "nrbe": nrbe, "estimate_history_every_5": hist[::5].tolist()}
+        del Ah
+
     # ---- direct (level-scheduled) form ----
     ms_direct = None
     depths = None
@@ -344,6 +372,7 @@ def main():
         "mixed_rel_diff_vs_f64": mixed_err,
         "rowcol": rowcol,
         "gauss_seidel": gs,
+        "fgmres": krylov,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,

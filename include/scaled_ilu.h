@@ -66,6 +66,8 @@ extern "C" {
 #define SILU_NO_WINDOW 0x2000     /* sweeps never stage the iterate window in LDS            */
 #define SILU_WINDOW 0x4000        /* sweeps stage the window wherever it fits                */
 #define SILU_CODE16 0x8000        /* sliced sweeps: no diagonal table (16-bit codes or wider) */
+#define SILU_ZERO_GUESS 0x10000   /* ilu_smooth: x is zero on entry, so the first residual   */
+                                  /* is b itself (skips one pass over A when m_L >= 2)       */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -278,6 +280,39 @@ int gs_scale_split(silu_ctx *ctx, const silu_csr *A, silu_factors *G, int flags)
  */
 int gs_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *G, const double *b, double *x, int outer_sweeps,
               int terms, int flags, void *ws, size_t ws_bytes);
+
+/* ---- Krylov solver around the smoother (Section 6) ---------------------- */
+
+/*
+ * FGMRES(restart) with the ILU smoother as right preconditioner: the paper
+ * runs flexible GMRES [Saad03] stopped on the relative residual (eq.
+ * relres).  Each step applies M^{-1} as one smoother call from z = 0
+ * (`outer` steps with m_L, m_U; SILU_MIXED gives the FP32-inner form, whose
+ * rounding makes M^{-1} slightly non-linear, which the flexible variant
+ * allows), one product with A, modified Gram-Schmidt against the basis and a
+ * Givens rotation; it stops when the residual estimate |g_{j+1}| / ||b|| falls
+ * below tol (or at max_iters steps, or on breakdown), and restarts from the
+ * current x every `restart` steps.  x: initial guess in, solution out.
+ * F: row- or row/column-scaled factors.  *iters: steps taken.  hist: NULL or
+ * a host array of max_iters + 1 doubles receiving the relative residual
+ * estimates (hist[0] for the initial x).  Dot products reduce in a fixed order
+ * (reproducible; not the sequential order).  ws: at least
+ * silu_fgmres_workspace_size(ctx, n, restart) bytes (2 restart + 6
+ * n-vectors and a few KB), 256-byte aligned.  Synchronous (the small
+ * least-squares problem is solved on the host every step).  Errors: ARG,
+ * SHAPE, NOMEM, UNSUPPORTED (factors neither row- nor row/column-scaled),
+ * and those of ilu_smooth.
+ */
+int silu_fgmres_workspace_size(silu_ctx *ctx, int64_t n, int restart, int flags, size_t *bytes);
+int silu_fgmres(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x, int restart,
+                int max_iters, double tol, int outer, int m_L, int m_U, int flags, void *ws, size_t ws_bytes,
+                int *iters, double *hist);
+
+/* y = A x (FP64, the sweep kernels' layout and row order).  Asynchronous. */
+int silu_spmv(silu_ctx *ctx, const silu_csr *A, const double *x, double *y, int flags);
+/* *result = a . b over n entries, reduced in the fixed order of the Krylov
+ * solver; ws: device scratch of at least 8200 bytes.  Synchronous. */
+int silu_dot(silu_ctx *ctx, int64_t n, const double *a, const double *b, double *result, void *ws, size_t ws_bytes);
 
 /* ---- triangular solves ------------------------------------------------- */
 

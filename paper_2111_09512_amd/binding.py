@@ -32,7 +32,7 @@ SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
-SILU_CODE16 = 0x8000
+SILU_CODE16, SILU_ZERO_GUESS = 0x8000, 0x10000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
@@ -86,6 +86,12 @@ _sig = {
     "gs_scale_split": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
     "gs_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int, _P,
                             C.c_size_t]),
+    "silu_fgmres_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
+    "silu_fgmres": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
+                              C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_size_t, C.POINTER(C.c_int),
+                              C.POINTER(C.c_double)]),
+    "silu_spmv": (C.c_int, [_P, C.POINTER(silu_csr), _P, _P, C.c_int]),
+    "silu_dot": (C.c_int, [_P, C.c_int64, _P, _P, C.POINTER(C.c_double), _P, C.c_size_t]),
     "ilu_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int,
                              _P, C.c_size_t]),
     "ilu_smooth2": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
@@ -300,6 +306,68 @@ class Context:
                                                   SILU_VALIDATE if validate else 0), "ilu_scale_factors_rowcol")
         return F
 
+    # ---- Krylov solver around the smoother ----
+    def fgmres(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, restart: int = 30, max_iters: int = 300,
+               tol: float = 1e-8, outer: int = 1, m_L: int = 3, m_U: int = 3, mixed: bool = False,
+               kernel: str | None = None, check_finite: bool = False):
+        """FGMRES(restart) with the smoother as right preconditioner, in place on x.
+        Returns (steps, history of relative residual estimates)."""
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        flags = (SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) | KERNELS[kernel]
+        nb = C.c_size_t()
+        self._check(_lib.silu_fgmres_workspace_size(self._h, A.n, restart, flags, C.byref(nb)),
+                    "silu_fgmres_workspace_size")
+        if getattr(self, "_kws", None) is None or self._kws.numel() < nb.value:
+            self._kws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        hist = np.zeros(max_iters + 1)
+        it = C.c_int()
+        self._track(A, F.Ls, F.Us, values=((), (F.Ls_val32,), (F.Us_val32,)))
+        Ac, Fc = A.c(), F.c()
+        self._check(_lib.silu_fgmres(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(x.data_ptr()), restart, max_iters, tol, outer, m_L, m_U, flags,
+                                     C.c_void_p(self._kws.data_ptr()), self._kws.numel(), C.byref(it),
+                                     hist.ctypes.data_as(C.POINTER(C.c_double))), "silu_fgmres")
+        return it.value, hist[: it.value + 1].copy()
+
+    def spmv(self, A: Csr, xin: torch.Tensor, y: torch.Tensor | None = None, kernel: str | None = None):
+        """y = A x."""
+        _vec(xin, A.n, "x")
+        y = torch.empty_like(xin) if y is None else y
+        self._track(A)
+        Ac = A.c()
+        self._check(_lib.silu_spmv(self._h, C.byref(Ac), C.c_void_p(xin.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   KERNELS[kernel]), "silu_spmv")
+        return y
+
+    def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
+        if getattr(self, "_dws", None) is None:
+            self._dws = torch.empty(8448, dtype=torch.uint8, device="cuda")
+        out = C.c_double()
+        self._check(_lib.silu_dot(self._h, a.numel(), C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                  C.byref(out), C.c_void_p(self._dws.data_ptr()), self._dws.numel()), "silu_dot")
+        return out.value
+
+    def norm2_estimate(self, A: Csr, iters: int = 30, seed: int = 0) -> float:
+        """Power-iteration estimate of the largest |eigenvalue| of A (= ||A||_2 for a
+        symmetric A; a lower bound on it otherwise), for the NRBE of eq. nbre."""
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        v = (torch.rand(A.n, generator=g, dtype=torch.float64) - 0.5).cuda()
+        v /= self.dot(v, v) ** 0.5
+        lam = 0.0
+        for _ in range(iters):
+            w = self.spmv(A, v)
+            lam = self.dot(w, w) ** 0.5
+            if lam == 0.0:
+                break
+            v = w / lam
+        return lam
+
+    def nrbe(self, A: Csr, b: torch.Tensor, x: torch.Tensor, norm_a: float) -> float:
+        """Norm-wise relative backward error ||b - A x|| / (||b|| + ||A|| ||x||) (eq. nbre)."""
+        r = b - self.spmv(A, x)
+        return self.dot(r, r) ** 0.5 / (self.dot(b, b) ** 0.5 + norm_a * self.dot(x, x) ** 0.5)
+
     # ---- polynomial Gauss-Seidel ----
     def gs_split(self, A: Csr, fp32: bool = False, validate: bool = False) -> Factors:
         """Gs = D^{-1} L (strictly lower part of A, row-scaled), d, dinv for gs_smooth."""
@@ -339,10 +407,11 @@ class Context:
     def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
                    m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
                    validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None,
-                   graph: bool = True) -> torch.Tensor:
-        """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned)."""
+                   graph: bool = True, zero_guess: bool = False) -> torch.Tensor:
+        """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned).
+        zero_guess: x holds zeros on entry (the first residual is b)."""
         m_U = m_L if m_U is None else m_U
-        flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) |
+        flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) | (SILU_ZERO_GUESS if zero_guess else 0) |
                  (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
                  (0 if graph else SILU_NO_GRAPH) | KERNELS[kernel])
         _vec(b, A.n, "b")

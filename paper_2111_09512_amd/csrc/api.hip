@@ -230,7 +230,8 @@ double epi_bytes(Prec p, int64_t n, int epi, bool dshift)
     if (p == Prec::MIX_RES || p == Prec::MIX_L || p == Prec::MIX_U || p == Prec::MIX_L1) ob = 4;
     double b = 0.0;
     switch (epi) {
-    case EPI_STORE: b = n * ob; break;
+    case EPI_STORE:
+    case EPI_SPMV: b = n * ob; break;
     case EPI_SCALE: b = n * (8.0 + ob); break;
     case EPI_UPDATE: b = n * 16.0; break;
     default: b = n * 24.0; break;
@@ -571,6 +572,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, (g.off16 || g.lw) ? 2.0 : 4.0);
     if (sliced_bytes >= 0.0) // the sliced layout's own bytes: padded slots, codes, slice tables
         bytes = sliced_bytes + epi_bytes(p, N->n_rows, epi, dshift != nullptr);
+    if (epi == EPI_SPMV) bytes -= (p == Prec::MIX_U ? 4.0 : 8.0) * (double)N->n_rows; // no rhs read
     if (a.dcol) bytes += 8.0 * (double)N->n_rows;
     return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
@@ -960,8 +962,13 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
                 return st;
             continue;
         }
-        // residual r = b - A x (fused with D^{-1} when m_L = 1)
-        if (m_L >= 2) {
+        // residual r = b - A x (fused with D^{-1} when m_L = 1); with a zero
+        // guess the first one is b itself (b - A 0 = b exactly)
+        const void *rr = r;
+        if (m_L >= 2 && it == 0 && (flags & SILU_ZERO_GUESS)) {
+            rr = b;
+            st = SILU_OK;
+        } else if (m_L >= 2) {
             st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, r, nullptr, nullptr, nullptr);
         } else if (scaled) {
             st = sweep(c, mixed ? Prec::MIX_RES : Prec::F64, gA, A, A->val, x, b, EPI_SCALE, s, F->dinv, nullptr,
@@ -979,14 +986,14 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             continue;
         }
         // L sweeps: y_1 = r, y_k = r - Ls y_{k-1}
-        const void *cur = r;
+        const void *cur = rr;
         for (int k = 2; k <= m_L; k++) {
             const bool last = k == m_L;
             void *out = last ? s : tmp[k & 1];
             int epi = last ? (m_U >= 2 ? to_s : to_x) : EPI_STORE;
             // in the mixed form y_1 = (float) r is never stored: the first sweep gathers r and rounds it
             const Prec p = (mixed && k == 2) ? Prec::MIX_L1 : pL;
-            st = sweep(c, p, gL, &F->Ls, Lval, cur, r, epi, (epi == EPI_SCALE || epi == EPI_STORE) ? out : nullptr,
+            st = sweep(c, p, gL, &F->Ls, Lval, cur, rr, epi, (epi == EPI_SCALE || epi == EPI_STORE) ? out : nullptr,
                        F->dinv, x, nullptr, dcol);
             if (st) return st;
             cur = out;
@@ -1144,6 +1151,175 @@ int gs_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *G, const doubl
         }
     }
     if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
+    return SILU_OK;
+}
+
+// ---- FGMRES with the smoother as right preconditioner -----------------------
+namespace {
+
+struct KrylovWs {
+    size_t vec;     // bytes of one n-vector slot
+    char *base;
+    int m;
+    double *V(int i) const { return (double *)(base + vec * (size_t)i); }               // i = 0..m
+    double *Z(int i) const { return (double *)(base + vec * (size_t)(m + 1 + i)); }     // i = 0..m-1
+    double *w() const { return (double *)(base + vec * (size_t)(2 * m + 1)); }
+    void *smoother() const { return base + vec * (size_t)(2 * m + 2); }                 // 4 slots
+    double *part() const { return (double *)(base + vec * (size_t)(2 * m + 6)); }      // DOT_BLOCKS
+    double *h() const { return part() + DOT_BLOCKS; }                                    // m + 2 scalars
+};
+
+size_t krylov_ws_bytes(int64_t n, int m)
+{
+    const size_t vec = ws_vec_bytes(n);
+    return vec * (size_t)(2 * m + 6) + ((size_t)DOT_BLOCKS + (size_t)m + 2) * sizeof(double) + 256;
+}
+
+} // namespace
+
+int silu_fgmres_workspace_size(silu_ctx *c, int64_t n, int restart, int flags, size_t *bytes)
+{
+    (void)flags;
+    if (!c || !bytes || n < 0 || restart < 1) return SILU_ERR_ARG;
+    *bytes = krylov_ws_bytes(n, restart);
+    return SILU_OK;
+}
+
+int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x, int restart,
+                int max_iters, double tol, int outer, int m_L, int m_U, int flags, void *ws, size_t ws_bytes,
+                int *iters, double *hist)
+{
+    if (!c || !A || !F || !b || !x || !ws || !iters) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    if (restart < 1 || max_iters < 0 || !(tol >= 0.0) || outer < 1 || m_L < 1 || m_U < 1) return SILU_ERR_ARG;
+    if (F->scaled != 1 && F->scaled != 2) return SILU_ERR_UNSUPPORTED;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    const int64_t n = A->n_rows;
+    if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
+    if (ws_bytes < krylov_ws_bytes(n, restart)) return SILU_ERR_NOMEM;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+    }
+    const int m = restart;
+    KrylovWs K{ws_vec_bytes(n), (char *)ws, m};
+    const size_t sws_bytes = 4 * K.vec;
+    const int pflags = (flags & ~(SILU_CHECK_FINITE | SILU_VALIDATE | SILU_DIRECT)) | SILU_ZERO_GUESS;
+    const SweepGeom gA = pick_geom(n, A->nnz, flags);
+    auto dot = [&](const double *a, const double *bb, double *out, bool root) {
+        return timed_launch(c, 16.0 * (double)n, [&](const char **nm) {
+            *nm = "dot";
+            return launch_dot(n, a, bb, K.part(), out, root, c->stream);
+        });
+    };
+    auto fetch = [&](double *host, const double *dev, int count) -> int {
+        HIPCHK(c, hipMemcpyAsync(host, dev, sizeof(double) * (size_t)count, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SILU_OK;
+    };
+    std::vector<double> H((size_t)(m + 1) * (size_t)m), cs((size_t)m), sn((size_t)m), g((size_t)m + 1),
+        y((size_t)m), hcol((size_t)m + 2);
+    double nb = 0.0, beta = 0.0;
+    // ||b|| and the first residual
+    if ((st = dot(b, b, K.h(), true))) return st;
+    if ((st = fetch(&nb, K.h(), 1))) return st;
+    if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, K.V(0), nullptr, nullptr, nullptr))) return st;
+    if ((st = dot(K.V(0), K.V(0), K.h(), true))) return st;
+    if ((st = fetch(&beta, K.h(), 1))) return st;
+    int k = 0;
+    if (hist) hist[0] = beta / nb;
+    if (!(beta / nb >= tol)) { // converged (or b = 0)
+        *iters = 0;
+        return SILU_OK;
+    }
+    while (k < max_iters) {
+        HIPCHK(c, launch_div_host(n, K.V(0), beta, K.V(0), c->stream));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && k < max_iters; j++) {
+            double *zj = K.Z(j), *w = K.w();
+            // z_j = M^{-1} v_j: one smoother call from z = 0
+            HIPCHK(c, launch_fill((int)n, zj, 0.0, nullptr, 0.0, c->stream));
+            if ((st = ilu_smooth2(c, A, F, K.V(j), zj, outer, m_L, m_U, pflags, K.smoother(), sws_bytes))) return st;
+            // w = A z_j, then modified Gram-Schmidt against v_0..v_j
+            if ((st = sweep(c, Prec::F64, gA, A, A->val, zj, nullptr, EPI_SPMV, w, nullptr, nullptr, nullptr)))
+                return st;
+            for (int i = 0; i <= j; i++) {
+                if ((st = dot(w, K.V(i), K.h() + i, false))) return st;
+                st = timed_launch(c, 24.0 * (double)n, [&](const char **nm) {
+                    *nm = "mgs_update";
+                    return launch_sub_scaled(n, w, K.V(i), K.h() + i, c->stream);
+                });
+                if (st) return st;
+            }
+            if ((st = dot(w, w, K.h() + j + 1, true))) return st;
+            if ((st = fetch(hcol.data(), K.h(), j + 2))) return st;
+            double *h = &H[(size_t)(m + 1) * (size_t)j];
+            for (int i = 0; i <= j + 1; i++) h[i] = hcol[(size_t)i];
+            if (h[j + 1] != 0.0) HIPCHK(c, launch_div_dev(n, w, K.h() + j + 1, K.V(j + 1), c->stream));
+            // Givens rotations on the new column (host; m is small)
+            for (int i = 0; i < j; i++) {
+                const double a0 = h[i], a1 = h[i + 1];
+                h[i] = cs[(size_t)i] * a0 + sn[(size_t)i] * a1;
+                h[i + 1] = -sn[(size_t)i] * a0 + cs[(size_t)i] * a1;
+            }
+            const double den = std::sqrt(h[j] * h[j] + h[j + 1] * h[j + 1]);
+            cs[(size_t)j] = h[j] / den;
+            sn[(size_t)j] = h[j + 1] / den;
+            h[j] = den;
+            h[j + 1] = 0.0;
+            g[(size_t)j + 1] = -sn[(size_t)j] * g[(size_t)j];
+            g[(size_t)j] = cs[(size_t)j] * g[(size_t)j];
+            k++;
+            const double est = std::fabs(g[(size_t)j + 1]) / nb;
+            if (hist) hist[k] = est;
+            if (est < tol || den == 0.0) {
+                done = true;
+                j++;
+                break;
+            }
+        }
+        // y = H^{-1} g, x = x + sum_i y_i z_i
+        for (int i = j - 1; i >= 0; i--) {
+            double t = g[(size_t)i];
+            for (int c2 = i + 1; c2 < j; c2++) t = t - H[(size_t)i + (size_t)(m + 1) * (size_t)c2] * y[(size_t)c2];
+            y[(size_t)i] = t / H[(size_t)i + (size_t)(m + 1) * (size_t)i];
+        }
+        for (int i = 0; i < j; i++) HIPCHK(c, launch_axpy_host(n, y[(size_t)i], K.Z(i), x, c->stream));
+        if (done) break;
+        if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, K.V(0), nullptr, nullptr, nullptr))) return st;
+        if ((st = dot(K.V(0), K.V(0), K.h(), true))) return st;
+        if ((st = fetch(&beta, K.h(), 1))) return st;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *iters = k;
+    if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
+    return SILU_OK;
+}
+
+int silu_spmv(silu_ctx *c, const silu_csr *A, const double *xin, double *y, int flags)
+{
+    if (!c || !A || !xin || !y || xin == y) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+    }
+    return sweep(c, Prec::F64, pick_geom(A->n_rows, A->nnz, flags), A, A->val, xin, nullptr, EPI_SPMV, y, nullptr,
+                 nullptr, nullptr);
+}
+
+int silu_dot(silu_ctx *c, int64_t n, const double *a, const double *b, double *result, void *ws, size_t ws_bytes)
+{
+    if (!c || !a || !b || !result || !ws || n < 0) return SILU_ERR_ARG;
+    if (ws_bytes < (DOT_BLOCKS + 1) * sizeof(double)) return SILU_ERR_NOMEM;
+    double *part = (double *)ws, *out = part + DOT_BLOCKS;
+    HIPCHK(c, launch_dot(n, a, b, part, out, false, c->stream));
+    HIPCHK(c, hipMemcpyAsync(result, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return SILU_OK;
 }
 

@@ -14,7 +14,8 @@ enum Epi : int {
     EPI_STORE = 0,        // out_i = t_i
     EPI_SCALE = 1,        // out_i = dinv_i * t_i                  (s = D^{-1} y)
     EPI_UPDATE = 2,       // x_i = x_i + c_i * t_i                 (x += z)
-    EPI_SCALE_UPDATE = 3  // x_i = x_i + c_i * (OT)(dinv_i * t_i)  (x += D^{-1} y when m_U = 1)
+    EPI_SCALE_UPDATE = 3, // x_i = x_i + c_i * (OT)(dinv_i * t_i)  (x += D^{-1} y when m_U = 1)
+    EPI_SPMV = 4          // out_i = sum_j N_ij xin_j  (no rhs; the product A z of the Krylov solver)
 };
 // c_i is the column factor d_c,i of the row/column scaling (SweepArgs::dcol),
 // or 1 (an exact multiplication) when dcol is null.
@@ -114,6 +115,16 @@ hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, 
 hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,
                               const int32_t *sptr, const int32_t *sk, int code, const int32_t *dmap, int lo,
                               void *sval, void *scode, hipStream_t s);
+// Krylov vector kernels (krylov.hip).  launch_dot writes a . b (or its
+// square root) to out[0] on the device, reducing in a fixed order through
+// part[DOT_BLOCKS]; the others update with a device (h[0]) or host scalar.
+constexpr int DOT_BLOCKS = 1024;
+hipError_t launch_dot(int64_t n, const double *a, const double *b, double *part, double *out, bool take_sqrt,
+                      hipStream_t s);
+hipError_t launch_sub_scaled(int64_t n, double *w, const double *v, const double *h, hipStream_t s);
+hipError_t launch_div_dev(int64_t n, const double *w, const double *h, double *out, hipStream_t s);
+hipError_t launch_div_host(int64_t n, const double *w, double d, double *out, hipStream_t s);
+hipError_t launch_axpy_host(int64_t n, double alpha, const double *z, double *x, hipStream_t s);
 // Largest window (LDS slots) the windowed sweep stages per workgroup.
 constexpr int WIN_MAX_SLOTS = 3072;
 

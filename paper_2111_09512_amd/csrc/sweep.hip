@@ -92,6 +92,7 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
     const double c = a.dcol ? a.dcol[row] : 1.0; // column factor; 1.0 * v is exact
     switch (a.epi) {
     case EPI_STORE:
+    case EPI_SPMV:
         ((OT *)a.out)[row] = (OT)v;
         break;
     case EPI_SCALE:
@@ -118,6 +119,7 @@ __device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typena
     const IT v = (IT)t;
     switch (a.epi) {
     case EPI_STORE:
+    case EPI_SPMV:
         ((OT *)a.out)[row] = (OT)v;
         break;
     case EPI_SCALE:
@@ -171,7 +173,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
     double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
     if (tid < nr) {
         const int row = r0 + tid;
-        rhs_v = ((const RT *)a.rhs)[row];
+        if (a.epi != EPI_SPMV) rhs_v = ((const RT *)a.rhs)[row];
         if (a.epi == EPI_UPDATE) aux = a.x[row];
         if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
         if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
@@ -216,7 +218,7 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
         __syncthreads();
     }
-    if (tid < nr) epilogue_pre<T>(a, r0 + tid, (AT)rhs_v - sum, aux, aux2, cf);
+    if (tid < nr) epilogue_pre<T>(a, r0 + tid, a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum, aux, aux2, cf);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
     RT rhs_v = (RT)0;
     double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
     if (live) {
-        rhs_v = ((const RT *)a.rhs)[row];
+        if (a.epi != EPI_SPMV) rhs_v = ((const RT *)a.rhs)[row];
         if (a.epi == EPI_UPDATE) aux = a.x[row];
         if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
         if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
@@ -356,7 +358,7 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
             }
         }
     }
-    if (live) epilogue_pre<T>(a, row, (AT)rhs_v - sum, aux, aux2, cf);
+    if (live) epilogue_pre<T>(a, row, a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum, aux, aux2, cf);
 }
 
 // Batched CSR-stream: one launch runs one sweep for each of `nops`
@@ -436,7 +438,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_rb(SweepArgs a, const int2 *__r
             if (a.dshift) sum = (AT)((a.dshift[row] - 1.0) * (double)xin[row]);
             const int klo = srp[t] - e0, khi = srp[t + 1] - e0;
             for (int k = klo; k < khi; ++k) sum = sum + prod[k];
-            epilogue<T>(a, row, (AT)rhs[row] - sum);
+            epilogue<T>(a, row, a.epi == EPI_SPMV ? sum : (AT)rhs[row] - sum);
         }
         return;
     }
@@ -452,7 +454,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_rb(SweepArgs a, const int2 *__r
             for (int k = 0; k < cn; ++k) sum = sum + prod[k];
         __syncthreads();
     }
-    if (tid == 0) epilogue<T>(a, row, (AT)rhs[row] - sum);
+    if (tid == 0) epilogue<T>(a, row, a.epi == EPI_SPMV ? sum : (AT)rhs[row] - sum);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,7 +484,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_vector(SweepArgs a)
     for (int off = K / 2; off > 0; off >>= 1) sum = sum + __shfl_xor(sum, off, K);
     if (live && lane == 0) {
         if (a.dshift) sum = sum + (AT)((a.dshift[row] - 1.0) * (double)xin[row]);
-        const AT t = (AT)((const RT *)a.rhs)[row] - sum;
+        const AT t = a.epi == EPI_SPMV ? sum : (AT)((const RT *)a.rhs)[row] - sum;
         epilogue<T>(a, row, t);
     }
 }
