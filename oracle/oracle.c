@@ -784,6 +784,72 @@ void orc_smooth_rowcol(int n, const int *Arp, const int *Acol, const double *Ava
 }
 
 /* =========================================================================
+ * ILU(0) by fixed-point sweeps (Section 7 names the fixed-point ILU of Chow
+ * and Patel as the way to factor on the GPU).  The unknowns are the entries
+ * of L (unit lower, strict part) and U (upper) on the pattern S of A; they
+ * satisfy, for every (i,j) in S,
+ *   u_ij = a_ij - sum_{k < i} l_ik u_kj            (j >= i)
+ *   l_ij = (a_ij - sum_{k < j} l_ik u_kj) / u_jj    (j <  i)
+ * with k over the entries (i,k) and (k,j) that are both in S.  A sweep
+ * evaluates every equation from the previous sweep's values (synchronous,
+ * so the result is independent of the order rows are visited), subtracting
+ * the products from a_ij in ascending k -- the order in which the row-wise
+ * (IKJ) elimination of orc_iluk applies them, so the fixed point equals that
+ * ILU(0) bit for bit.  Initial guess: u_ij = a_ij, l_ij = a_ij / a_jj.
+ * LU: values aligned with A's CSR (entry p holds l_ij or u_ij); ws: nnz(A)
+ * doubles + n ints.  Returns the number of sweeps after which the values
+ * stopped changing (sweeps + 1 if they still changed), or -1 (a row without
+ * its diagonal).
+ * ========================================================================= */
+static int orc_find(const int *rp, const int *col, int row, int c)
+{
+    int lo = rp[row], hi = rp[row + 1] - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) / 2;
+        if (col[mid] == c) return mid;
+        if (col[mid] < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+int orc_ilu0_fixed_point(int n, const int *Arp, const int *Acol, const double *Aval, int sweeps, double *LU,
+                         double *ws)
+{
+    const int nnz = Arp[n];
+    double *old = ws;
+    int *dpos = (int *)(ws + nnz);
+    for (int i = 0; i < n; i++) {
+        dpos[i] = orc_find(Arp, Acol, i, i);
+        if (dpos[i] < 0) return -1;
+    }
+    for (int i = 0; i < n; i++)
+        for (int p = Arp[i]; p < Arp[i + 1]; p++) {
+            const int j = Acol[p];
+            LU[p] = j < i ? Aval[p] / Aval[dpos[j]] : Aval[p];
+        }
+    for (int sw = 1; sw <= sweeps; sw++) {
+        for (int p = 0; p < nnz; p++) old[p] = LU[p];
+        int changed = 0;
+        for (int i = 0; i < n; i++)
+            for (int p = Arp[i]; p < Arp[i + 1]; p++) {
+                const int j = Acol[p];
+                const int kmax = j < i ? j : i;
+                double s = Aval[p];
+                for (int q = Arp[i]; q < Arp[i + 1] && Acol[q] < kmax; q++) {
+                    const int pk = orc_find(Arp, Acol, Acol[q], j);
+                    if (pk >= 0) s = s - old[q] * old[pk];
+                }
+                const double v = j < i ? s / old[dpos[j]] : s;
+                if (v != old[p]) changed = 1;
+                LU[p] = v;
+            }
+        if (!changed) return sw - 1;
+    }
+    return sweeps + 1;
+}
+
+/* =========================================================================
  * Polynomial Gauss-Seidel smoother (Section 2: the polynomial smoother the
  * ILU smoother is compared with).  Gauss-Seidel's (D + L)^{-1}, with D the
  * diagonal and L the strictly lower part of A, is written (I + D^{-1}L)^{-1}

@@ -70,6 +70,7 @@ def lib():
         L.orc_gs_smooth.restype = None
         L.orc_fgmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p,
                                  C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int, C.c_int, C.c_double, _f64p, _f64p]
+        L.orc_ilu0_fixed_point.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_spmv.restype = None
         L.orc_residual.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p, _f64p]
@@ -285,6 +286,26 @@ def fgmres(A, Ls, Us, dinv, b, x0, m: int, max_iters: int, tol: float, outer: in
                          np.ascontiguousarray(dinv, np.float64), int(outer), int(mL), int(mU),
                          np.ascontiguousarray(b, np.float64), x, int(m), int(max_iters), float(tol), hist, ws)
     return k, x, hist[: k + 1].copy()
+
+
+def ilu0_fixed_point(A, sweeps: int):
+    """ILU(0) by synchronous fixed-point sweeps (Section 7).  Returns (Ls, U, n_stable)
+    where n_stable is the sweep after which the values stopped changing (sweeps + 1
+    if they had not)."""
+    A = _mat(A)
+    n = A.n
+    LU = np.empty(max(A.nnz, 1))
+    ws = np.empty(A.nnz + n + 1)
+    st = lib().orc_ilu0_fixed_point(n, A.row_ptr, A.col, A.val, int(sweeps), LU, ws)
+    if st < 0:
+        raise OracleError(3, -1, "fixed-point ILU(0)")
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    low = A.col < rows
+    Lrp = np.concatenate([[0], np.cumsum(np.bincount(rows[low], minlength=n))]).astype(np.int32)
+    Urp = np.concatenate([[0], np.cumsum(np.bincount(rows[~low], minlength=n))]).astype(np.int32)
+    Ls = Mat(n, Lrp, A.col[low].copy(), LU[: A.nnz][low].copy())
+    U = Mat(n, Urp, A.col[~low].copy(), LU[: A.nnz][~low].copy())
+    return Ls, U, st
 
 
 def spmv(N, x):
