@@ -12,7 +12,9 @@ smoother with both triangular solves done by level-set substitution), the
 FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, the
 polynomial Gauss-Seidel smoother (time and residual after one application
 beside the ILU smoother's), FGMRES(30) with the smoother as preconditioner
-solved to 1e-8 (steps, time, NRBE), a streaming-copy bandwidth calibration, the
+solved to 1e-8 (steps, time, NRBE), ILU(0) computed on the device by
+fixed-point sweeps against the host ILU(0), a streaming-copy bandwidth
+calibration, the
 roofline of
 the dominant kernel from per-launch HIP events, and the CPU oracle timed on a
 bounded sample of the same operator, and the serving stream (1,280 requests
@@ -160,6 +162,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-gs", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
+    ap.add_argument("--no-fixed-point", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -314,6 +317,47 @@ def main():
                              "relres": relres, "nrbe": nrbe, "estimate_history_every_5": hist[::5].tolist()}
         del Ah
 
+    # ---- ILU(0) of the operator on the device by fixed-point sweeps, against the host ILU(0) ----
+    fixed_point = None
+    if not args.no_fixed_point:
+        import scipy.sparse as sp
+
+        Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(n, n))
+        bh = bvec.cpu().numpy()
+        nb = float(np.linalg.norm(bh))
+
+        def quality(Fq):
+            x.zero_()
+            ctx.ilu_smooth(Ad, Fq, bvec, x, outer, mL, mU, kernel=kern, ws=ws)
+            return float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / nb)
+
+        t = time.perf_counter()
+        L0, U0 = B.factor_iluk(A, 0)
+        host_s = time.perf_counter() - t
+        F0 = ctx.ilu_scale_factors(B.Csr.from_host(L0), B.Csr.from_host(U0))
+        del L0, U0
+        fixed_point = {"host_ilu0_seconds": host_s, "relres_exact_ilu0": quality(F0), "sweeps": {}}
+        del F0
+        for sweeps in (1, 2, 3, 5, 8):
+            ctx.stats_reset()
+            ctx.set_timing(True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            Lg, Ug, _ = ctx.ilu0_fixed_point(Ad, sweeps)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t
+            ctx.set_timing(False)
+            st_fp = ctx.stats().get("ilu0_fixed_point_sweep", {"ms": 0.0, "launches": 1})
+            Fg = ctx.ilu_scale_factors(Lg, Ug)
+            fixed_point["sweeps"][sweeps] = {"seconds_incl_setup": secs,
+                                             "ms_per_sweep": st_fp["ms"] / max(st_fp["launches"], 1),
+                                             "relres_after_one_app": quality(Fg)}
+            log(f"fixed-point ILU(0), {sweeps} sweeps: {secs * 1e3:.1f} ms, relres after one application "
+                f"{fixed_point['sweeps'][sweeps]['relres_after_one_app']:.3e} "
+                f"(host ILU(0) {fixed_point['relres_exact_ilu0']:.3e}, {host_s:.1f} s on the host)")
+            del Lg, Ug, Fg
+        del Ah
+
     # ---- direct (level-scheduled) form ----
     ms_direct = None
     depths = None
@@ -373,6 +417,7 @@ def main():
         "rowcol": rowcol,
         "gauss_seidel": gs,
         "fgmres": krylov,
+        "ilu0_fixed_point": fixed_point,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,

@@ -281,6 +281,34 @@ int gs_scale_split(silu_ctx *ctx, const silu_csr *A, silu_factors *G, int flags)
 int gs_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *G, const double *b, double *x, int outer_sweeps,
               int terms, int flags, void *ws, size_t ws_bytes);
 
+/* ---- ILU(0) on the device by fixed-point sweeps (Section 7) -------------- */
+
+/*
+ * The factorization the paper plans to move to the GPU with the fixed-point
+ * ILU of Chow and Patel.  The entries of L (unit lower) and U on the pattern
+ * S of A satisfy, for every (i,j) in S,
+ *   u_ij = a_ij - sum_{k<i} l_ik u_kj,   l_ij = (a_ij - sum_{k<j} l_ik u_kj) / u_jj
+ * (k over the pairs (i,k), (k,j) in S).  Starting from u_ij = a_ij,
+ * l_ij = a_ij / a_jj, each of `sweeps` synchronous sweeps evaluates every
+ * equation from the previous sweep's values, subtracting the products from
+ * a_ij in ascending k; swept to a standstill the result is the row-wise
+ * ILU(0) bit for bit, and a few sweeps give an approximate factorization.
+ *
+ * silu_split_sizes: entries strictly below the diagonal and on or above it
+ * (synchronous).  silu_ilu0_fixed_point writes Ls (strictly lower, unit
+ * diagonal implied) and U (upper, diagonal first in every row), in the
+ * format ilu_scale_factors takes: caller-allocated row_ptr [n+1], col_idx and
+ * val of the two sizes.  *changed (may be NULL): 1 if the last sweep still
+ * changed a value.  ws: silu_ilu0_fixed_point_workspace_size bytes (two value
+ * arrays and two index arrays), 256-byte aligned.  Synchronous.  Errors: ARG,
+ * SHAPE, NOMEM, PATTERN (a row of A without its diagonal), ZERO_PIVOT (a zero
+ * or non-finite diagonal of A), HIP.
+ */
+int silu_split_sizes(silu_ctx *ctx, const silu_csr *A, int64_t *nnz_lower, int64_t *nnz_upper);
+int silu_ilu0_fixed_point_workspace_size(silu_ctx *ctx, int64_t n, int64_t nnz, size_t *bytes);
+int silu_ilu0_fixed_point(silu_ctx *ctx, const silu_csr *A, int sweeps, silu_csr *Ls, silu_csr *U, int *changed,
+                          int flags, void *ws, size_t ws_bytes);
+
 /* ---- Krylov solver around the smoother (Section 6) ---------------------- */
 
 /*

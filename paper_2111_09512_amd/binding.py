@@ -86,6 +86,10 @@ _sig = {
     "gs_scale_split": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.c_int]),
     "gs_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int, _P,
                             C.c_size_t]),
+    "silu_split_sizes": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "silu_ilu0_fixed_point_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "silu_ilu0_fixed_point": (C.c_int, [_P, C.POINTER(silu_csr), C.c_int, C.POINTER(silu_csr), C.POINTER(silu_csr),
+                                        C.POINTER(C.c_int), C.c_int, _P, C.c_size_t]),
     "silu_fgmres_workspace_size": (C.c_int, [_P, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_size_t)]),
     "silu_fgmres": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
                               C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_size_t, C.POINTER(C.c_int),
@@ -305,6 +309,28 @@ class Context:
         self._check(_lib.ilu_scale_factors_rowcol(self._h, C.byref(Lc), C.byref(Uc), int(ruiz_iters), C.byref(Fc),
                                                   SILU_VALIDATE if validate else 0), "ilu_scale_factors_rowcol")
         return F
+
+    # ---- ILU(0) on the device by fixed-point sweeps ----
+    def ilu0_fixed_point(self, A: Csr, sweeps: int, validate: bool = False):
+        """Returns (Ls, U, changed): ILU(0) after `sweeps` synchronous fixed-point sweeps."""
+        Ac = A.c()
+        nl, nu = C.c_int64(), C.c_int64()
+        self._check(_lib.silu_split_sizes(self._h, C.byref(Ac), C.byref(nl), C.byref(nu)), "silu_split_sizes")
+        dev = A.val.device
+        Ls = Csr(torch.empty(A.n + 1, dtype=torch.int32, device=dev), torch.empty(nl.value, dtype=torch.int32, device=dev),
+                 torch.empty(nl.value, dtype=torch.float64, device=dev))
+        U = Csr(torch.empty(A.n + 1, dtype=torch.int32, device=dev), torch.empty(nu.value, dtype=torch.int32, device=dev),
+                torch.empty(nu.value, dtype=torch.float64, device=dev))
+        nb = C.c_size_t()
+        self._check(_lib.silu_ilu0_fixed_point_workspace_size(self._h, A.n, A.nnz, C.byref(nb)),
+                    "silu_ilu0_fixed_point_workspace_size")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        Lc, Uc = Ls.c(), U.c()
+        ch = C.c_int()
+        self._check(_lib.silu_ilu0_fixed_point(self._h, C.byref(Ac), int(sweeps), C.byref(Lc), C.byref(Uc),
+                                               C.byref(ch), SILU_VALIDATE if validate else 0,
+                                               C.c_void_p(ws.data_ptr()), ws.numel()), "silu_ilu0_fixed_point")
+        return Ls, U, bool(ch.value)
 
     # ---- Krylov solver around the smoother ----
     def fgmres(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, restart: int = 30, max_iters: int = 300,

@@ -1154,6 +1154,86 @@ int gs_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *G, const doubl
     return SILU_OK;
 }
 
+// ---- ILU(0) by fixed-point sweeps on the device ------------------------------
+int silu_split_sizes(silu_ctx *c, const silu_csr *A, int64_t *nnz_lower, int64_t *nnz_upper)
+{
+    if (!c || !A || !nnz_lower || !nnz_upper) return SILU_ERR_ARG;
+    int st = gs_split_size(c, A, nnz_lower);
+    if (st) return st;
+    *nnz_upper = A->nnz - *nnz_lower;
+    return SILU_OK;
+}
+
+int silu_ilu0_fixed_point_workspace_size(silu_ctx *c, int64_t n, int64_t nnz, size_t *bytes)
+{
+    if (!c || !bytes || n < 0 || nnz < 0) return SILU_ERR_ARG;
+    *bytes = 2 * ws_vec_bytes(nnz) + ws_vec_bytes((nnz + 1) / 2) + ws_vec_bytes((n + 1) / 2);
+    return SILU_OK;
+}
+
+int silu_ilu0_fixed_point(silu_ctx *c, const silu_csr *A, int sweeps, silu_csr *Ls, silu_csr *U, int *changed,
+                          int flags, void *ws, size_t ws_bytes)
+{
+    if (!c || !A || !Ls || !U || !ws || sweeps < 0) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    const int64_t n = A->n_rows, nnz = A->nnz;
+    if (nnz >= INT32_MAX) return SILU_ERR_SHAPE;
+    size_t need = 0;
+    silu_ilu0_fixed_point_workspace_size(c, n, nnz, &need);
+    if (ws_bytes < need || ((uintptr_t)ws & 255) != 0) return ws_bytes < need ? SILU_ERR_NOMEM : SILU_ERR_ARG;
+    if (!Ls->row_ptr || !U->row_ptr) return SILU_ERR_ARG;
+    if (flags & SILU_VALIDATE) {
+        if ((st = validate(c, A, 0))) return st;
+    }
+    // row counts of the two parts (with the diagonal and pivot checks)
+    std::vector<int32_t> counts;
+    if ((st = gs_counts(c, A, counts))) return st;
+    std::vector<int32_t> rp((size_t)n + 1), Lrp((size_t)n + 1, 0), Urp((size_t)n + 1, 0);
+    HIPCHK(c, hipMemcpyAsync(rp.data(), A->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; i++) {
+        Lrp[(size_t)i + 1] = Lrp[(size_t)i] + counts[(size_t)i];
+        Urp[(size_t)i + 1] = Urp[(size_t)i] + (rp[(size_t)i + 1] - rp[(size_t)i] - counts[(size_t)i]);
+    }
+    const int64_t l_nnz = Lrp[(size_t)n], u_nnz = Urp[(size_t)n];
+    if ((l_nnz > 0 && (!Ls->col_idx || !Ls->val)) || (u_nnz > 0 && (!U->col_idx || !U->val))) return SILU_ERR_ARG;
+    if ((st = silu_release(c, Ls->row_ptr, Ls->col_idx))) return st;
+    if ((st = silu_release(c, U->row_ptr, U->col_idx))) return st;
+    char *w = (char *)ws;
+    double *LU0 = (double *)w, *LU1 = (double *)(w + ws_vec_bytes(nnz));
+    int32_t *row_of = (int32_t *)(w + 2 * ws_vec_bytes(nnz));
+    int32_t *dpos = (int32_t *)(w + 2 * ws_vec_bytes(nnz) + ws_vec_bytes((nnz + 1) / 2));
+    HIPCHK(c, launch_init_flags(c->d_flags, 4, INT32_MAX, c->stream));
+    HIPCHK(c, launch_fp_index((int)n, A->row_ptr, A->col_idx, dpos, row_of, c->d_flags, c->stream));
+    HIPCHK(c, launch_fp_init(nnz, A->col_idx, (const double *)A->val, dpos, row_of, LU0, c->stream));
+    double *cur = LU0, *nxt = LU1;
+    int32_t h[4] = {INT32_MAX, 0, 0, 0};
+    for (int sw = 0; sw < sweeps; sw++) {
+        HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, 0, c->stream));
+        st = timed_launch(c, 8.0 * 3.0 * (double)nnz, [&](const char **nm) {
+            *nm = "ilu0_fixed_point_sweep";
+            return launch_fp_sweep(nnz, A->row_ptr, A->col_idx, (const double *)A->val, dpos, row_of, cur, nxt,
+                                   c->d_flags, c->stream);
+        });
+        if (st) return st;
+        std::swap(cur, nxt);
+    }
+    HIPCHK(c, hipMemcpyAsync(Ls->row_ptr, Lrp.data(), Lrp.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(U->row_ptr, Urp.data(), Urp.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fp_split((int)n, A->row_ptr, A->col_idx, cur, Ls->row_ptr, Ls->col_idx, (double *)Ls->val,
+                              U->row_ptr, U->col_idx, (double *)U->val, l_nnz, u_nnz, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h, c->d_flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream)); // host row pointers go out of scope
+    Ls->n_rows = Ls->n_cols = U->n_rows = U->n_cols = n;
+    Ls->nnz = l_nnz;
+    U->nnz = u_nnz;
+    Ls->dtype = U->dtype = SILU_F64;
+    if (changed) *changed = sweeps > 0 ? h[1] : 1;
+    return SILU_OK;
+}
+
 // ---- FGMRES with the smoother as right preconditioner -----------------------
 namespace {
 

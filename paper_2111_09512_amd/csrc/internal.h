@@ -125,6 +125,18 @@ hipError_t launch_sub_scaled(int64_t n, double *w, const double *v, const double
 hipError_t launch_div_dev(int64_t n, const double *w, const double *h, double *out, hipStream_t s);
 hipError_t launch_div_host(int64_t n, const double *w, double d, double *out, hipStream_t s);
 hipError_t launch_axpy_host(int64_t n, double alpha, const double *z, double *x, hipStream_t s);
+// ILU(0) by fixed-point sweeps (fixedpoint.hip): diagonal positions and the
+// row of every entry, the initial guess, one synchronous sweep (flags[1] set
+// when a value changed), and the split into Ls and U.
+hipError_t launch_fp_index(int n, const int32_t *rp, const int32_t *col, int32_t *dpos, int32_t *row_of,
+                           int32_t *flags, hipStream_t s);
+hipError_t launch_fp_init(int64_t nnz, const int32_t *col, const double *val, const int32_t *dpos,
+                          const int32_t *row_of, double *LU, hipStream_t s);
+hipError_t launch_fp_sweep(int64_t nnz, const int32_t *rp, const int32_t *col, const double *val, const int32_t *dpos,
+                           const int32_t *row_of, const double *old, double *nw, int32_t *flags, hipStream_t s);
+hipError_t launch_fp_split(int n, const int32_t *rp, const int32_t *col, const double *LU, const int32_t *Lrp,
+                           int32_t *Lcol, double *Lval, const int32_t *Urp, int32_t *Ucol, double *Uval, int64_t l_nnz,
+                           int64_t u_nnz, hipStream_t s);
 // Largest window (LDS slots) the windowed sweep stages per workgroup.
 constexpr int WIN_MAX_SLOTS = 3072;
 
