@@ -195,7 +195,9 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
  * column, and a column code per slot -- 1 byte (an index into the table of
  * the matrix's distinct diagonals col - row, when there are at most 256: a
  * stencil operator and its ILU factors), else 2 bytes (slice-relative offset,
- * when it fits), else the 4-byte column.  Each row's products are still added
+ * when it fits); a matrix with neither structure (random columns) is swept
+ * in CSR-stream instead (SILU_INDEX32 forces a sliced copy with 4-byte
+ * columns).  Each row's products are still added
  * in ascending column order, so finite results are bit-identical to the
  * row-by-row definition; a padded slot adds +0.0.  The first use synchronizes
  * a few times.  The copy holds the VALUES as they were at that first sweep:

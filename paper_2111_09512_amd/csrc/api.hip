@@ -478,6 +478,13 @@ int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int 
             lo = (int)olo;
         }
     }
+    // a matrix without diagonal or offset structure gathers at random either
+    // way; unless 4-byte codes were asked for, the CSR stream (no padding) is
+    // used for it instead
+    if (code == 4 && code_min < 4) {
+        free_sliced(S);
+        return store();
+    }
     int32_t *d_dmap = nullptr;
     e = hipMalloc(&S.sptr, (size_t)nslice * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(S.sptr, sptr.data(), (size_t)nslice * 4, hipMemcpyHostToDevice, c->stream);
@@ -531,7 +538,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
             sliced_bytes = (double)S->v.slots * (vbytes + S->v.code) + 8.0 * S->v.nslice +
                            8.0 * (double)S->masked_rows + (double)N->n_rows * (xb + rb) + 4.0 * S->v.ndiag;
         } else {
-            g.kind = SweepKernel::STREAM; // no entries, or too large for the sliced copy
+            g.kind = SweepKernel::STREAM; // no entries, too large for the sliced copy, or no structure
         }
     }
     if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
