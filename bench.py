@@ -129,12 +129,12 @@ def bench_serving(torch, B, ctx, arena_mb):
     for r in reqs:
         r.x.zero_()
     lat_b, span_b, steps = S.run_batched(server, mids, reqs)
-    xb = [r.x.clone() for r in reqs[:32]]
+    xb = [r.x.clone() for r in reqs]
+    server.close()
     for r in reqs:
         r.x.zero_()
     lat_1, span_1 = S.run_one_at_a_time(ctx, mats, reqs)
-    same = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(xb)))
-    server.close()
+    same = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
     res = {"requests": len(reqs), "matrices": len(mats), "arrival_rate_per_s": 2000.0, "arena_MB": arena_mb,
            "batched": {"apps_per_s": len(reqs) / span_b, "makespan_s": span_b, "steps": steps,
                        **S.percentiles(lat_b)},

@@ -46,6 +46,7 @@ extern "C" {
 #define SILU_ERR_NOMEM (-6)       /* caller workspace smaller than silu_workspace_size() */
 #define SILU_ERR_HIP (-7)         /* a HIP runtime call failed */
 #define SILU_ERR_UNSUPPORTED (-8) /* valid request this build does not implement */
+#define SILU_ERR_TIMEOUT (-9)     /* a persistent serving launch gave up a bounded wait */
 
 /* ---- value types of silu_csr.val ------------------------------------- */
 #define SILU_F64 0
@@ -427,7 +428,7 @@ int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
  * each is at; requests that arrive later join at the next step.  A request's
  * workspace returns to the arena once the GPU has passed its last launch.
  * Each row is summed in a fixed order by one lane, so a request's result is
- * bit-identical to ilu_smooth on its own.  At most 4 steps are in flight.
+ * bit-identical to ilu_smooth on its own.  At most 8 steps are in flight.
  *
  * arena: device memory owned by the caller, 256-byte aligned, alive until
  * silu_server_destroy.  b and x of a request: device FP64 [n], alive until
@@ -447,9 +448,43 @@ int silu_server_submit(silu_server *server, int matrix_id, const double *b, doub
                        int64_t *ticket);
 /* One scheduling step (asynchronous; blocks only when 4 steps are in flight). */
 int silu_server_step(silu_server *server, int *n_active, int *n_queued);
-/* state: 0 queued, 1 running, 2 last sweep enqueued, 3 done (result in x). */
+/* state: 0 queued, 1 running, 2 last sweep enqueued, 3 done (result in x).
+ * Returns SILU_ERR_TIMEOUT (state 3) for a request whose persistent launch
+ * gave up a wait: its x is not a valid result. */
 int silu_server_poll(silu_server *server, int64_t ticket, int *state);
 int silu_server_last_hip_error(const silu_server *server);
+
+/*
+ * Scheduling mode of a server (the serving form; Algorithm 2 per request).
+ *   SILU_SERVE_STEPWISE (default): as above, one batched launch per step, one
+ *     sweep per active request.
+ *   SILU_SERVE_PERSISTENT: NOT AVAILABLE in this build -- set_mode returns
+ *     SILU_ERR_UNSUPPORTED (its launches did not finish on MI355X, for a
+ *     cause not yet found).  As designed: a step hands the requests it admits, with all of
+ *     their sweeps, to ONE persistent launch on the next of three streams the
+ *     server creates (default priority) after the caller's stream has passed
+ *     the point of the step.  Inside the launch each request's sweeps follow
+ *     one another through device-side counters, with no kernel boundary; the
+ *     launches of different steps run concurrently, so a request that arrives
+ *     while others run starts at once.  Results are bit-identical to the
+ *     stepwise mode and to ilu_smooth.  max_workgroups caps the workgroups of
+ *     one launch (0: 1024; at most 65535); a launch needs no more than twice
+ *     the row tiles (256 rows) of its requests' matrices.  max_active counts
+ *     requests whose launch the GPU has not passed.  A wait inside the launch
+ *     is bounded; one that expires makes poll return SILU_ERR_TIMEOUT for the
+ *     requests of that launch.  x is written on the server's streams: use it
+ *     after poll reports state 3.
+ * The mode may change only while no request is queued, active or in flight
+ * (else SILU_ERR_ARG).  Synchronous.
+ */
+#define SILU_SERVE_STEPWISE 0
+#define SILU_SERVE_PERSISTENT 1
+int silu_server_set_mode(silu_server *server, int mode, int max_workgroups);
+/* Polls a persistent launch's bounded wait makes before it gives up (each
+ * poll follows a sleep of about 0.1 us; 0 restores the default 262144).  For
+ * tests of the failure path: a limit of 1 makes most waits expire, and the
+ * launch still drains and reports SILU_ERR_TIMEOUT through poll. */
+int silu_server_set_wait_limit(silu_server *server, int polls);
 
 #ifdef __cplusplus
 }

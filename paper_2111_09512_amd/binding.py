@@ -46,6 +46,7 @@ SILU_UNIT, SILU_NONUNIT = 0, 1
 STATUS = {
     0: "SILU_OK", -1: "SILU_ERR_ARG", -2: "SILU_ERR_SHAPE", -3: "SILU_ERR_PATTERN", -4: "SILU_ERR_ZERO_PIVOT",
     -5: "SILU_ERR_NONFINITE", -6: "SILU_ERR_NOMEM", -7: "SILU_ERR_HIP", -8: "SILU_ERR_UNSUPPORTED",
+    -9: "SILU_ERR_TIMEOUT",
 }
 
 
@@ -123,6 +124,8 @@ _sig = {
     "silu_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "silu_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
     "silu_server_last_hip_error": (C.c_int, [_P]),
+    "silu_server_set_mode": (C.c_int, [_P, C.c_int, C.c_int]),
+    "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -600,8 +603,10 @@ class Server:
     referenced until the server is closed, so the device pointers stay valid."""
 
     QUEUED, RUNNING, LAUNCHED, DONE = 0, 1, 2, 3
+    STEPWISE, PERSISTENT = 0, 1
 
-    def __init__(self, ctx: Context, arena_bytes: int, max_active: int = 256):
+    def __init__(self, ctx: Context, arena_bytes: int, max_active: int = 256, persistent: bool = False,
+                 max_workgroups: int = 0):
         self.ctx = ctx
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
         h = C.c_void_p()
@@ -612,6 +617,17 @@ class Server:
         self._h = h
         self._keep = []
         self._req = {}
+        if persistent:
+            self.set_mode(self.PERSISTENT, max_workgroups)
+
+    def set_mode(self, mode: int, max_workgroups: int = 0):
+        """STEPWISE (one batched launch per sweep) or PERSISTENT (one launch
+        per admitted batch running every sweep of its requests)."""
+        self._check(_lib.silu_server_set_mode(self._h, mode, max_workgroups), "silu_server_set_mode")
+
+    def set_wait_limit(self, polls: int):
+        """Polls before a persistent launch's wait gives up (0: default)."""
+        self._check(_lib.silu_server_set_wait_limit(self._h, polls), "silu_server_set_wait_limit")
 
     def close(self):
         if getattr(self, "_h", None):

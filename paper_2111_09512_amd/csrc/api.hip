@@ -805,6 +805,7 @@ const char *silu_status_string(int s)
     case SILU_ERR_NOMEM: return "workspace too small or out of memory";
     case SILU_ERR_HIP: return "HIP runtime error";
     case SILU_ERR_UNSUPPORTED: return "unsupported combination of arguments";
+    case SILU_ERR_TIMEOUT: return "a bounded wait inside a persistent launch expired";
     default: return "unknown status";
     }
 }

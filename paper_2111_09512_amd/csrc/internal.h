@@ -148,6 +148,34 @@ hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStrea
 // sum.  Both arrays live in device memory.
 hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
                               hipStream_t s);
+// The same with the op table passed in the kernel arguments (no copy to the
+// device first): at most BATCH_ARG_OPS ops, 256 rows per workgroup.
+constexpr int BATCH_ARG_OPS = 24;
+struct BatchArgs {
+    SweepArgs op[BATCH_ARG_OPS];
+    int32_t first[BATCH_ARG_OPS + 1];
+    int nops;
+};
+hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s);
+
+// Persistent batched FP64 CSR-stream sweeps (serving): one launch runs chains
+// of dependent sweeps.  Op i covers tiles [first[i], first[i+1]) of
+// PERSIST_RPB rows and may start once done[dep[i]] == first[dep[i]+1] -
+// first[dep[i]] (dep[i] < i, or -1).  ctl[0] (next tile) and ctl[1] (0, or
+// 1 + the op whose wait expired) and done[] must be zero at launch; all of it
+// lives in device memory.  Any grid size >= 1 drains the queue.
+constexpr int PERSIST_RPB = 256;
+struct PersistPlan {
+    int32_t *ctl;
+    const int32_t *first; // [nops + 1]
+    const int32_t *dep;   // [nops]
+    int32_t *done;        // [nops]
+    const SweepArgs *ops; // [nops]
+    int nops;
+    int spin_limit;       // polls before a wait gives up (>= 1)
+};
+constexpr int PERSIST_SPIN_LIMIT = 1 << 18;
+hipError_t launch_sweep_persist(const PersistPlan &p, int grid, hipStream_t s);
 
 struct LevelArgs {
     const int32_t *perm; // rows ordered by level

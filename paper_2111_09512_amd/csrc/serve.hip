@@ -6,10 +6,17 @@
 // last fused with D^{-1}), m_U - 1 sweeps on U~s (the last fused with the
 // update of x).  A step admits queued requests in arrival order while their
 // workspace fits in the caller's arena, then launches ONE batched kernel that
-// advances every active request by one op, whatever op each is at.  A
-// request's workspace returns to the arena once the GPU has passed its last
-// launch.  Each row is summed by one lane in a fixed order, so a request's
-// result does not depend on which requests shared its launches.
+// advances every active request by one op, whatever op each is at (with up to
+// 24 active requests the op table goes in the kernel arguments, else it is
+// copied to the device first).  A request's workspace returns to the arena
+// once the GPU has passed its last launch.  Each row is summed by one lane in
+// a fixed order, so a request's result does not depend on which requests
+// shared its launches.
+//
+// Persistent mode (switched off, see PERSISTENT_AVAILABLE): a step would hand
+// the requests it admits, with all of their ops, to one persistent launch
+// (k_sweep_persist) on the next of a few server streams, each request's
+// sweeps following one another through device-side dependency counters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,8 +33,15 @@ using namespace silu;
 
 namespace {
 
-constexpr int RING = 4;        // op-table staging slots = steps in flight
+constexpr int RING = 8;        // op-table staging slots = steps in flight
 constexpr int SERVE_RPB = 256; // rows per workgroup of the batched sweep
+constexpr int PSTREAMS = 3;    // persistent mode: streams the launches rotate over
+constexpr int DEFAULT_MAX_WG = 1024;
+// The persistent mode is switched off: on MI355X its launches did not finish
+// (the requests never completed and the process waited for the kernel at
+// exit), with the dependency counters at agent scope and again at system
+// scope, for a cause not yet shown.  Until it is, set_mode refuses the mode.
+constexpr bool PERSISTENT_AVAILABLE = false;
 
 struct Matrix {
     silu_csr A;
@@ -66,12 +80,30 @@ struct silu_server {
     std::map<int64_t, int64_t> finish_step;            // ticket -> step of its last op
     int64_t next_ticket = 0, steps = 0, completed_through = -1;
     hipEvent_t ev[RING] = {};
+    int64_t done_step[RING];   // the step a slot last held, once the GPU has passed it
     SweepArgs *h_ops[RING] = {};
     int32_t *h_first[RING] = {};
     SweepArgs *d_ops = nullptr;
     int32_t *d_first = nullptr;
     int cap = 0; // op-table capacity
     hipError_t last = hipSuccess;
+    // persistent mode
+    int mode = 0;
+    int max_wg = DEFAULT_MAX_WG;
+    int spin_limit = PERSIST_SPIN_LIMIT;
+    hipStream_t ps[PSTREAMS] = {};
+    hipEvent_t ev_in = nullptr;
+    char *h_plan[RING] = {};
+    char *d_plan[RING] = {};
+    size_t plan_cap[RING] = {};
+    int32_t *h_ctl[RING] = {}; // ctl words read back after each launch
+    int slot_reqs[RING] = {};
+    int inflight = 0;            // requests launched whose step the GPU has not passed
+    std::vector<int64_t> failed; // steps whose launch gave up a wait
+    silu_server()
+    {
+        for (int i = 0; i < RING; i++) done_step[i] = -1;
+    }
 };
 
 namespace {
@@ -113,17 +145,26 @@ bool allocate(silu_server *s, size_t bytes, Range *out)
     return false;
 }
 
-// Steps whose event has completed: reclaim the workspace they held.
+bool step_done(const silu_server *s, int64_t k) { return k <= s->completed_through || s->done_step[k % RING] == k; }
+
+// Steps whose event has completed (persistent launches may finish out of
+// order): reclaim the workspace they held.
 void reap(silu_server *s)
 {
     for (int64_t k = s->completed_through + 1; k < s->steps; k++) {
-        if (hipEventQuery(s->ev[k % RING]) != hipSuccess) break;
-        s->completed_through = k;
+        const int slot = (int)(k % RING);
+        if (s->done_step[slot] == k || hipEventQuery(s->ev[slot]) != hipSuccess) continue;
+        s->done_step[slot] = k;
+        if (s->mode == 1) {
+            s->inflight -= s->slot_reqs[slot];
+            if (s->h_ctl[slot][1] != 0) s->failed.push_back(k);
+        }
     }
+    while (s->completed_through + 1 < s->steps && step_done(s, s->completed_through + 1)) s->completed_through++;
     auto &tr = s->to_release;
     size_t w = 0;
     for (size_t i = 0; i < tr.size(); i++) {
-        if (tr[i].first <= s->completed_through)
+        if (step_done(s, tr[i].first))
             release(s, tr[i].second);
         else
             tr[w++] = tr[i];
@@ -223,6 +264,145 @@ int grow(silu_server *s, int need)
     return SILU_OK;
 }
 
+// Wait for a staging slot's previous launch before reusing it.
+int take_slot(silu_server *s, int *slot_out)
+{
+    const int slot = (int)(s->steps % RING);
+    if (s->steps >= RING) {
+        hipError_t e = hipEventSynchronize(s->ev[slot]);
+        if (e != hipSuccess) return fail(s, e);
+        reap(s);
+    }
+    *slot_out = slot;
+    return SILU_OK;
+}
+
+size_t align64(size_t v) { return (v + 63) & ~(size_t)63; }
+
+// Persistent mode: one launch runs every op of the admitted batch.  Requests
+// go in order of their work (rows x ops), smallest first, each as one chain
+// of ops; the plan is [ctl 4 x int32][first nops+1][dep nops][done nops] then
+// the op table, copied to the device in one transfer that also zeroes the
+// counters.
+int launch_persistent(silu_server *s, std::vector<Request> &batch)
+{
+    std::stable_sort(batch.begin(), batch.end(), [s](const Request &a, const Request &b) {
+        return s->mats[(size_t)a.mid].A.n_rows * a.total < s->mats[(size_t)b.mid].A.n_rows * b.total;
+    });
+    int64_t nops = 0, tiles = 0, grid = 0;
+    for (const Request &q : batch) {
+        const int64_t t = (s->mats[(size_t)q.mid].A.n_rows + SERVE_RPB - 1) / SERVE_RPB;
+        nops += q.total;
+        tiles += t * q.total;
+        grid += 2 * t; // one op's tiles at work, the next op's waiting
+    }
+    if (nops > (1 << 24) || tiles > INT32_MAX - (1 << 20)) return SILU_ERR_UNSUPPORTED;
+    grid = std::min<int64_t>(grid, s->max_wg);
+    const size_t n_int = 4 + (size_t)(nops + 1) + 2 * (size_t)nops;
+    const size_t ops_off = align64(n_int * sizeof(int32_t));
+    const size_t bytes = ops_off + (size_t)nops * sizeof(SweepArgs);
+    int slot;
+    int st = take_slot(s, &slot);
+    if (st) return st;
+    hipError_t e;
+    if (s->plan_cap[slot] < bytes) {
+        (void)hipHostFree(s->h_plan[slot]);
+        (void)hipFree(s->d_plan[slot]);
+        s->h_plan[slot] = nullptr;
+        s->d_plan[slot] = nullptr;
+        s->plan_cap[slot] = 0;
+        const size_t cap = std::max(bytes, (size_t)64 << 10);
+        if ((e = hipHostMalloc((void **)&s->h_plan[slot], cap)) != hipSuccess) return fail(s, e);
+        if ((e = hipMalloc((void **)&s->d_plan[slot], cap)) != hipSuccess) return fail(s, e);
+        s->plan_cap[slot] = cap;
+    }
+    int32_t *ctl = (int32_t *)s->h_plan[slot];
+    int32_t *first = ctl + 4, *dep = first + nops + 1, *done = dep + nops;
+    SweepArgs *ops = (SweepArgs *)(s->h_plan[slot] + ops_off);
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = (int32_t)nops;
+    ctl[3] = (int32_t)tiles;
+    int64_t i = 0, t0 = 0;
+    for (const Request &q : batch) {
+        const int64_t t = (s->mats[(size_t)q.mid].A.n_rows + SERVE_RPB - 1) / SERVE_RPB;
+        Request r = q;
+        for (int j = 0; j < q.total; j++, i++) {
+            r.op = j;
+            ops[i] = op_of(s, r);
+            first[i] = (int32_t)t0;
+            dep[i] = j == 0 ? -1 : (int32_t)(i - 1);
+            done[i] = 0;
+            t0 += t;
+        }
+    }
+    first[nops] = (int32_t)tiles;
+    hipStream_t ps = s->ps[s->steps % PSTREAMS];
+    char *d = s->d_plan[slot];
+    PersistPlan p;
+    p.ctl = (int32_t *)d;
+    p.first = p.ctl + 4;
+    p.dep = p.first + nops + 1;
+    p.done = (int32_t *)p.dep + nops;
+    p.ops = (const SweepArgs *)(d + ops_off);
+    p.nops = (int)nops;
+    p.spin_limit = s->spin_limit;
+    e = hipEventRecord(s->ev_in, s->stream); // b and x are produced on the caller's stream
+    if (e == hipSuccess) e = hipStreamWaitEvent(ps, s->ev_in, 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, s->h_plan[slot], bytes, hipMemcpyHostToDevice, ps);
+    if (e == hipSuccess) e = launch_sweep_persist(p, (int)grid, ps);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->h_ctl[slot], d, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, ps);
+    if (e == hipSuccess) e = hipEventRecord(s->ev[slot], ps);
+    if (e != hipSuccess) return fail(s, e);
+    s->slot_reqs[slot] = (int)batch.size();
+    s->inflight += (int)batch.size();
+    const int64_t step = s->steps++;
+    for (const Request &q : batch) {
+        s->finish_step[q.ticket] = step;
+        s->to_release.push_back({step, q.ws});
+    }
+    return SILU_OK;
+}
+
+int destroy_persistent(silu_server *s)
+{
+    for (int i = 0; i < PSTREAMS; i++) {
+        if (s->ps[i]) {
+            (void)hipStreamSynchronize(s->ps[i]);
+            (void)hipStreamDestroy(s->ps[i]);
+            s->ps[i] = nullptr;
+        }
+    }
+    if (s->ev_in) (void)hipEventDestroy(s->ev_in);
+    s->ev_in = nullptr;
+    for (int i = 0; i < RING; i++) {
+        (void)hipHostFree(s->h_plan[i]);
+        (void)hipFree(s->d_plan[i]);
+        (void)hipHostFree(s->h_ctl[i]);
+        s->h_plan[i] = nullptr;
+        s->d_plan[i] = nullptr;
+        s->h_ctl[i] = nullptr;
+        s->plan_cap[i] = 0;
+    }
+    return SILU_OK;
+}
+
+int create_persistent(silu_server *s)
+{
+    hipError_t e;
+    for (int i = 0; i < PSTREAMS; i++)
+        if (!s->ps[i] && (e = hipStreamCreateWithFlags(&s->ps[i], hipStreamNonBlocking)) != hipSuccess)
+            return fail(s, e);
+    if (!s->ev_in && (e = hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming)) != hipSuccess) return fail(s, e);
+    for (int i = 0; i < RING; i++) {
+        if (!s->h_ctl[i]) {
+            if ((e = hipHostMalloc((void **)&s->h_ctl[i], 4 * sizeof(int32_t))) != hipSuccess) return fail(s, e);
+            s->h_ctl[i][1] = 0;
+        }
+    }
+    return SILU_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -259,6 +439,7 @@ int silu_server_destroy(silu_server *s)
 {
     if (!s) return SILU_ERR_ARG;
     (void)hipStreamSynchronize(s->stream);
+    destroy_persistent(s);
     for (int i = 0; i < RING; i++) {
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
         (void)hipHostFree(s->h_ops[i]);
@@ -313,6 +494,32 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
 {
     if (!s) return SILU_ERR_ARG;
     reap(s);
+    if (s->mode == 1) {
+        std::vector<Request> batch;
+        while (!s->queue.empty() && s->inflight + (int)batch.size() < s->max_active) {
+            Request &q = s->queue.front();
+            Range r;
+            if (!allocate(s, (size_t)silu_server_request_bytes(s, q.mid), &r)) break;
+            q.ws = r;
+            batch.push_back(q);
+            s->queue.pop_front();
+        }
+        if (!batch.empty()) {
+            const int st = launch_persistent(s, batch);
+            if (st == SILU_ERR_UNSUPPORTED) { // rejected before anything was enqueued
+                for (const Request &q : batch) release(s, q.ws);
+                for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
+                    Request q = *it;
+                    q.ws = {0, 0};
+                    s->queue.push_front(q);
+                }
+            }
+            if (st) return st; // a HIP failure leaves the server unusable
+        }
+        if (n_active) *n_active = s->inflight;
+        if (n_queued) *n_queued = (int)s->queue.size();
+        return SILU_OK;
+    }
     // admission in arrival order while the workspace fits (no overtaking)
     while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
         Request &q = s->queue.front();
@@ -323,29 +530,40 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         s->queue.pop_front();
     }
     if (!s->active.empty()) {
-        int st = grow(s, (int)s->active.size());
-        if (st) return st;
-        const int slot = (int)(s->steps % RING);
-        if (s->steps >= RING) { // the staging slot was used RING steps ago
-            hipError_t e = hipEventSynchronize(s->ev[slot]);
-            if (e != hipSuccess) return fail(s, e);
-            reap(s);
-        }
-        SweepArgs *ops = s->h_ops[slot];
-        int32_t *first = s->h_first[slot];
-        int total = 0;
         const int nops = (int)s->active.size();
-        for (int i = 0; i < nops; i++) {
-            ops[i] = op_of(s, s->active[(size_t)i]);
-            first[i] = total;
-            total += (ops[i].n + SERVE_RPB - 1) / SERVE_RPB;
+        int st = nops > BATCH_ARG_OPS ? grow(s, nops) : SILU_OK;
+        if (st) return st;
+        int slot;
+        st = take_slot(s, &slot); // the staging slot was used RING steps ago
+        if (st) return st;
+        hipError_t e;
+        if (nops <= BATCH_ARG_OPS) { // the op table travels in the kernel arguments
+            BatchArgs ba;
+            int total = 0;
+            for (int i = 0; i < nops; i++) {
+                ba.op[i] = op_of(s, s->active[(size_t)i]);
+                ba.first[i] = total;
+                total += (ba.op[i].n + SERVE_RPB - 1) / SERVE_RPB;
+            }
+            ba.first[nops] = total;
+            ba.nops = nops;
+            e = launch_sweep_batch_args(ba, s->stream);
+        } else {
+            SweepArgs *ops = s->h_ops[slot];
+            int32_t *first = s->h_first[slot];
+            int total = 0;
+            for (int i = 0; i < nops; i++) {
+                ops[i] = op_of(s, s->active[(size_t)i]);
+                first[i] = total;
+                total += (ops[i].n + SERVE_RPB - 1) / SERVE_RPB;
+            }
+            first[nops] = total;
+            e = hipMemcpyAsync(s->d_ops, ops, sizeof(SweepArgs) * (size_t)nops, hipMemcpyHostToDevice, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->d_first, first, sizeof(int32_t) * (size_t)(nops + 1), hipMemcpyHostToDevice,
+                                   s->stream);
+            if (e == hipSuccess) e = launch_sweep_batch(SERVE_RPB, s->d_ops, s->d_first, nops, total, s->stream);
         }
-        first[nops] = total;
-        hipError_t e = hipMemcpyAsync(s->d_ops, ops, sizeof(SweepArgs) * (size_t)nops, hipMemcpyHostToDevice, s->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(s->d_first, first, sizeof(int32_t) * (size_t)(nops + 1), hipMemcpyHostToDevice,
-                               s->stream);
-        if (e == hipSuccess) e = launch_sweep_batch(SERVE_RPB, s->d_ops, s->d_first, nops, total, s->stream);
         if (e == hipSuccess) e = hipEventRecord(s->ev[slot], s->stream);
         if (e != hipSuccess) return fail(s, e);
         const int64_t step = s->steps++;
@@ -378,7 +596,33 @@ int silu_server_poll(silu_server *s, int64_t ticket, int *state)
         return SILU_OK;
     }
     reap(s);
-    *state = it->second <= s->completed_through ? 3 : 2;
+    *state = step_done(s, it->second) ? 3 : 2;
+    if (*state == 3 && std::find(s->failed.begin(), s->failed.end(), it->second) != s->failed.end())
+        return SILU_ERR_TIMEOUT;
+    return SILU_OK;
+}
+
+int silu_server_set_wait_limit(silu_server *s, int polls)
+{
+    if (!s || polls < 0) return SILU_ERR_ARG;
+    s->spin_limit = polls ? polls : PERSIST_SPIN_LIMIT;
+    return SILU_OK;
+}
+
+int silu_server_set_mode(silu_server *s, int mode, int max_workgroups)
+{
+    if (!s || (mode != SILU_SERVE_STEPWISE && mode != SILU_SERVE_PERSISTENT) || max_workgroups < 0 ||
+        max_workgroups > 65535)
+        return SILU_ERR_ARG;
+    reap(s);
+    if (!s->queue.empty() || !s->active.empty() || s->completed_through + 1 < s->steps) return SILU_ERR_ARG;
+    if (mode == SILU_SERVE_PERSISTENT && !PERSISTENT_AVAILABLE) return SILU_ERR_UNSUPPORTED;
+    if (mode == SILU_SERVE_PERSISTENT) {
+        const int st = create_persistent(s);
+        if (st) return st;
+    }
+    s->mode = mode == SILU_SERVE_PERSISTENT ? 1 : 0;
+    s->max_wg = max_workgroups ? max_workgroups : DEFAULT_MAX_WG;
     return SILU_OK;
 }
 

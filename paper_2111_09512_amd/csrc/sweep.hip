@@ -380,6 +380,88 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch(const SweepArgs *_
     stream_rows<T, BLOCK, RPB, CAP, IDX32>(ops[lo], b - first[lo], nullptr, 0, nullptr, 0);
 }
 
+// The same with the op table in the kernel arguments.
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch_args(BatchArgs ba)
+{
+    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    int lo = 0, hi = ba.nops - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ba.first[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    stream_rows<T, BLOCK, RPB, CAP, IDX32>(ba.op[lo], b - ba.first[lo], nullptr, 0, nullptr, 0);
+}
+
+// Persistent batched CSR-stream: one launch runs whole chains of sweeps (all
+// the ops of several requests).  The tiles of every op (RPB rows each) form
+// one queue, numbered in the plan's op order, in which each op comes after
+// the op it depends on (the previous sweep of its request).  A workgroup
+// takes the next tile number from ctl[0]; before running a tile of an op
+// with a dependency it waits until done[dep] counts every tile of that op.
+// The wait cannot deadlock: the tiles it waits for have smaller numbers, so
+// workgroups that are already running took them, and the smallest unfinished
+// tile never waits.  Each wait is bounded (p.spin_limit polls, each after a
+// short sleep): on expiry the op's index + 1 goes to ctl[1], the tile is
+// skipped and still counted, so every workgroup drains in bounded time and
+// the host reports the failure.
+// Memory order: every XCD has its own L2, so the counters are updated and
+// polled at system scope, which places them beyond the L2s (an agent-scope
+// atomic is performed in the issuing XCD's L2, where a poll from another XCD
+// need not see it).  A finished tile's stores reach memory through each
+// thread's fence (L2 write-back) before the barrier and the count; the
+// waiting thread fences (L2 invalidate) after observing the count, before the
+// barrier that releases its workgroup.
+template <class T, int BLOCK, int RPB, int CAP>
+__global__ void __launch_bounds__(BLOCK) k_sweep_persist(PersistPlan p)
+{
+    __shared__ int s_tile, s_op, s_skip;
+    const int total = p.first[p.nops];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int t = __hip_atomic_fetch_add(&p.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            int op = 0, skip = 0;
+            if (t < total) {
+                int lo = 0, hi = p.nops - 1; // largest op with first[op] <= t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (p.first[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                op = lo;
+                const int d = p.dep[op];
+                if (d >= 0) {
+                    const int need = p.first[d + 1] - p.first[d];
+                    int polls = 0;
+                    while (__hip_atomic_load(&p.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
+                        __builtin_amdgcn_s_sleep(4);
+                        if (++polls >= p.spin_limit) {
+                            int zero = 0;
+                            __hip_atomic_compare_exchange_strong(&p.ctl[1], &zero, op + 1, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                            skip = 1;
+                            break;
+                        }
+                    }
+                    __threadfence();
+                }
+            }
+            s_tile = t;
+            s_op = op;
+            s_skip = skip;
+        }
+        __syncthreads();
+        const int t = s_tile, op = s_op, skip = s_skip;
+        __syncthreads();
+        if (t >= total) return;
+        if (!skip) stream_rows<T, BLOCK, RPB, CAP, IDX32>(p.ops[op], t - p.first[op], nullptr, 0, nullptr, 0);
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(&p.done[op], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CSR-stream over a row-block partition: workgroup b owns rows
 // [blk[b].row, blk[b+1].row) whose entries are [blk[b].ent, blk[b+1].ent): at
@@ -696,6 +778,20 @@ hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_
                               hipStream_t s)
 {
     return dispatch_batch<TF64>(rpb, d_ops, d_first, nops, total, s);
+}
+
+hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s)
+{
+    if (b.nops <= 0 || b.nops > BATCH_ARG_OPS || b.first[b.nops] <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_stream_batch_args<TF64, 256, 256, 1024>), dim3(b.first[b.nops]), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_persist(const PersistPlan &p, int grid, hipStream_t s)
+{
+    if (p.nops <= 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_persist<TF64, 256, PERSIST_RPB, 1024>), dim3(grid), dim3(256), 0, s, p);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name)

@@ -3,7 +3,9 @@
 Each request's result in the mix must equal the same request run alone
 (ilu_smooth) bit for bit, and the oracle's; admission respects the workspace
 arena; every request completes (no starvation), including requests that
-arrive while others are running."""
+arrive while others are running.  Both scheduling modes: one batched launch
+per sweep (stepwise), and one persistent launch per admitted batch whose
+requests chain their sweeps through device-side counters."""
 import numpy as np
 import pytest
 import torch
@@ -74,10 +76,18 @@ def _drain(server, tickets, max_steps=100000):
     return steps
 
 
-def test_mix_equals_alone_and_oracle(orc, B, ctx, pool):
-    say("serving: mix vs alone")
+# The persistent mode is switched off in the library (set_mode refuses it):
+# its launches did not finish on MI355X, and the cause is not yet found.
+OFF = pytest.mark.skip(reason="persistent serving mode switched off: its launches did not finish on MI355X "
+                              "(counters at agent and at system scope); cause not yet found")
+MODES = [False, pytest.param(True, marks=OFF)]
+
+
+@pytest.mark.parametrize("persistent", MODES, ids=["stepwise", "persistent"])
+def test_mix_equals_alone_and_oracle(orc, B, ctx, pool, persistent):
+    say(f"serving: mix vs alone, persistent={persistent}")
     reqs = _requests(pool, 60, seed=1)
-    server = B.Server(ctx, arena_bytes=64 << 20, max_active=64)
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=64, persistent=persistent)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
     xs, tickets = [], []
     for r in reqs:
@@ -95,16 +105,17 @@ def test_mix_equals_alone_and_oracle(orc, B, ctx, pool):
     server.close()
 
 
-def test_admission_by_workspace_budget(B, ctx, pool):
+@pytest.mark.parametrize("persistent", MODES, ids=["stepwise", "persistent"])
+def test_admission_by_workspace_budget(B, ctx, pool, persistent):
     """An arena that holds exactly two of the largest requests: never more
     active than fit, and everything completes in order of arrival."""
-    say("serving: admission")
+    say(f"serving: admission, persistent={persistent}")
     big = len(pool) - 1
     server = B.Server(ctx, arena_bytes=1 << 30, max_active=1000)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
     per = server.request_bytes(mids[big])
     server.close()
-    server = B.Server(ctx, arena_bytes=2 * per, max_active=1000)
+    server = B.Server(ctx, arena_bytes=2 * per, max_active=1000, persistent=persistent)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
     n = pool[big]["A"].n
     tickets, xs = [], []
@@ -136,12 +147,13 @@ def test_admission_by_workspace_budget(B, ctx, pool):
     server.close()
 
 
-def test_arrivals_while_running(B, ctx, pool):
+@pytest.mark.parametrize("persistent", MODES, ids=["stepwise", "persistent"])
+def test_arrivals_while_running(B, ctx, pool, persistent):
     """Requests submitted between steps join running ones; each still equals
     its lone run."""
-    say("serving: staggered arrivals")
+    say(f"serving: staggered arrivals, persistent={persistent}")
     reqs = _requests(pool, 40, seed=7)
-    server = B.Server(ctx, arena_bytes=32 << 20, max_active=16)
+    server = B.Server(ctx, arena_bytes=32 << 20, max_active=16, persistent=persistent)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
     xs, tickets = [], []
     for i, r in enumerate(reqs):
@@ -172,4 +184,102 @@ def test_serving_errors(B, ctx, pool):
     with pytest.raises(B.SiluError) as e:
         server.register(pool[0]["Ad"], Fu)
     assert e.value.status == -8
+    server.close()
+
+
+@pytest.fixture(scope="module")
+def big_pool(orc, B, ctx):
+    """Two larger matrices (1,024 and 432 row tiles of 256 rows), so that a
+    persistent launch has many workgroups waiting on each other's tiles."""
+    out = []
+    for j, N in enumerate((64, 48)):
+        A = W.vardens7(N, seed_rho=20 + j, with_cuts=False)
+        Ls, U = orc.ilu0(A)
+        Ad, Ld, Ud = B.Csr.from_host(A), B.Csr.from_host(Ls), B.Csr.from_host(U)
+        out.append(dict(A=A, Ad=Ad, F=ctx.ilu_scale_factors(Ld, Ud)))
+    torch.cuda.synchronize()
+    return out
+
+
+@OFF
+@pytest.mark.parametrize("max_wg", [1, 7, 300, 0])
+def test_persistent_large_equals_alone(B, ctx, big_pool, max_wg):
+    """Any workgroup cap (one workgroup runs the queue in order; 0 = the
+    default) gives the lone results bit for bit, with requests on both
+    matrices in one launch and further launches overlapping it."""
+    say(f"serving: persistent large, max_wg={max_wg}")
+    server = B.Server(ctx, arena_bytes=512 << 20, max_active=64, persistent=True, max_workgroups=max_wg)
+    mids = [server.register(p["Ad"], p["F"]) for p in big_pool]
+    reqs, xs, tickets = [], [], []
+    for k in range(6):
+        mid = k % 2
+        n = big_pool[mid]["A"].n
+        r = dict(mid=mid, b=W.rhs(n, 900 + k), x0=W.rhs(n, 950 + k) * (k % 3 == 0), outer=1 + k % 3, mL=3, mU=3)
+        reqs.append(r)
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[mid], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+        if k % 2:
+            server.step()
+    _drain(server, tickets)
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, big_pool, r))
+    server.close()
+
+
+@OFF
+def test_persistent_wait_limit_reports_timeout(B, ctx, big_pool):
+    """The failure path, forced from the host: with a wait limit of one poll
+    nearly every dependent tile gives up at once, the launch still drains, and
+    poll reports SILU_ERR_TIMEOUT; the server then serves normally again."""
+    say("serving: persistent wait limit")
+    server = B.Server(ctx, arena_bytes=512 << 20, max_active=64, persistent=True, max_workgroups=1024)
+    mid = server.register(big_pool[0]["Ad"], big_pool[0]["F"])
+    n = big_pool[0]["A"].n
+    server.set_wait_limit(1)
+    tickets = [server.submit(mid, dev(W.rhs(n, k)), dev(np.zeros(n)), 2, 3, 3) for k in range(4)]
+    server.step()
+    torch.cuda.synchronize()
+    timeouts = 0
+    left = set(tickets)
+    for _ in range(100000):
+        for t in list(left):
+            try:
+                if server.poll(t) == server.DONE:
+                    left.discard(t)
+            except B.SiluError as e:
+                assert e.status == -9
+                timeouts += 1
+                left.discard(t)
+        if not left:
+            break
+    assert not left and timeouts >= 1
+    server.set_wait_limit(0)
+    r = dict(mid=0, b=W.rhs(n, 77), x0=np.zeros(n), outer=2, mL=3, mU=3)
+    x = dev(r["x0"])
+    t = server.submit(mid, dev(r["b"]), x, 2, 3, 3)
+    _drain(server, [t])
+    np.testing.assert_array_equal(host(x), _alone(ctx, big_pool, r))
+    server.close()
+
+
+def test_set_mode_rules(B, ctx, pool):
+    say("serving: set_mode rules")
+    server = B.Server(ctx, arena_bytes=8 << 20, max_active=4)
+    mid = server.register(pool[0]["Ad"], pool[0]["F"])
+    n = pool[0]["A"].n
+    for bad in [(2, 0), (1, -1), (1, 70000)]:
+        with pytest.raises(B.SiluError) as e:
+            server.set_mode(*bad)
+        assert e.value.status == -1
+    t = server.submit(mid, dev(W.rhs(n, 0)), dev(np.zeros(n)), 1, 3, 3)
+    with pytest.raises(B.SiluError) as e:  # a request is queued
+        server.set_mode(server.PERSISTENT)
+    assert e.value.status == -1
+    _drain(server, [t])
+    torch.cuda.synchronize()
+    with pytest.raises(B.SiluError) as e:  # switched off in this build
+        server.set_mode(server.PERSISTENT, 16)
+    assert e.value.status == -8
+    server.set_mode(server.STEPWISE)
     server.close()
