@@ -395,18 +395,23 @@ int silu_release(silu_ctx *ctx, const void *row_ptr, const void *col_idx);
 /*
  * Per-kernel timing.  With timing on, every kernel launch the context makes
  * is bracketed by a pair of HIP events recorded on the context stream, and the
- * launch is credited with its algorithmic HBM bytes (each CSR entry read once,
- * each dense vector read or written once).  silu_stats_collect synchronizes
- * the stream and folds the recorded events into per-kernel totals; it
- * returns the number of kernel kinds seen.  silu_stats_get reads entry idx:
- * kernel name (NUL-terminated, truncated to name_len), launch count, summed
- * duration in milliseconds and summed algorithmic bytes.  silu_stats_reset
- * clears them.
+ * launch is credited with two byte counts.  Algorithmic bytes: the CSR form of
+ * the step -- every entry of the matrix read once as its value plus a 4-byte
+ * column index, 4 bytes of row pointer per row, every dense vector read or
+ * written once.  Layout bytes: what the layout the kernel actually streams
+ * occupies (a sliced copy's padded slots, 1- or 2-byte column codes and slice
+ * tables; 16-bit offsets), never more than the algorithmic bytes by more than
+ * the padding.  silu_stats_collect synchronizes the stream and folds the
+ * recorded events into per-kernel totals; it returns the number of kernel
+ * kinds seen.  silu_stats_get reads entry idx: kernel name (NUL-terminated,
+ * truncated to name_len), launch count, summed duration in milliseconds,
+ * summed algorithmic bytes and summed layout bytes (either pointer may be
+ * NULL).  silu_stats_reset clears them.
  */
 int silu_set_timing(silu_ctx *ctx, int enable);
 int silu_stats_collect(silu_ctx *ctx);
 int silu_stats_get(silu_ctx *ctx, int idx, char *name, int name_len, int64_t *launches, double *ms,
-                   double *bytes);
+                   double *bytes, double *layout_bytes);
 int silu_stats_reset(silu_ctx *ctx);
 
 /* Plain device copy dst[0..bytes) = src[0..bytes) with a streaming kernel

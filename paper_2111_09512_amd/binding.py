@@ -108,7 +108,7 @@ _sig = {
     "silu_set_timing": (C.c_int, [_P, C.c_int]),
     "silu_stats_collect": (C.c_int, [_P]),
     "silu_stats_get": (C.c_int, [_P, C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                 C.POINTER(C.c_double)]),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "silu_stats_reset": (C.c_int, [_P]),
     "silu_stream_copy": (C.c_int, [_P, _P, _P, C.c_size_t]),
     "silu_factor_iluk": (C.c_int, [C.POINTER(silu_host_csr), C.c_int, C.POINTER(silu_host_csr),
@@ -498,10 +498,11 @@ class Context:
         out = {}
         buf = C.create_string_buffer(64)
         for i in range(k):
-            la, ms, by = C.c_int64(), C.c_double(), C.c_double()
-            self._check(_lib.silu_stats_get(self._h, i, buf, 64, C.byref(la), C.byref(ms), C.byref(by)),
+            la, ms, by, lb = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            self._check(_lib.silu_stats_get(self._h, i, buf, 64, C.byref(la), C.byref(ms), C.byref(by), C.byref(lb)),
                         "silu_stats_get")
-            out[buf.value.decode()] = {"launches": la.value, "ms": ms.value, "bytes": by.value}
+            out[buf.value.decode()] = {"launches": la.value, "ms": ms.value, "bytes": by.value,
+                                       "layout_bytes": lb.value}
         return out
 
     def stats_reset(self):

@@ -91,7 +91,7 @@ using GraphKey = std::tuple<const void *, const void *, const void *, const void
 struct Pending {
     int kid;
     hipEvent_t e0, e1;
-    double bytes;
+    double bytes, layout;
 };
 
 } // namespace
@@ -113,7 +113,7 @@ struct silu_ctx {
     std::vector<hipEvent_t> free_events;
     std::vector<std::string> knames;
     std::vector<int64_t> klaunch;
-    std::vector<double> kms, kbytes;
+    std::vector<double> kms, kbytes, klayout;
 };
 
 namespace {
@@ -138,6 +138,7 @@ int kernel_id(silu_ctx *c, const char *name)
     c->klaunch.push_back(0);
     c->kms.push_back(0.0);
     c->kbytes.push_back(0.0);
+    c->klayout.push_back(0.0);
     return (int)c->knames.size() - 1;
 }
 
@@ -152,8 +153,10 @@ hipError_t get_event(silu_ctx *c, hipEvent_t *e)
 }
 
 // Launch through `fn(const char** name)`, bracketed by timing events when on.
+// bytes: the launch's algorithmic bytes; layout: the bytes its data layout
+// actually moves (differs from bytes only for compressed sweep layouts).
 template <class F>
-int timed_launch(silu_ctx *c, double bytes, F &&fn)
+int timed_launch(silu_ctx *c, double bytes, double layout, F &&fn)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -166,9 +169,15 @@ int timed_launch(silu_ctx *c, double bytes, F &&fn)
     if (err != hipSuccess) return hip_fail(c, err);
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
-        c->pending.push_back({kernel_id(c, name), e0, e1, bytes});
+        c->pending.push_back({kernel_id(c, name), e0, e1, bytes, layout});
     }
     return SILU_OK;
+}
+
+template <class F>
+int timed_launch(silu_ctx *c, double bytes, F &&fn)
+{
+    return timed_launch(c, bytes, bytes, fn);
 }
 
 bool csr_ok(const silu_csr *M, int dtype)
@@ -240,8 +249,9 @@ double epi_bytes(Prec p, int64_t n, int epi, bool dshift)
     return b;
 }
 
-// Algorithmic bytes of a CSR sweep: each entry (value + ib bytes of index)
-// and the row pointers read once, the gathered iterate and the rhs once.
+// Bytes of a CSR sweep: each entry (value + ib bytes of index) and the row
+// pointers read once, the gathered iterate and the rhs once.  With ib = 4
+// (the int32 column) these are the sweep's algorithmic bytes.
 double sweep_bytes(Prec p, int64_t n, int64_t nnz, int epi, bool dshift, double ib)
 {
     double vb = 8, xb = 8, rb = 8;
@@ -576,12 +586,15 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     a.dshift = dshift;
     const bool upd = epi == EPI_UPDATE || epi == EPI_SCALE_UPDATE;
     a.dcol = upd ? dcol : nullptr;
-    double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, (g.off16 || g.lw) ? 2.0 : 4.0);
+    double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, 4.0);
+    double layout = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, (g.off16 || g.lw) ? 2.0 : 4.0);
     if (sliced_bytes >= 0.0) // the sliced layout's own bytes: padded slots, codes, slice tables
-        bytes = sliced_bytes + epi_bytes(p, N->n_rows, epi, dshift != nullptr);
-    if (epi == EPI_SPMV) bytes -= (p == Prec::MIX_U ? 4.0 : 8.0) * (double)N->n_rows; // no rhs read
-    if (a.dcol) bytes += 8.0 * (double)N->n_rows;
-    return timed_launch(c, bytes, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
+        layout = sliced_bytes + epi_bytes(p, N->n_rows, epi, dshift != nullptr);
+    const double adj = (epi == EPI_SPMV ? -(p == Prec::MIX_U ? 4.0 : 8.0) : 0.0) * (double)N->n_rows + // no rhs read
+                       (a.dcol ? 8.0 : 0.0) * (double)N->n_rows;
+    bytes += adj;
+    layout += adj;
+    return timed_launch(c, bytes, layout, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
 
 // ---- level analysis (Section 4: level-set scheduling) ----------------------
@@ -1538,6 +1551,7 @@ int silu_stats_collect(silu_ctx *c)
         c->klaunch[(size_t)p.kid] += 1;
         c->kms[(size_t)p.kid] += ms;
         c->kbytes[(size_t)p.kid] += p.bytes;
+        c->klayout[(size_t)p.kid] += p.layout;
         c->free_events.push_back(p.e0);
         c->free_events.push_back(p.e1);
     }
@@ -1545,7 +1559,8 @@ int silu_stats_collect(silu_ctx *c)
     return (int)c->knames.size();
 }
 
-int silu_stats_get(silu_ctx *c, int idx, char *name, int name_len, int64_t *launches, double *ms, double *bytes)
+int silu_stats_get(silu_ctx *c, int idx, char *name, int name_len, int64_t *launches, double *ms, double *bytes,
+                   double *layout_bytes)
 {
     if (!c || idx < 0 || idx >= (int)c->knames.size()) return SILU_ERR_ARG;
     if (name && name_len > 0) {
@@ -1555,6 +1570,7 @@ int silu_stats_get(silu_ctx *c, int idx, char *name, int name_len, int64_t *laun
     if (launches) *launches = c->klaunch[(size_t)idx];
     if (ms) *ms = c->kms[(size_t)idx];
     if (bytes) *bytes = c->kbytes[(size_t)idx];
+    if (layout_bytes) *layout_bytes = c->klayout[(size_t)idx];
     return SILU_OK;
 }
 
@@ -1567,6 +1583,7 @@ int silu_stats_reset(silu_ctx *c)
         c->klaunch[i] = 0;
         c->kms[i] = 0.0;
         c->kbytes[i] = 0.0;
+        c->klayout[i] = 0.0;
     }
     return SILU_OK;
 }
