@@ -13,7 +13,9 @@ FP32-inner mixed form, the smoother on row/column (Ruiz) scaled factors, the
 polynomial Gauss-Seidel smoother (time and residual after one application
 beside the ILU smoother's), FGMRES(30) with the smoother as preconditioner
 solved to 1e-8 (steps, time, NRBE), ILU(0) computed on the device by
-fixed-point sweeps against the host ILU(0), a streaming-copy bandwidth
+fixed-point sweeps against the host ILU(0), one outer step with 1..8 inner
+iterations on row-scaled and on unscaled factors (time and residual), a
+streaming-copy bandwidth
 calibration, the roofline of the dominant kernel from per-launch HIP events,
 the CPU oracle timed on a bounded sample of the same operator, and the serving
 stream (1,280 requests on 64 resident matrices, continuous batching vs one at
@@ -169,6 +171,7 @@ def main():
     ap.add_argument("--no-gs", action="store_true")
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-fixed-point", action="store_true")
+    ap.add_argument("--no-inner-sweep", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -371,6 +374,29 @@ def main():
             del Lg, Ug, Fg
         del Ah
 
+    # ---- inner iterations 1..8, row-scaled against unscaled factors (one outer step from x = 0) ----
+    inner_sweep = None
+    if not args.no_inner_sweep:
+        Fu = ctx.ilu_scale_factors(Ld, Ud, scale=False)
+        nb = ctx.dot(bvec, bvec) ** 0.5
+        inner_sweep = []
+        for m in range(1, 9):
+            row = {"m": m}
+            for label, Fm in (("scaled", F), ("unscaled", Fu)):
+                def app_m():
+                    ctx.ilu_smooth(Ad, Fm, bvec, x, 1, m, m, kernel=kern, ws=ws)
+
+                ms_m = time_steps(torch, app_m, 10, 2)
+                x.zero_()
+                app_m()
+                r = bvec - ctx.spmv(Ad, x)
+                rr = ctx.dot(r, r) ** 0.5 / nb
+                row[label] = {"ms": ms_m, "relres_after_one_app": rr if np.isfinite(rr) else None}
+            inner_sweep.append(row)
+            log(f"inner m={m}: scaled {row['scaled']['ms']:.3f} ms relres {row['scaled']['relres_after_one_app']}, "
+                f"unscaled {row['unscaled']['ms']:.3f} ms relres {row['unscaled']['relres_after_one_app']}")
+        del Fu
+
     # ---- direct (level-scheduled) form ----
     ms_direct = None
     depths = None
@@ -433,6 +459,7 @@ def main():
         "gauss_seidel": gs,
         "fgmres": krylov,
         "ilu0_fixed_point": fixed_point,
+        "inner_sweep": inner_sweep,
         "direct_apps_per_s": (1e3 / ms_direct) if ms_direct else None,
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,
