@@ -5,7 +5,8 @@ grid, n = 8,000,000, ILUT(1e-3, 20) factors, row-scaled, 2 outer smoothing
 steps x 4 Richardson iterations per factor, b ~ U(-1,1) seed 0, x0 = 0.
 
 One step = one FP64 smoother application (ilu_smooth: residual, L sweeps with
-fused D^{-1}, U sweeps with fused x update, twice).  `value` is FP64 smoother
+fused D^{-1}, U sweeps with fused x update, twice).  The same application is
+also timed replayed from a recorded hipGraph (SILU_GRAPH).  `value` is FP64 smoother
 applications per second with every input resident in HBM.  In the same run,
 and reported in the same JSON line: the level-scheduled direct form (the same
 smoother with both triangular solves done by level-set substitution), the
@@ -258,6 +259,16 @@ def main():
     ach = dv["bytes"] / dv["launches"] / avg_s / 1e9
     ach_layout = dv["layout_bytes"] / dv["launches"] / avg_s / 1e9
 
+    # ---- the same application replayed from a recorded hipGraph (SILU_GRAPH) ----
+    def app_graph():
+        x.zero_()
+        ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, record=True)
+
+    app_graph()  # the first call records
+    ms_graph = time_steps(torch, app_graph, args.steps, args.warmup)
+    graph_same = bool(torch.equal(x, x64))
+    log(f"graph replay: {ms_graph:.3f} ms/app ({1e3 / ms_graph:.1f} apps/s), identical to plain launches: {graph_same}")
+
     # ---- mixed form ----
     ms_mixed = bytes_mixed = mixed_err = None
     st_mixed = {}
@@ -450,6 +461,9 @@ def main():
         "layout_GBps": layout_app / (ms * 1e-3) / 1e9,
         "layout_bytes_per_app": layout_app,
         "copy_GBps": copy_gbps,
+        "graph_ms": ms_graph,
+        "graph_apps_per_s": 1e3 / ms_graph,
+        "graph_identical": graph_same,
         "mixed_apps_per_s": (1e3 / ms_mixed) if ms_mixed else None,
         "mixed_ms": ms_mixed,
         "mixed_GBps": (bytes_mixed / (ms_mixed * 1e-3) / 1e9) if ms_mixed else None,

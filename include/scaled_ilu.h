@@ -69,6 +69,7 @@ extern "C" {
 #define SILU_CODE16 0x8000        /* sliced sweeps: no diagonal table (16-bit codes or wider) */
 #define SILU_ZERO_GUESS 0x10000   /* ilu_smooth: x is zero on entry, so the first residual   */
                                   /* is b itself (skips one pass over A when m_L >= 2)       */
+#define SILU_GRAPH 0x20000        /* ilu_smooth: replay the call's sweeps from a hipGraph    */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -235,6 +236,16 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
  * a synchronous scan of x (returns NONFINITE); SILU_VALIDATE checks the CSR
  * structures first.  With F->scaled == 0 (SILU_NO_SCALING) the U loop is the
  * unscaled Richardson iteration z <- y - (U - I) z (FP64 only).
+ * SILU_GRAPH (iterative form; ignored with SILU_DIRECT, whose level sweeps
+ * are captured anyway): the first call with a given set of arguments (the
+ * matrices' and vectors' pointers, sizes, counts and flags) runs as usual and
+ * then records its whole launch sequence into a hipGraph kept in the context;
+ * later calls with the same arguments replay it with one launch, on the same
+ * data layouts, with the same results bit for bit.  The graph bakes in the
+ * pointers: the caller keeps b, x and ws at those addresses, and any
+ * silu_release on the context drops every recorded graph (the cached layouts
+ * they read may be rebuilt).  If the sequence cannot be recorded the call
+ * still succeeds and later calls run unrecorded.
  * ws: workspace of at least silu_workspace_size(ctx, n, flags) bytes.
  * Asynchronous on the context stream (unless CHECK_FINITE / VALIDATE).
  * Errors: ARG (null, outer_sweeps < 1, m_L < 1 or m_U < 1 in ITER mode,

@@ -32,7 +32,7 @@ SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
-SILU_CODE16, SILU_ZERO_GUESS = 0x8000, 0x10000
+SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH = 0x8000, 0x10000, 0x20000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
@@ -436,13 +436,15 @@ class Context:
     def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
                    m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
                    validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None,
-                   graph: bool = True, zero_guess: bool = False) -> torch.Tensor:
+                   graph: bool = True, zero_guess: bool = False, record: bool = False) -> torch.Tensor:
         """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned).
-        zero_guess: x holds zeros on entry (the first residual is b)."""
+        zero_guess: x holds zeros on entry (the first residual is b).
+        record: replay the call's sweep sequence from a hipGraph recorded on the
+        first call with the same tensors and counts (SILU_GRAPH)."""
         m_U = m_L if m_U is None else m_U
         flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) | (SILU_ZERO_GUESS if zero_guess else 0) |
                  (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
-                 (0 if graph else SILU_NO_GRAPH) | KERNELS[kernel])
+                 (0 if graph else SILU_NO_GRAPH) | (SILU_GRAPH if record else 0) | KERNELS[kernel])
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws

@@ -9,6 +9,7 @@
 //     z_k = s - Us z_{k-1},  k = 2..m_U     (z_1 = s; the last launch does x += z)
 // so 1 + (m_L - 1) + (m_U - 1) launches, each streaming one CSR matrix once.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <cstring>
 #include <map>
@@ -94,6 +95,13 @@ struct Pending {
     double bytes, layout;
 };
 
+// A recorded smoother call: the arguments that fix its launch sequence.
+using SmoothKey = std::array<uintptr_t, 24>;
+struct SmoothGraph {
+    hipGraphExec_t ex = nullptr; // null: the sequence could not be recorded
+    double bytes = 0.0, layout = 0.0;
+};
+
 } // namespace
 
 struct silu_ctx {
@@ -107,7 +115,10 @@ struct silu_ctx {
     std::map<CompKey, Compressed> comp;
     std::map<SlicedKey, Sliced> sliced;
     std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<SmoothKey, SmoothGraph> smooth_graphs;
     hipStream_t capture_stream = nullptr; // private, default priority, for graph capture
+    bool recording = false;               // launches go into a capture: add up their bytes
+    double rec_bytes = 0.0, rec_layout = 0.0;
     bool timing = false;
     std::vector<Pending> pending;
     std::vector<hipEvent_t> free_events;
@@ -167,6 +178,10 @@ int timed_launch(silu_ctx *c, double bytes, double layout, F &&fn)
     const char *name = "kernel";
     hipError_t err = fn(&name);
     if (err != hipSuccess) return hip_fail(c, err);
+    if (c->recording) {
+        c->rec_bytes += bytes;
+        c->rec_layout += layout;
+    }
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->pending.push_back({kernel_id(c, name), e0, e1, bytes, layout});
@@ -784,6 +799,8 @@ int silu_destroy(silu_ctx *c)
     for (auto &kv : c->comp) free_compressed(kv.second);
     for (auto &kv : c->sliced) free_sliced(kv.second);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : c->smooth_graphs)
+        if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
         (void)hipEventDestroy(p.e0);
@@ -930,8 +947,8 @@ int ilu_scale_factors_rowcol(silu_ctx *c, const silu_csr *L, const silu_csr *U, 
     return st;
 }
 
-int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
-                int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes)
+static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                        int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes)
 {
     if (!c || !A || !F || !b || !x || !ws) return SILU_ERR_ARG;
     c->bad_row = -1;
@@ -1031,6 +1048,71 @@ int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
         }
     }
     if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
+    return SILU_OK;
+}
+
+// SILU_GRAPH: replay a recorded call, or run it and record it.
+int ilu_smooth2(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes)
+{
+    if (!(flags & SILU_GRAPH) || (flags & SILU_DIRECT))
+        return smooth_plain(c, A, F, b, x, outer_sweeps, m_L, m_U, flags & ~SILU_GRAPH, ws, ws_bytes);
+    if (!c || !A || !F || !b || !x || !ws) return SILU_ERR_ARG;
+    const int rec_flags = flags & ~(SILU_GRAPH | SILU_CHECK_FINITE | SILU_VALIDATE);
+    const SmoothKey key{(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val, (uintptr_t)A->n_rows,
+                        (uintptr_t)A->nnz, (uintptr_t)F->Ls.row_ptr, (uintptr_t)F->Ls.col_idx,
+                        (uintptr_t)F->Ls.val, (uintptr_t)F->Ls.nnz, (uintptr_t)F->Us.row_ptr,
+                        (uintptr_t)F->Us.col_idx, (uintptr_t)F->Us.val, (uintptr_t)F->Us.nnz,
+                        (uintptr_t)F->Ls_val32, (uintptr_t)F->Us_val32, (uintptr_t)F->dinv,
+                        (uintptr_t)(F->scaled == 0 ? F->d : F->dc) ^ ((uintptr_t)F->scaled << 60), (uintptr_t)b,
+                        (uintptr_t)x, (uintptr_t)ws, (uintptr_t)outer_sweeps, (uintptr_t)m_L, (uintptr_t)m_U,
+                        (uintptr_t)rec_flags};
+    auto it = c->smooth_graphs.find(key);
+    if (it != c->smooth_graphs.end() && it->second.ex) {
+        int st;
+        if (flags & SILU_VALIDATE) {
+            if ((st = validate(c, A, 0))) return st;
+            if ((st = validate(c, &F->Ls, -1))) return st;
+            if ((st = validate(c, &F->Us, 1))) return st;
+        }
+        const SmoothGraph &g = it->second;
+        st = timed_launch(c, g.bytes, g.layout, [&](const char **nm) {
+            *nm = "smooth_graph";
+            return hipGraphLaunch(g.ex, c->stream);
+        });
+        if (st) return st;
+        return (flags & SILU_CHECK_FINITE) ? check_finite(c, A->n_rows, x) : SILU_OK;
+    }
+    // the call itself (builds every cached layout the sequence reads)
+    int st = smooth_plain(c, A, F, b, x, outer_sweeps, m_L, m_U, flags & ~SILU_GRAPH, ws, ws_bytes);
+    if (st || it != c->smooth_graphs.end()) return st; // an unrecordable sequence runs unrecorded
+    // record the same sequence: every layout is cached now, so it enqueues kernels only
+    SmoothGraph g;
+    const hipError_t last = c->last_hip;
+    if (!c->capture_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    const bool timing = c->timing;
+    c->stream = c->capture_stream;
+    c->timing = false;
+    c->recording = true;
+    c->rec_bytes = c->rec_layout = 0.0;
+    if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int rst = smooth_plain(c, A, F, b, x, outer_sweeps, m_L, m_U, rec_flags, ws, ws_bytes);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->capture_stream, &gr);
+        if (rst == SILU_OK && e == hipSuccess && gr &&
+            hipGraphInstantiate(&g.ex, gr, nullptr, nullptr, 0) != hipSuccess)
+            g.ex = nullptr;
+        if (gr) (void)hipGraphDestroy(gr);
+    }
+    (void)hipGetLastError(); // a failed recording leaves nothing behind
+    c->stream = saved;
+    c->timing = timing;
+    c->recording = false;
+    c->last_hip = last;
+    g.bytes = c->rec_bytes;
+    g.layout = c->rec_layout;
+    c->smooth_graphs.emplace(key, g);
     return SILU_OK;
 }
 
@@ -1305,7 +1387,7 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     const int m = restart;
     KrylovWs K{ws_vec_bytes(n), (char *)ws, m};
     const size_t sws_bytes = 4 * K.vec;
-    const int pflags = (flags & ~(SILU_CHECK_FINITE | SILU_VALIDATE | SILU_DIRECT)) | SILU_ZERO_GUESS;
+    const int pflags = (flags & ~(SILU_CHECK_FINITE | SILU_VALIDATE | SILU_DIRECT | SILU_GRAPH)) | SILU_ZERO_GUESS;
     const SweepGeom gA = pick_geom(n, A->nnz, flags);
     auto dot = [&](const double *a, const double *bb, double *out, bool root) {
         return timed_launch(c, 16.0 * (double)n, [&](const char **nm) {
@@ -1490,6 +1572,10 @@ int silu_release(silu_ctx *c, const void *row_ptr, const void *col_idx)
 {
     if (!c) return SILU_ERR_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream)); // nothing queued may still use what is dropped
+    // recorded smoother calls bake in the cached layouts' addresses: drop them all
+    for (auto &kv : c->smooth_graphs)
+        if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+    c->smooth_graphs.clear();
     for (auto it = c->levels.begin(); it != c->levels.end();) {
         if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
             const LevelInfo *li = &it->second;
