@@ -173,6 +173,7 @@ def main():
     ap.add_argument("--no-krylov", action="store_true")
     ap.add_argument("--no-fixed-point", action="store_true")
     ap.add_argument("--no-inner-sweep", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -260,14 +261,17 @@ def main():
     ach_layout = dv["layout_bytes"] / dv["launches"] / avg_s / 1e9
 
     # ---- the same application replayed from a recorded hipGraph (SILU_GRAPH) ----
-    def app_graph():
-        x.zero_()
-        ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, record=True)
+    ms_graph = graph_same = None
+    if not args.no_graph:
+        def app_graph():
+            x.zero_()
+            ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, record=True)
 
-    app_graph()  # the first call records
-    ms_graph = time_steps(torch, app_graph, args.steps, args.warmup)
-    graph_same = bool(torch.equal(x, x64))
-    log(f"graph replay: {ms_graph:.3f} ms/app ({1e3 / ms_graph:.1f} apps/s), identical to plain launches: {graph_same}")
+        app_graph()  # the first call records
+        ms_graph = time_steps(torch, app_graph, args.steps, args.warmup)
+        graph_same = bool(torch.equal(x, x64))
+        log(f"graph replay: {ms_graph:.3f} ms/app ({1e3 / ms_graph:.1f} apps/s), identical to plain launches: "
+            f"{graph_same}")
 
     # ---- mixed form ----
     ms_mixed = bytes_mixed = mixed_err = None
@@ -462,7 +466,7 @@ def main():
         "layout_bytes_per_app": layout_app,
         "copy_GBps": copy_gbps,
         "graph_ms": ms_graph,
-        "graph_apps_per_s": 1e3 / ms_graph,
+        "graph_apps_per_s": (1e3 / ms_graph) if ms_graph else None,
         "graph_identical": graph_same,
         "mixed_apps_per_s": (1e3 / ms_mixed) if ms_mixed else None,
         "mixed_ms": ms_mixed,
