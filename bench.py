@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--no-fixed-point", action="store_true")
     ap.add_argument("--no-inner-sweep", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--reorder", action="store_true", help="also time SILU_REORDER (on by default for perm256)")
+    ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -272,6 +274,32 @@ def main():
         graph_same = bool(torch.equal(x, x64))
         log(f"graph replay: {ms_graph:.3f} ms/app ({1e3 / ms_graph:.1f} apps/s), identical to plain launches: "
             f"{graph_same}")
+
+    # ---- locality-relabeled copies (SILU_REORDER): same results, gathers kept local ----
+    reorder = None
+    if args.reorder or (args.workload == "perm256" and not args.no_reorder):
+        t = time.perf_counter()
+        x.zero_()
+        ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, reorder=True)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t
+        wsr = ctx.workspace(n, B.SILU_REORDER)
+        reorder = {"setup_seconds": setup_s}
+        for label, mixed in (("fp64", False), ("mixed", True)):
+            def app_r():
+                x.zero_()
+                ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, mixed=mixed, kernel=kern, ws=wsr, reorder=True)
+
+            ms_r, bytes_r, st_r = timed(app_r, f"reorder {label}")
+            lb_r = st_r.pop("_layout_bytes_per_app")
+            reorder[label] = {"ms": ms_r, "apps_per_s": 1e3 / ms_r, "GBps": bytes_r / (ms_r * 1e-3) / 1e9,
+                              "layout_GBps": lb_r / (ms_r * 1e-3) / 1e9,
+                              "kernels": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                                              "GBps": v["bytes"] / v["ms"] / 1e6} for k, v in st_r.items()}}
+            if not mixed:
+                reorder["fp64"]["identical_to_plain"] = bool(torch.equal(x, x64))
+        log(f"reorder: set-up {setup_s:.1f} s, FP64 {reorder['fp64']['ms']:.3f} ms, mixed {reorder['mixed']['ms']:.3f} ms, "
+            f"identical {reorder['fp64']['identical_to_plain']}")
 
     # ---- mixed form ----
     ms_mixed = bytes_mixed = mixed_err = None
@@ -465,6 +493,7 @@ def main():
         "layout_GBps": layout_app / (ms * 1e-3) / 1e9,
         "layout_bytes_per_app": layout_app,
         "copy_GBps": copy_gbps,
+        "reorder": reorder,
         "graph_ms": ms_graph,
         "graph_apps_per_s": (1e3 / ms_graph) if ms_graph else None,
         "graph_identical": graph_same,

@@ -70,6 +70,7 @@ extern "C" {
 #define SILU_ZERO_GUESS 0x10000   /* ilu_smooth: x is zero on entry, so the first residual   */
                                   /* is b itself (skips one pass over A when m_L >= 2)       */
 #define SILU_GRAPH 0x20000        /* ilu_smooth: replay the call's sweeps from a hipGraph    */
+#define SILU_REORDER 0x40000      /* ilu_smooth: sweep locality-relabeled copies             */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -246,6 +247,18 @@ int ilu_scale_factors_rowcol(silu_ctx *ctx, const silu_csr *L, const silu_csr *U
  * silu_release on the context drops every recorded graph (the cached layouts
  * they read may be rebuilt).  If the sequence cannot be recorded the call
  * still succeeds and later calls run unrecorded.
+ * SILU_REORDER (iterative form; UNSUPPORTED with SILU_DIRECT): the sweeps run
+ * on copies of A and the factors whose rows and columns are relabeled so that
+ * strongly coupled rows sit next to each other (silu_reorder_rcm, theta 0.25,
+ * from A's values), each row keeping its entries in their original order;
+ * b and x are permuted in and x back out by the call.  A Richardson sweep
+ * updates all rows from the previous iterate, so the relabeling changes
+ * nothing in the arithmetic: results are bit-identical to the call without
+ * the flag.  It pays where the given order scatters the gathers (a randomly
+ * permuted matrix).  The copies are built on the first call (synchronous: A
+ * is read back to order it on the host) and cached like the sliced copies;
+ * silu_release of A or a factor drops them.  The workspace grows to six
+ * n-vectors (silu_workspace_size with the flag).
  * ws: workspace of at least silu_workspace_size(ctx, n, flags) bytes.
  * Asynchronous on the context stream (unless CHECK_FINITE / VALIDATE).
  * Errors: ARG (null, outer_sweeps < 1, m_L < 1 or m_U < 1 in ITER mode,
@@ -258,6 +271,19 @@ int ilu_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const do
 /* Same with separate inner iteration counts for the L and the U factor. */
 int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
                 int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes);
+
+/* The relabeling of SILU_REORDER, on HOST arrays: reverse Cuthill-McKee on
+ * the graph of strong couplings, row i coupled to j != i when |a_ij| >= theta
+ * * max_{k != i} |a_ik| (the strength of connection of algebraic multigrid,
+ * Section 3).  Each component starts from its unvisited row of least strong
+ * degree; a row's unvisited strong neighbours are queued by increasing degree
+ * (ties: lower index); the visit order is reversed.  order[k] receives the
+ * row placed at position k (a permutation of 0..n-1).  row_ptr [n+1], col_idx
+ * and val [nnz] (FP64) are read only; order [n] is written.  Synchronous, no
+ * GPU needed.  Errors: ARG (null, n < 0, theta < 0 or NaN), PATTERN (row
+ * pointers decreasing, a column outside 0..n-1). */
+int silu_reorder_rcm(int64_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *val, double theta,
+                     int32_t *order);
 
 /* ---- polynomial Gauss-Seidel smoother (Section 2) ------------------------ */
 

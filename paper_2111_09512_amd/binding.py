@@ -32,7 +32,7 @@ SILU_F64, SILU_F32 = 0, 1
 SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1, 0x2, 0x4, 0x8, 0x10
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
-SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH = 0x8000, 0x10000, 0x20000
+SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH, SILU_REORDER = 0x8000, 0x10000, 0x20000, 0x40000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
@@ -125,6 +125,7 @@ _sig = {
     "silu_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
     "silu_server_last_hip_error": (C.c_int, [_P]),
     "silu_server_set_mode": (C.c_int, [_P, C.c_int, C.c_int]),
+    "silu_reorder_rcm": (C.c_int, [C.c_int64, _P, _P, _P, C.c_double, _P]),
     "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -436,15 +437,18 @@ class Context:
     def ilu_smooth(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
                    m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
                    validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None,
-                   graph: bool = True, zero_guess: bool = False, record: bool = False) -> torch.Tensor:
+                   graph: bool = True, zero_guess: bool = False, record: bool = False,
+                   reorder: bool = False) -> torch.Tensor:
         """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned).
         zero_guess: x holds zeros on entry (the first residual is b).
         record: replay the call's sweep sequence from a hipGraph recorded on the
-        first call with the same tensors and counts (SILU_GRAPH)."""
+        first call with the same tensors and counts (SILU_GRAPH).
+        reorder: sweep locality-relabeled copies (SILU_REORDER; same results)."""
         m_U = m_L if m_U is None else m_U
         flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) | (SILU_ZERO_GUESS if zero_guess else 0) |
                  (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
-                 (0 if graph else SILU_NO_GRAPH) | (SILU_GRAPH if record else 0) | KERNELS[kernel])
+                 (0 if graph else SILU_NO_GRAPH) | (SILU_GRAPH if record else 0) |
+                 (SILU_REORDER if reorder else 0) | KERNELS[kernel])
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws
@@ -584,6 +588,20 @@ def factor_ilut(A, tau: float, p: int) -> tuple[HostCsr, HostCsr]:
     if st:
         raise SiluError(st, f"silu_factor_ilut(tau={tau}, p={p})", int(bad.value))
     return _host_out(L), _host_out(U)
+
+
+def reorder_rcm(A, theta: float = 0.25) -> np.ndarray:
+    """The SILU_REORDER relabeling of a host CSR matrix: order[k] = the row
+    placed at position k (reverse Cuthill-McKee on the strong couplings)."""
+    rp = np.ascontiguousarray(A.row_ptr, np.int32)
+    col = np.ascontiguousarray(A.col, np.int32)
+    val = np.ascontiguousarray(A.val, np.float64)
+    order = np.empty(A.n, np.int32)
+    st = _lib.silu_reorder_rcm(int(A.n), rp.ctypes.data, col.ctypes.data, val.ctypes.data, float(theta),
+                               order.ctypes.data)
+    if st:
+        raise SiluError(st, "silu_reorder_rcm")
+    return order
 
 
 def factor(A, kind: str, params: dict) -> tuple[HostCsr, HostCsr]:

@@ -12,7 +12,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
-HIP_SOURCES = ["sweep.hip", "setup.hip", "krylov.hip", "fixedpoint.hip", "api.hip", "serve.hip"]
+HIP_SOURCES = ["sweep.hip", "setup.hip", "krylov.hip", "fixedpoint.hip", "reorder.hip", "api.hip", "serve.hip"]
 CXX_SOURCES = ["factor.cpp"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -66,6 +66,38 @@ struct Sliced {
 };
 using SlicedKey = std::tuple<const void *, const void *, const void *, int64_t, int64_t, int, int>;
 
+// Locality-relabeled copies of A and the factors (SILU_REORDER), keyed by the
+// pointers of A, Ls, Us, dinv, the second vector (d or d_c) and the FP32 copies.
+struct Reorder {
+    int32_t *order = nullptr, *pos = nullptr; // device [n]
+    silu_csr A2{}, L2{}, U2{};                // relabeled copies (arrays owned here)
+    double *dinv2 = nullptr, *aux2 = nullptr; // dinv, and d (unscaled) or d_c (row/column), relabeled
+    float *L32 = nullptr, *U32 = nullptr;     // relabeled FP32 values, when the factors carry them
+};
+using ReorderKey = std::array<uintptr_t, 13>;
+
+void free_csr_copy(silu_csr &M)
+{
+    (void)hipFree(M.row_ptr);
+    (void)hipFree(M.col_idx);
+    (void)hipFree(M.val);
+    M = silu_csr();
+}
+
+void free_reorder(Reorder &R)
+{
+    (void)hipFree(R.order);
+    (void)hipFree(R.pos);
+    free_csr_copy(R.A2);
+    free_csr_copy(R.L2);
+    free_csr_copy(R.U2);
+    (void)hipFree(R.dinv2);
+    (void)hipFree(R.aux2);
+    (void)hipFree(R.L32);
+    (void)hipFree(R.U32);
+    R = Reorder();
+}
+
 void free_sliced(Sliced &S)
 {
     (void)hipFree(S.sptr);
@@ -116,6 +148,7 @@ struct silu_ctx {
     std::map<SlicedKey, Sliced> sliced;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::map<SmoothKey, SmoothGraph> smooth_graphs;
+    std::map<ReorderKey, Reorder> reorders;
     hipStream_t capture_stream = nullptr; // private, default priority, for graph capture
     bool recording = false;               // launches go into a capture: add up their bytes
     double rec_bytes = 0.0, rec_layout = 0.0;
@@ -612,6 +645,103 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     return timed_launch(c, bytes, layout, [&](const char **nm) { return launch_sweep(p, g, a, c->stream, nm); });
 }
 
+// ---- locality relabeling (SILU_REORDER) ------------------------------------
+// Relabeled copy of one CSR matrix: rows in `order`, entries in their original
+// order, columns through pos.  h_rp: the matrix's row pointers on the host.
+int relabel_csr(silu_ctx *c, const silu_csr *M, const std::vector<int32_t> &h_rp, const std::vector<int32_t> &h_order,
+                const int32_t *order, const int32_t *pos, silu_csr *out, int32_t **rp2_out)
+{
+    const int64_t n = M->n_rows;
+    std::vector<int32_t> rp2((size_t)n + 1, 0);
+    for (int64_t k = 0; k < n; k++) {
+        const int32_t i = h_order[(size_t)k];
+        rp2[(size_t)k + 1] = rp2[(size_t)k] + (h_rp[(size_t)i + 1] - h_rp[(size_t)i]);
+    }
+    *out = *M;
+    out->row_ptr = nullptr;
+    out->col_idx = nullptr;
+    out->val = nullptr;
+    HIPCHK(c, hipMalloc((void **)&out->row_ptr, ((size_t)n + 1) * 4));
+    HIPCHK(c, hipMalloc((void **)&out->col_idx, (size_t)std::max<int64_t>(M->nnz, 1) * 4));
+    HIPCHK(c, hipMalloc(&out->val, (size_t)std::max<int64_t>(M->nnz, 1) * 8));
+    HIPCHK(c, hipMemcpy(out->row_ptr, rp2.data(), ((size_t)n + 1) * 4, hipMemcpyHostToDevice));
+    if (M->nnz > 0)
+        HIPCHK(c, launch_relabel((int)n, order, pos, M->row_ptr, M->col_idx, M->val, 8, out->row_ptr, out->col_idx,
+                                 out->val, c->stream));
+    *rp2_out = out->row_ptr;
+    return SILU_OK;
+}
+
+int get_reorder(silu_ctx *c, const silu_csr *A, const silu_factors *F, Reorder **out)
+{
+    const double *aux = F->scaled == 0 ? F->d : (F->scaled == 2 ? F->dc : nullptr);
+    const ReorderKey key{(uintptr_t)A->row_ptr, (uintptr_t)A->col_idx, (uintptr_t)A->val,
+                         (uintptr_t)F->Ls.row_ptr, (uintptr_t)F->Ls.col_idx, (uintptr_t)F->Ls.val,
+                         (uintptr_t)F->Us.row_ptr, (uintptr_t)F->Us.col_idx, (uintptr_t)F->Us.val,
+                         (uintptr_t)F->dinv, (uintptr_t)aux, (uintptr_t)F->Ls_val32, (uintptr_t)F->Us_val32};
+    auto it = c->reorders.find(key);
+    if (it != c->reorders.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    const int64_t n = A->n_rows;
+    // the order, from A's strong couplings (host)
+    std::vector<int32_t> rpA((size_t)n + 1), colA((size_t)std::max<int64_t>(A->nnz, 1));
+    std::vector<double> valA((size_t)std::max<int64_t>(A->nnz, 1));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(rpA.data(), A->row_ptr, rpA.size() * 4, hipMemcpyDeviceToHost));
+    if (A->nnz > 0) {
+        HIPCHK(c, hipMemcpy(colA.data(), A->col_idx, (size_t)A->nnz * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(valA.data(), A->val, (size_t)A->nnz * 8, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> order((size_t)n), pos((size_t)n);
+    int st = rcm_strength_order(n, rpA.data(), colA.data(), valA.data(), REORDER_THETA, order.data());
+    if (st) return st;
+    for (int64_t k = 0; k < n; k++) pos[(size_t)order[(size_t)k]] = (int32_t)k;
+    colA = std::vector<int32_t>();
+    valA = std::vector<double>();
+    Reorder R;
+    auto fail_free = [&](int code) {
+        (void)hipStreamSynchronize(c->stream);
+        free_reorder(R);
+        return code;
+    };
+    hipError_t e = hipMalloc((void **)&R.order, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMalloc((void **)&R.pos, (size_t)n * 4);
+    if (e == hipSuccess) e = hipMemcpy(R.order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(R.pos, pos.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail_free(hip_fail(c, e));
+    int32_t *rp2 = nullptr;
+    if ((st = relabel_csr(c, A, rpA, order, R.order, R.pos, &R.A2, &rp2))) return fail_free(st);
+    std::vector<int32_t> rp((size_t)n + 1);
+    const silu_csr *fac[2] = {&F->Ls, &F->Us};
+    silu_csr *dst[2] = {&R.L2, &R.U2};
+    const float *f32[2] = {F->Ls_val32, F->Us_val32};
+    float **d32[2] = {&R.L32, &R.U32};
+    for (int t = 0; t < 2; t++) {
+        if ((e = hipMemcpy(rp.data(), fac[t]->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            return fail_free(hip_fail(c, e));
+        if ((st = relabel_csr(c, fac[t], rp, order, R.order, R.pos, dst[t], &rp2))) return fail_free(st);
+        if (f32[t] && fac[t]->nnz > 0) {
+            if ((e = hipMalloc((void **)d32[t], (size_t)fac[t]->nnz * 4)) != hipSuccess) return fail_free(hip_fail(c, e));
+            if ((e = launch_relabel((int)n, R.order, R.pos, fac[t]->row_ptr, nullptr, f32[t], 4, rp2, nullptr,
+                                    *d32[t], c->stream)) != hipSuccess)
+                return fail_free(hip_fail(c, e));
+        }
+    }
+    if ((e = hipMalloc((void **)&R.dinv2, (size_t)n * 8)) != hipSuccess) return fail_free(hip_fail(c, e));
+    if ((e = launch_gather((int)n, R.order, F->dinv, R.dinv2, c->stream)) != hipSuccess)
+        return fail_free(hip_fail(c, e));
+    if (aux) {
+        if ((e = hipMalloc((void **)&R.aux2, (size_t)n * 8)) != hipSuccess) return fail_free(hip_fail(c, e));
+        if ((e = launch_gather((int)n, R.order, aux, R.aux2, c->stream)) != hipSuccess)
+            return fail_free(hip_fail(c, e));
+    }
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail_free(hip_fail(c, e));
+    *out = &c->reorders.emplace(key, R).first->second;
+    return SILU_OK;
+}
+
 // ---- level analysis (Section 4: level-set scheduling) ----------------------
 int get_levels(silu_ctx *c, const silu_csr *T, int uplo, LevelInfo **out)
 {
@@ -801,6 +931,7 @@ int silu_destroy(silu_ctx *c)
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto &kv : c->smooth_graphs)
         if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
+    for (auto &kv : c->reorders) free_reorder(kv.second);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto &p : c->pending) {
         (void)hipEventDestroy(p.e0);
@@ -842,9 +973,8 @@ const char *silu_status_string(int s)
 
 int silu_workspace_size(silu_ctx *c, int64_t n, int flags, size_t *bytes)
 {
-    (void)flags;
     if (!c || !bytes || n < 0) return SILU_ERR_ARG;
-    *bytes = 4 * ws_vec_bytes(n);
+    *bytes = ((flags & SILU_REORDER) ? 6 : 4) * ws_vec_bytes(n);
     return SILU_OK;
 }
 
@@ -971,6 +1101,46 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         if ((st = validate(c, A, 0))) return st;
         if ((st = validate(c, &F->Ls, -1))) return st;
         if ((st = validate(c, &F->Us, 1))) return st;
+    }
+    if (flags & SILU_REORDER) {
+        // the same steps on the relabeled copies: b and x in, x out
+        if (direct) return SILU_ERR_UNSUPPORTED;
+        Reorder *R = nullptr;
+        if ((st = get_reorder(c, A, F, &R))) return st;
+        Ws w{(char *)ws, ws_vec_bytes(n)};
+        double *b2 = (double *)w.slot(4), *x2 = (double *)w.slot(5);
+        const double vb = 20.0 * (double)n; // index, read, write
+        st = timed_launch(c, vb, [&](const char **nm) {
+            *nm = "reorder_gather";
+            return launch_gather((int)n, R->order, b, b2, c->stream);
+        });
+        if (!st && !(flags & SILU_ZERO_GUESS))
+            st = timed_launch(c, vb, [&](const char **nm) {
+                *nm = "reorder_gather";
+                return launch_gather((int)n, R->order, x, x2, c->stream);
+            });
+        if (!st && (flags & SILU_ZERO_GUESS))
+            st = timed_launch(c, 8.0 * (double)n, [&](const char **nm) {
+                *nm = "fill";
+                return launch_fill((int)n, x2, 0.0, nullptr, 0.0, c->stream);
+            });
+        if (st) return st;
+        silu_factors F2 = *F;
+        F2.Ls = R->L2;
+        F2.Us = R->U2;
+        F2.dinv = R->dinv2;
+        if (F->scaled == 0) F2.d = R->aux2;
+        if (F->scaled == 2) F2.dc = R->aux2;
+        F2.Ls_val32 = R->L32;
+        F2.Us_val32 = R->U32;
+        const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
+        if ((st = smooth_plain(c, &R->A2, &F2, b2, x2, outer_sweeps, m_L, m_U, inner, ws, ws_bytes))) return st;
+        st = timed_launch(c, vb, [&](const char **nm) {
+            *nm = "reorder_scatter";
+            return launch_scatter((int)n, R->order, x2, x, c->stream);
+        });
+        if (st) return st;
+        return (flags & SILU_CHECK_FINITE) ? check_finite(c, n, x) : SILU_OK;
     }
     Ws w{(char *)ws, ws_vec_bytes(n)};
     void *r = w.slot(0), *s = w.slot(1), *tmp[2] = {w.slot(2), w.slot(3)};
@@ -1576,6 +1746,24 @@ int silu_release(silu_ctx *c, const void *row_ptr, const void *col_idx)
     for (auto &kv : c->smooth_graphs)
         if (kv.second.ex) (void)hipGraphExecDestroy(kv.second.ex);
     c->smooth_graphs.clear();
+    // relabeled copies made from this matrix, with everything cached for them
+    std::vector<Reorder> gone;
+    for (auto it = c->reorders.begin(); it != c->reorders.end();) {
+        const ReorderKey &k = it->first;
+        const uintptr_t r = (uintptr_t)row_ptr, ci = (uintptr_t)col_idx;
+        if (k[0] == r || k[3] == r || k[6] == r || (ci && (k[1] == ci || k[4] == ci || k[7] == ci))) {
+            gone.push_back(it->second);
+            it = c->reorders.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    for (Reorder &R : gone) {
+        const silu_csr *m[3] = {&R.A2, &R.L2, &R.U2};
+        for (const silu_csr *M : m)
+            if (M->row_ptr) (void)silu_release(c, M->row_ptr, M->col_idx);
+        free_reorder(R);
+    }
     for (auto it = c->levels.begin(); it != c->levels.end();) {
         if (std::get<0>(it->first) == row_ptr || std::get<1>(it->first) == col_idx) {
             const LevelInfo *li = &it->second;

@@ -137,6 +137,19 @@ hipError_t launch_fp_sweep(int64_t nnz, const int32_t *rp, const int32_t *col, c
 hipError_t launch_fp_split(int n, const int32_t *rp, const int32_t *col, const double *LU, const int32_t *Lrp,
                            int32_t *Lcol, double *Lval, const int32_t *Urp, int32_t *Ucol, double *Uval, int64_t l_nnz,
                            int64_t u_nnz, hipStream_t s);
+// Locality relabeling (reorder.hip): order[k] = the row placed at position k,
+// pos = its inverse.  relabel writes row k of N' = Q N Q^T (rp2 given, entries
+// in the original order, columns through pos; col2 may be null to copy values
+// only); gather dst[k] = src[order[k]]; scatter dst[order[k]] = src[k].
+hipError_t launch_relabel(int n, const int32_t *order, const int32_t *pos, const int32_t *rp, const int32_t *col,
+                          const void *val, int val_bytes, const int32_t *rp2, int32_t *col2, void *val2,
+                          hipStream_t s);
+hipError_t launch_gather(int n, const int32_t *order, const double *src, double *dst, hipStream_t s);
+hipError_t launch_scatter(int n, const int32_t *order, const double *src, double *dst, hipStream_t s);
+int rcm_strength_order(int64_t n, const int32_t *rp, const int32_t *col, const double *val, double theta,
+                       int32_t *order);
+constexpr double REORDER_THETA = 0.25;
+
 // Largest window (LDS slots) the windowed sweep stages per workgroup.
 constexpr int WIN_MAX_SLOTS = 3072;
 

@@ -124,3 +124,8 @@ def test_full_perm256_mixed(orc, B, ctx):
     x.zero_()
     ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U)
     np.testing.assert_array_equal(host(x), ref64)
+    # the same on locality-relabeled copies (SILU_REORDER): bit for bit
+    for mixed, ref in ((True, ref32), (False, ref64)):
+        x.zero_()
+        ctx.ilu_smooth(c.Ad, c.F, dev(b), x, wl.outer, wl.m_L, wl.m_U, mixed=mixed, reorder=True)
+        np.testing.assert_array_equal(host(x), ref)
