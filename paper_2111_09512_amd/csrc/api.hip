@@ -1110,16 +1110,12 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         Ws w{(char *)ws, ws_vec_bytes(n)};
         double *b2 = (double *)w.slot(4), *x2 = (double *)w.slot(5);
         const double vb = 20.0 * (double)n; // index, read, write
-        st = timed_launch(c, vb, [&](const char **nm) {
-            *nm = "reorder_gather";
-            return launch_gather((int)n, R->order, b, b2, c->stream);
+        const bool zero = (flags & SILU_ZERO_GUESS) != 0;
+        st = timed_launch(c, vb + (zero ? 0.0 : 16.0 * (double)n), [&](const char **nm) {
+            *nm = "reorder_in";
+            return launch_permute_in((int)n, R->pos, b, zero ? nullptr : x, b2, x2, c->stream);
         });
-        if (!st && !(flags & SILU_ZERO_GUESS))
-            st = timed_launch(c, vb, [&](const char **nm) {
-                *nm = "reorder_gather";
-                return launch_gather((int)n, R->order, x, x2, c->stream);
-            });
-        if (!st && (flags & SILU_ZERO_GUESS))
+        if (!st && zero)
             st = timed_launch(c, 8.0 * (double)n, [&](const char **nm) {
                 *nm = "fill";
                 return launch_fill((int)n, x2, 0.0, nullptr, 0.0, c->stream);
@@ -1136,7 +1132,7 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
         if ((st = smooth_plain(c, &R->A2, &F2, b2, x2, outer_sweeps, m_L, m_U, inner, ws, ws_bytes))) return st;
         st = timed_launch(c, vb, [&](const char **nm) {
-            *nm = "reorder_scatter";
+            *nm = "reorder_out";
             return launch_scatter((int)n, R->order, x2, x, c->stream);
         });
         if (st) return st;

@@ -145,6 +145,9 @@ hipError_t launch_relabel(int n, const int32_t *order, const int32_t *pos, const
                           const void *val, int val_bytes, const int32_t *rp2, int32_t *col2, void *val2,
                           hipStream_t s);
 hipError_t launch_gather(int n, const int32_t *order, const double *src, double *dst, hipStream_t s);
+// b2[pos[i]] = b[i], and x2[pos[i]] = x[i] when x is not null
+hipError_t launch_permute_in(int n, const int32_t *pos, const double *b, const double *x, double *b2, double *x2,
+                             hipStream_t s);
 hipError_t launch_scatter(int n, const int32_t *order, const double *src, double *dst, hipStream_t s);
 int rcm_strength_order(int64_t n, const int32_t *rp, const int32_t *col, const double *val, double theta,
                        int32_t *order);

@@ -44,6 +44,19 @@ __global__ void __launch_bounds__(256) k_gather(int n, const int32_t *__restrict
     if (k < n) dst[k] = src[order[k]];
 }
 
+// Vectors into the relabeled order: b2[pos[i]] = b[i] and, when x is given,
+// x2[pos[i]] = x[i] (unit-stride reads, scattered writes, one pass for both).
+__global__ void __launch_bounds__(256) k_permute_in(int n, const int32_t *__restrict__ pos,
+                                                    const double *__restrict__ b, const double *__restrict__ x,
+                                                    double *__restrict__ b2, double *__restrict__ x2)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const int k = pos[i];
+    b2[k] = b[i];
+    if (x) x2[k] = x[i];
+}
+
 __global__ void __launch_bounds__(256) k_scatter(int n, const int32_t *__restrict__ order,
                                                  const double *__restrict__ src, double *__restrict__ dst)
 {
@@ -73,6 +86,14 @@ hipError_t launch_gather(int n, const int32_t *order, const double *src, double 
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather, dim3(blocks(n)), dim3(256), 0, s, n, order, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in(int n, const int32_t *pos, const double *b, const double *x, double *b2, double *x2,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_in, dim3(blocks(n)), dim3(256), 0, s, n, pos, b, x, b2, x2);
     return hipGetLastError();
 }
 
