@@ -494,6 +494,11 @@ int silu_server_step(silu_server *server, int *n_active, int *n_queued);
  * Returns SILU_ERR_TIMEOUT (state 3) for a request whose persistent launch
  * gave up a wait: its x is not a valid result. */
 int silu_server_poll(silu_server *server, int64_t ticket, int *state);
+/* The tickets of requests found done (state 3) since the last call, each
+ * returned once, oldest first, at most `capacity` of them in tickets[] (host
+ * array); *count receives how many.  One call replaces a poll per pending
+ * request.  Done tickets are kept until returned here (8 bytes each). */
+int silu_server_completed(silu_server *server, int64_t *tickets, int capacity, int *count);
 int silu_server_last_hip_error(const silu_server *server);
 
 /*

@@ -125,6 +125,7 @@ _sig = {
     "silu_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
     "silu_server_last_hip_error": (C.c_int, [_P]),
     "silu_server_set_mode": (C.c_int, [_P, C.c_int, C.c_int]),
+    "silu_server_completed": (C.c_int, [_P, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
     "silu_reorder_rcm": (C.c_int, [C.c_int64, _P, _P, _P, C.c_double, _P]),
     "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
@@ -686,6 +687,16 @@ class Server:
         a, q = C.c_int(), C.c_int()
         self._check(_lib.silu_server_step(self._h, C.byref(a), C.byref(q)), "silu_server_step")
         return a.value, q.value
+
+    def completed(self, capacity: int = 1024) -> list:
+        """Tickets of the requests found done since the last call (each once)."""
+        buf = (C.c_int64 * capacity)()
+        k = C.c_int()
+        self._check(_lib.silu_server_completed(self._h, buf, capacity, C.byref(k)), "silu_server_completed")
+        out = [int(buf[i]) for i in range(k.value)]
+        for t in out:
+            self._req.pop(t, None)
+        return out
 
     def poll(self, ticket: int) -> int:
         st = C.c_int()

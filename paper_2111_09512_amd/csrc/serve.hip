@@ -78,6 +78,8 @@ struct silu_server {
     std::vector<Range> free_list;                      // sorted by offset, coalesced
     std::vector<std::pair<int64_t, Range>> to_release; // (step, range)
     std::map<int64_t, int64_t> finish_step;            // ticket -> step of its last op
+    std::vector<std::pair<int64_t, int64_t>> to_report; // (step, ticket) not yet known done
+    std::deque<int64_t> done_queue;                     // done, not yet returned by completed()
     int64_t next_ticket = 0, steps = 0, completed_through = -1;
     hipEvent_t ev[RING] = {};
     int64_t done_step[RING];   // the step a slot last held, once the GPU has passed it
@@ -170,6 +172,15 @@ void reap(silu_server *s)
             tr[w++] = tr[i];
     }
     tr.resize(w);
+    auto &rp = s->to_report;
+    w = 0;
+    for (size_t i = 0; i < rp.size(); i++) {
+        if (step_done(s, rp[i].first))
+            s->done_queue.push_back(rp[i].second);
+        else
+            rp[w++] = rp[i];
+    }
+    rp.resize(w);
 }
 
 // The op request q runs at its current position.
@@ -360,6 +371,7 @@ int launch_persistent(silu_server *s, std::vector<Request> &batch)
     for (const Request &q : batch) {
         s->finish_step[q.ticket] = step;
         s->to_release.push_back({step, q.ws});
+        s->to_report.push_back({step, q.ticket});
     }
     return SILU_OK;
 }
@@ -574,6 +586,7 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             if (q.op == q.total) {
                 s->finish_step[q.ticket] = step;
                 s->to_release.push_back({step, q.ws});
+                s->to_report.push_back({step, q.ticket});
             } else {
                 s->active[w++] = q;
             }
@@ -599,6 +612,19 @@ int silu_server_poll(silu_server *s, int64_t ticket, int *state)
     *state = step_done(s, it->second) ? 3 : 2;
     if (*state == 3 && std::find(s->failed.begin(), s->failed.end(), it->second) != s->failed.end())
         return SILU_ERR_TIMEOUT;
+    return SILU_OK;
+}
+
+int silu_server_completed(silu_server *s, int64_t *tickets, int capacity, int *count)
+{
+    if (!s || !count || capacity < 0 || (capacity > 0 && !tickets)) return SILU_ERR_ARG;
+    reap(s);
+    int k = 0;
+    while (k < capacity && !s->done_queue.empty()) {
+        tickets[k++] = s->done_queue.front();
+        s->done_queue.pop_front();
+    }
+    *count = k;
     return SILU_OK;
 }
 

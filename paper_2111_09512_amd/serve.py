@@ -86,7 +86,7 @@ def run_batched(server: B.Server, mids, reqs, realtime: bool = True):
     """Feed arrivals (in real time) to the server, step it, poll completions.
     Returns (latencies in s, makespan in s, steps)."""
     n = len(reqs)
-    tickets = [-1] * n
+    index = {}
     done_at = [0.0] * n
     pending = set()
     nxt = 0
@@ -97,16 +97,16 @@ def run_batched(server: B.Server, mids, reqs, realtime: bool = True):
         now = time.perf_counter() - t0
         while nxt < n and (not realtime or reqs[nxt].arrival <= now):
             r = reqs[nxt]
-            tickets[nxt] = server.submit(mids[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U)
+            index[server.submit(mids[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U)] = nxt
             pending.add(nxt)
             nxt += 1
         active, queued = server.step()
         steps += 1
         now = time.perf_counter() - t0
-        for i in list(pending):
-            if server.poll(tickets[i]) == B.Server.DONE:
-                done_at[i] = now
-                pending.discard(i)
+        for t in server.completed():
+            i = index.pop(t)
+            done_at[i] = now
+            pending.discard(i)
         if not pending and nxt < n and realtime:
             wait = reqs[nxt].arrival - (time.perf_counter() - t0)
             if wait > 0:

@@ -283,3 +283,34 @@ def test_set_mode_rules(B, ctx, pool):
     assert e.value.status == -8
     server.set_mode(server.STEPWISE)
     server.close()
+
+
+def test_completed_reports_each_ticket_once(B, ctx, pool):
+    """silu_server_completed returns every finished ticket exactly once, only
+    after poll would report it done, with results equal to the lone runs."""
+    say("serving: completed()")
+    reqs = _requests(pool, 30, seed=11)
+    server = B.Server(ctx, arena_bytes=16 << 20, max_active=8)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    xs, tickets = [], []
+    seen = []
+    for i, r in enumerate(reqs):
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+        server.step()
+        seen += server.completed()
+    for _ in range(100000):
+        if len(seen) == len(tickets):
+            break
+        server.step()
+        got = server.completed(capacity=3)
+        assert len(got) <= 3
+        for t in got:
+            assert server.poll(t) == server.DONE
+        seen += got
+    assert sorted(seen) == sorted(tickets)
+    assert server.completed() == []
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
+    server.close()
