@@ -255,6 +255,17 @@ def main():
     ms, bytes_app, st = timed(app_f64, "FP64 iter")
     layout_app = st.pop("_layout_bytes_per_app")
     x64 = x.clone()
+    # spread: the same applications timed one by one (after the timed region)
+    per = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        app_f64()
+        e1.record()
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1))
+    spread = {f"p{q}": float(np.percentile(per, q)) for q in (10, 50, 90)}
+    log(f"per-application ms p10/p50/p90: {spread['p10']:.3f} / {spread['p50']:.3f} / {spread['p90']:.3f}")
     apps = 1e3 / ms
     gbps = bytes_app / (ms * 1e-3) / 1e9
     dname, dv = max(st.items(), key=lambda kv: kv[1]["ms"])
@@ -480,6 +491,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_app_spread": spread,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -522,6 +534,7 @@ def main():
                      "algorithmic_bytes_per_launch": dv["bytes"] / dv["launches"],
                      "layout_bytes_per_launch": dv["layout_bytes"] / dv["launches"],
                      "layout_achieved": ach_layout, "layout_frac": ach_layout / HBM_PEAK_GBPS,
+                     "layout_frac_of_copy": ach_layout / copy_gbps,
                      "traffic_achieved": (traffic / avg_s / 1e9) if traffic else None},
         "cpu_baseline": cpu,
         "serving": serving,
