@@ -140,6 +140,22 @@ def bench_serving(torch, B, ctx, arena_mb):
     lat_b, span_b, steps = S.run_batched(server, mids, reqs)
     xb = [r.x.clone() for r in reqs]
     server.close()
+    # two lanes: matrices up to 64^3 rows batched on the context's stream, larger
+    # ones on a second stream of their own, each lane half of the arena
+    ctx2 = B.Context(stream=torch.cuda.Stream())
+    small = B.Server(ctx, arena_bytes=(arena_mb << 20) // 2, max_active=1024)
+    large = B.Server(ctx2, arena_bytes=(arena_mb << 20) // 2, max_active=1024)
+    lanes = [(small, [small.register(Ad, F) for (Ad, F, _) in mats], 64 ** 3),
+             (large, [large.register(Ad, F) for (Ad, F, _) in mats], None)]
+    for r in reqs:
+        r.x.zero_()
+    S.run_batched(None, None, reqs[:8], realtime=False, lanes=lanes)
+    for r in reqs:
+        r.x.zero_()
+    lat_l, span_l, steps_l = S.run_batched(None, None, reqs, lanes=lanes)
+    same_l = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
+    small.close()
+    large.close()
     for r in reqs:
         r.x.zero_()
     lat_1, span_1 = S.run_one_at_a_time(ctx, mats, reqs)
@@ -147,12 +163,15 @@ def bench_serving(torch, B, ctx, arena_mb):
     res = {"requests": len(reqs), "matrices": len(mats), "arrival_rate_per_s": 2000.0, "arena_MB": arena_mb,
            "batched": {"apps_per_s": len(reqs) / span_b, "makespan_s": span_b, "steps": steps,
                        **S.percentiles(lat_b)},
+           "batched_two_lanes": {"apps_per_s": len(reqs) / span_l, "makespan_s": span_l, "steps": steps_l,
+                                 "small_lane_max_rows": 64 ** 3, **S.percentiles(lat_l)},
            "one_at_a_time": {"apps_per_s": len(reqs) / span_1, "makespan_s": span_1, **S.percentiles(lat_1)},
-           "results_identical": same}
+           "results_identical": bool(same and same_l)}
     log(f"serving: batched p50 {res['batched']['p50_ms']:.2f} ms p99 {res['batched']['p99_ms']:.2f} ms "
-        f"{res['batched']['apps_per_s']:.0f} apps/s; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
+        f"{res['batched']['apps_per_s']:.0f} apps/s; two lanes p50 {res['batched_two_lanes']['p50_ms']:.2f} ms "
+        f"p99 {res['batched_two_lanes']['p99_ms']:.2f} ms; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
         f"p99 {res['one_at_a_time']['p99_ms']:.2f} ms {res['one_at_a_time']['apps_per_s']:.0f} apps/s; "
-        f"identical={same}")
+        f"identical={same} {same_l}")
     return res
 
 

@@ -488,8 +488,12 @@ int silu_server_register(silu_server *server, const silu_csr *A, const silu_fact
 int64_t silu_server_request_bytes(const silu_server *server, int matrix_id);
 int silu_server_submit(silu_server *server, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
                        int64_t *ticket);
-/* One scheduling step (asynchronous; blocks only when 4 steps are in flight). */
+/* One scheduling step (asynchronous; blocks only when 8 steps are in flight). */
 int silu_server_step(silu_server *server, int *n_active, int *n_queued);
+/* Up to max_steps steps in one call (each one admits and launches as above),
+ * stopping early when no request is active: a host loop that calls this
+ * keeps the GPU fed with fewer round trips. */
+int silu_server_run(silu_server *server, int max_steps, int *n_active, int *n_queued);
 /* state: 0 queued, 1 running, 2 last sweep enqueued, 3 done (result in x).
  * Returns SILU_ERR_TIMEOUT (state 3) for a request whose persistent launch
  * gave up a wait: its x is not a valid result. */

@@ -126,6 +126,7 @@ _sig = {
     "silu_server_last_hip_error": (C.c_int, [_P]),
     "silu_server_set_mode": (C.c_int, [_P, C.c_int, C.c_int]),
     "silu_server_completed": (C.c_int, [_P, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
+    "silu_server_run": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "silu_reorder_rcm": (C.c_int, [C.c_int64, _P, _P, _P, C.c_double, _P]),
     "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
@@ -688,9 +689,17 @@ class Server:
         self._check(_lib.silu_server_step(self._h, C.byref(a), C.byref(q)), "silu_server_step")
         return a.value, q.value
 
+    def run(self, max_steps: int) -> tuple[int, int]:
+        """Up to max_steps scheduling steps in one call."""
+        a, q = C.c_int(), C.c_int()
+        self._check(_lib.silu_server_run(self._h, max_steps, C.byref(a), C.byref(q)), "silu_server_run")
+        return a.value, q.value
+
     def completed(self, capacity: int = 1024) -> list:
         """Tickets of the requests found done since the last call (each once)."""
-        buf = (C.c_int64 * capacity)()
+        buf = getattr(self, "_done_buf", None)
+        if buf is None or len(buf) < capacity:
+            buf = self._done_buf = (C.c_int64 * capacity)()
         k = C.c_int()
         self._check(_lib.silu_server_completed(self._h, buf, capacity, C.byref(k)), "silu_server_completed")
         out = [int(buf[i]) for i in range(k.value)]

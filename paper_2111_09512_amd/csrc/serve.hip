@@ -155,7 +155,11 @@ void reap(silu_server *s)
 {
     for (int64_t k = s->completed_through + 1; k < s->steps; k++) {
         const int slot = (int)(k % RING);
-        if (s->done_step[slot] == k || hipEventQuery(s->ev[slot]) != hipSuccess) continue;
+        if (s->done_step[slot] == k) continue;
+        if (hipEventQuery(s->ev[slot]) != hipSuccess) {
+            if (s->mode == 0) break; // one stream: later steps are not done either
+            continue;
+        }
         s->done_step[slot] = k;
         if (s->mode == 1) {
             s->inflight -= s->slot_reqs[slot];
@@ -595,6 +599,20 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
     }
     if (n_active) *n_active = (int)s->active.size();
     if (n_queued) *n_queued = (int)s->queue.size();
+    return SILU_OK;
+}
+
+int silu_server_run(silu_server *s, int max_steps, int *n_active, int *n_queued)
+{
+    if (!s || max_steps < 1) return SILU_ERR_ARG;
+    int a = 0, q = 0;
+    for (int k = 0; k < max_steps; k++) {
+        const int st = silu_server_step(s, &a, &q);
+        if (st) return st;
+        if (a == 0) break;
+    }
+    if (n_active) *n_active = a;
+    if (n_queued) *n_queued = q;
     return SILU_OK;
 }
 

@@ -82,9 +82,15 @@ def make_requests(mats, rhs_per_matrix: int = 20, rate: float = 2000.0, seed: in
     return reqs
 
 
-def run_batched(server: B.Server, mids, reqs, realtime: bool = True):
-    """Feed arrivals (in real time) to the server, step it, poll completions.
-    Returns (latencies in s, makespan in s, steps)."""
+def run_batched(server: B.Server, mids, reqs, realtime: bool = True, lanes=None, steps_per_call: int = 1):
+    """Feed arrivals (in real time) to the server, step it, collect completions.
+    lanes: optional list of (server, mids, max_rows) tried in order instead of
+    the single server -- a request goes to the first lane whose max_rows covers
+    its matrix, so each size class is batched on its own stream and small
+    requests do not wait for the steps of large ones.  steps_per_call: scheduling
+    steps per call into the library (silu_server_run), so the host loop does not
+    pace the GPU.  Returns (latencies in s, makespan in s, loop iterations)."""
+    lanes = lanes or [(server, mids, None)]
     n = len(reqs)
     index = {}
     done_at = [0.0] * n
@@ -97,16 +103,23 @@ def run_batched(server: B.Server, mids, reqs, realtime: bool = True):
         now = time.perf_counter() - t0
         while nxt < n and (not realtime or reqs[nxt].arrival <= now):
             r = reqs[nxt]
-            index[server.submit(mids[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U)] = nxt
+            li = next(k for k, (_, _, cap) in enumerate(lanes) if cap is None or r.b.numel() <= cap)
+            sv, mv, _ = lanes[li]
+            index[(li, sv.submit(mv[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U))] = nxt
             pending.add(nxt)
             nxt += 1
-        active, queued = server.step()
+        for li, (sv, _, _) in enumerate(lanes):
+            if steps_per_call > 1:
+                sv.run(steps_per_call)
+            else:
+                sv.step()
         steps += 1
         now = time.perf_counter() - t0
-        for t in server.completed():
-            i = index.pop(t)
-            done_at[i] = now
-            pending.discard(i)
+        for li, (sv, _, _) in enumerate(lanes):
+            for t in sv.completed():
+                i = index.pop((li, t))
+                done_at[i] = now
+                pending.discard(i)
         if not pending and nxt < n and realtime:
             wait = reqs[nxt].arrival - (time.perf_counter() - t0)
             if wait > 0:

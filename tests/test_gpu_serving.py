@@ -314,3 +314,28 @@ def test_completed_reports_each_ticket_once(B, ctx, pool):
     for i, r in enumerate(reqs):
         np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
     server.close()
+
+
+def test_run_several_steps_per_call(B, ctx, pool):
+    """silu_server_run: several scheduling steps per call, same results."""
+    reqs = _requests(pool, 20, seed=13)
+    server = B.Server(ctx, arena_bytes=16 << 20, max_active=8)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    xs, tickets = [], []
+    for r in reqs:
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+    done = []
+    for _ in range(10000):
+        active, queued = server.run(5)
+        done += server.completed()
+        if len(done) == len(tickets):
+            break
+    assert sorted(done) == sorted(tickets)
+    with pytest.raises(B.SiluError) as e:
+        server.run(0)
+    assert e.value.status == -1
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
+    server.close()
