@@ -305,6 +305,16 @@ def main():
         log(f"graph replay: {ms_graph:.3f} ms/app ({1e3 / ms_graph:.1f} apps/s), identical to plain launches: "
             f"{graph_same}")
 
+    # ---- the same application with the zero initial guess declared (SILU_ZERO_GUESS: the
+    # first residual b - A 0 is b itself, so its pass over A is skipped; same result) ----
+    def app_zero():
+        x.zero_()
+        ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, zero_guess=True)
+
+    ms_zero = time_steps(torch, app_zero, args.steps, args.warmup)
+    zero_same = bool(torch.equal(x, x64))
+    log(f"zero guess declared: {ms_zero:.3f} ms/app ({1e3 / ms_zero:.1f} apps/s), identical: {zero_same}")
+
     # ---- locality-relabeled copies (SILU_REORDER): same results, gathers kept local ----
     reorder = None
     if args.reorder or (args.workload == "perm256" and not args.no_reorder):
@@ -524,6 +534,8 @@ def main():
         "layout_GBps": layout_app / (ms * 1e-3) / 1e9,
         "layout_bytes_per_app": layout_app,
         "copy_GBps": copy_gbps,
+        "zero_guess_ms": ms_zero,
+        "zero_guess_identical": zero_same,
         "reorder": reorder,
         "graph_ms": ms_graph,
         "graph_apps_per_s": (1e3 / ms_graph) if ms_graph else None,
