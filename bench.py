@@ -193,6 +193,7 @@ def main():
     ap.add_argument("--no-fixed-point", action="store_true")
     ap.add_argument("--no-inner-sweep", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-zero-guess", action="store_true")
     ap.add_argument("--reorder", action="store_true", help="also time SILU_REORDER (on by default for perm256)")
     ap.add_argument("--no-reorder", action="store_true")
     ap.add_argument("--serving-arena-mb", type=int, default=512)
@@ -307,13 +308,15 @@ def main():
 
     # ---- the same application with the zero initial guess declared (SILU_ZERO_GUESS: the
     # first residual b - A 0 is b itself, so its pass over A is skipped; same result) ----
-    def app_zero():
-        x.zero_()
-        ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, zero_guess=True)
+    ms_zero = zero_same = None
+    if not args.no_zero_guess:
+        def app_zero():
+            x.zero_()
+            ctx.ilu_smooth(Ad, F, bvec, x, outer, mL, mU, kernel=kern, ws=ws, zero_guess=True)
 
-    ms_zero = time_steps(torch, app_zero, args.steps, args.warmup)
-    zero_same = bool(torch.equal(x, x64))
-    log(f"zero guess declared: {ms_zero:.3f} ms/app ({1e3 / ms_zero:.1f} apps/s), identical: {zero_same}")
+        ms_zero = time_steps(torch, app_zero, args.steps, args.warmup)
+        zero_same = bool(torch.equal(x, x64))
+        log(f"zero guess declared: {ms_zero:.3f} ms/app ({1e3 / ms_zero:.1f} apps/s), identical: {zero_same}")
 
     # ---- locality-relabeled copies (SILU_REORDER): same results, gathers kept local ----
     reorder = None
