@@ -402,14 +402,19 @@ def main():
         bh = bvec.cpu().numpy()
         norm_a = ctx.norm2_estimate(Ad, iters=50)
         krylov = {"restart": 30, "tol": 1e-8, "precond": "1 outer x 4/4 ILU smoother", "norm2_A_estimate": norm_a}
-        for label, mixed in (("fp64", False), ("mixed", True)):
+        use_reorder = args.reorder or (args.workload == "perm256" and not args.no_reorder)
+        runs = [("fp64", False, False), ("mixed", True, False)]
+        if use_reorder:
+            runs += [("fp64_reorder", False, True), ("mixed_reorder", True, True)]
+        for label, mixed, ro in runs:
             x.zero_()
-            ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=5, tol=1e-8, outer=1, m_L=4, m_U=4, mixed=mixed)
+            ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=5, tol=1e-8, outer=1, m_L=4, m_U=4, mixed=mixed,
+                       reorder=ro)
             x.zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=1e-8, outer=1, m_L=4, m_U=4,
-                                     mixed=mixed)
+                                     mixed=mixed, reorder=ro)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
             relres = float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / np.linalg.norm(bh))

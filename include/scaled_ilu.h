@@ -364,9 +364,11 @@ int silu_ilu0_fixed_point(silu_ctx *ctx, const silu_csr *A, int sweeps, silu_csr
  * F: row- or row/column-scaled factors.  *iters: steps taken.  hist: NULL or
  * a host array of max_iters + 1 doubles receiving the relative residual
  * estimates (hist[0] for the initial x).  Dot products reduce in a fixed order
- * (reproducible; not the sequential order).  ws: at least
- * silu_fgmres_workspace_size(ctx, n, restart) bytes (2 restart + 6
- * n-vectors and a few KB), 256-byte aligned.  Synchronous (the small
+ * (reproducible; not the sequential order).  flags: SILU_MIXED, SILU_REORDER
+ * (the preconditioner sweeps relabeled copies; same iterates bit for bit),
+ * the kernel choices, SILU_VALIDATE; SILU_GRAPH is ignored.  ws: at least
+ * silu_fgmres_workspace_size(ctx, n, restart, flags) bytes (2 restart + 6
+ * n-vectors, 2 more with SILU_REORDER, and a few KB), 256-byte aligned.  Synchronous (the small
  * least-squares problem is solved on the host every step).  Errors: ARG,
  * SHAPE, NOMEM, UNSUPPORTED (factors neither row- nor row/column-scaled),
  * and those of ilu_smooth.

@@ -341,12 +341,13 @@ class Context:
     # ---- Krylov solver around the smoother ----
     def fgmres(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, restart: int = 30, max_iters: int = 300,
                tol: float = 1e-8, outer: int = 1, m_L: int = 3, m_U: int = 3, mixed: bool = False,
-               kernel: str | None = None, check_finite: bool = False):
+               kernel: str | None = None, check_finite: bool = False, reorder: bool = False):
         """FGMRES(restart) with the smoother as right preconditioner, in place on x.
         Returns (steps, history of relative residual estimates)."""
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
-        flags = (SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) | KERNELS[kernel]
+        flags = ((SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) |
+                 (SILU_REORDER if reorder else 0) | KERNELS[kernel])
         nb = C.c_size_t()
         self._check(_lib.silu_fgmres_workspace_size(self._h, A.n, restart, flags, C.byref(nb)),
                     "silu_fgmres_workspace_size")

@@ -1506,31 +1506,35 @@ int silu_ilu0_fixed_point(silu_ctx *c, const silu_csr *A, int sweeps, silu_csr *
 // ---- FGMRES with the smoother as right preconditioner -----------------------
 namespace {
 
+// Smoother slots: 4 n-vectors, 6 when the smoother runs on relabeled copies.
+int smoother_slots(int flags) { return (flags & SILU_REORDER) ? 6 : 4; }
+
 struct KrylovWs {
     size_t vec;     // bytes of one n-vector slot
     char *base;
     int m;
+    int ss;         // smoother slots
     double *V(int i) const { return (double *)(base + vec * (size_t)i); }               // i = 0..m
     double *Z(int i) const { return (double *)(base + vec * (size_t)(m + 1 + i)); }     // i = 0..m-1
     double *w() const { return (double *)(base + vec * (size_t)(2 * m + 1)); }
-    void *smoother() const { return base + vec * (size_t)(2 * m + 2); }                 // 4 slots
-    double *part() const { return (double *)(base + vec * (size_t)(2 * m + 6)); }      // DOT_BLOCKS
+    void *smoother() const { return base + vec * (size_t)(2 * m + 2); }                 // ss slots
+    double *part() const { return (double *)(base + vec * (size_t)(2 * m + 2 + ss)); } // DOT_BLOCKS
     double *h() const { return part() + DOT_BLOCKS; }                                    // m + 2 scalars
 };
 
-size_t krylov_ws_bytes(int64_t n, int m)
+size_t krylov_ws_bytes(int64_t n, int m, int flags)
 {
     const size_t vec = ws_vec_bytes(n);
-    return vec * (size_t)(2 * m + 6) + ((size_t)DOT_BLOCKS + (size_t)m + 2) * sizeof(double) + 256;
+    return vec * (size_t)(2 * m + 2 + smoother_slots(flags)) + ((size_t)DOT_BLOCKS + (size_t)m + 2) * sizeof(double) +
+           256;
 }
 
 } // namespace
 
 int silu_fgmres_workspace_size(silu_ctx *c, int64_t n, int restart, int flags, size_t *bytes)
 {
-    (void)flags;
     if (!c || !bytes || n < 0 || restart < 1) return SILU_ERR_ARG;
-    *bytes = krylov_ws_bytes(n, restart);
+    *bytes = krylov_ws_bytes(n, restart, flags);
     return SILU_OK;
 }
 
@@ -1546,13 +1550,13 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     if (st) return st;
     const int64_t n = A->n_rows;
     if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
-    if (ws_bytes < krylov_ws_bytes(n, restart)) return SILU_ERR_NOMEM;
+    if (ws_bytes < krylov_ws_bytes(n, restart, flags)) return SILU_ERR_NOMEM;
     if (flags & SILU_VALIDATE) {
         if ((st = validate(c, A, 0))) return st;
     }
     const int m = restart;
-    KrylovWs K{ws_vec_bytes(n), (char *)ws, m};
-    const size_t sws_bytes = 4 * K.vec;
+    KrylovWs K{ws_vec_bytes(n), (char *)ws, m, smoother_slots(flags)};
+    const size_t sws_bytes = (size_t)K.ss * K.vec;
     const int pflags = (flags & ~(SILU_CHECK_FINITE | SILU_VALIDATE | SILU_DIRECT | SILU_GRAPH)) | SILU_ZERO_GUESS;
     const SweepGeom gA = pick_geom(n, A->nnz, flags);
     auto dot = [&](const double *a, const double *bb, double *out, bool root) {

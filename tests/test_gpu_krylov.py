@@ -152,3 +152,18 @@ def test_zero_guess_flag(ctx, cases, name):
         ctx.ilu_smooth(c.Ad, c.F, b, x1, 2, 3, 3, mixed=mixed)
         ctx.ilu_smooth(c.Ad, c.F, b, x2, 2, 3, 3, mixed=mixed, zero_guess=True)
         np.testing.assert_array_equal(host(x1), host(x2))
+
+
+@pytest.mark.parametrize("name", ["perm9", "vardens13_ilu1"])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_fgmres_with_relabeled_preconditioner(ctx, cases, name, mixed):
+    """SILU_REORDER inside FGMRES: every preconditioner application is bit for
+    bit the plain one, so the whole run is too."""
+    c = cases[name]
+    b = dev(W.rhs(c.A.n, 3))
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    k1, h1 = ctx.fgmres(c.Ad, c.F, b, x1, restart=8, max_iters=60, tol=1e-10, mixed=mixed)
+    k2, h2 = ctx.fgmres(c.Ad, c.F, b, x2, restart=8, max_iters=60, tol=1e-10, mixed=mixed, reorder=True)
+    assert k1 == k2
+    np.testing.assert_array_equal(h1, h2)
+    np.testing.assert_array_equal(host(x1), host(x2))
