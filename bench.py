@@ -73,6 +73,20 @@ def time_steps(torch, fn, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def host_cpu():
+    """The host CPU's model name and the hardware threads visible to this process."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {len(os.sched_getaffinity(0))} hardware threads visible"
+
+
 def cpu_baseline(W, nsample=100, reps=None):
     """The oracle (plain C, one thread) on a bounded sample of the same operator:
     the 27-pt anisotropic operator on an nsample^3 grid, its own ILUT factors,
@@ -498,7 +512,7 @@ def main():
         depths = (dL, dU)
         log(f"level analysis: depth L={dL} U={dU} ({time.perf_counter() - t:.1f}s)")
         ms_direct = time_steps(torch, app_direct, max(3, min(args.steps, 10)), 2)
-        log(f"direct: {ms_direct:.3f} ms/app")
+        log(f"direct: {ms_direct:.3f} ms/app, {ms_direct * 1e3 / (outer * (dL + dU)):.2f} us per level")
 
     # ---- CPU oracle baseline on a bounded sample ----
     cpu = None
@@ -506,7 +520,7 @@ def main():
         per_app, work_s, n_s, k = cpu_baseline(W)
         work_full = nnzA + 3 * nnzL + 3 * nnzU
         cpu_apps = 1.0 / (per_app * work_full / work_s)
-        cpu = {"value": cpu_apps, "unit": "apps/s", "cores": 1, "kind": "oracle",
+        cpu = {"value": cpu_apps, "unit": "apps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
                "sample": f"oracle (plain C, 1 thread): same 27-pt operator on a 100^3 grid (n={n_s}), its own "
                          f"ILUT(1e-3,20) factors, {k} applications of 2x4 smoothing at {per_app * 1e3:.1f} ms each, "
                          f"scaled to n=8M by matrix entries per application ({work_full}/{work_s})"}
@@ -562,6 +576,7 @@ def main():
         "direct_ms": ms_direct,
         "speedup_vs_direct": (ms_direct / ms) if ms_direct else None,
         "direct_levels": depths,
+        "direct_us_per_level": (ms_direct * 1e3 / (outer * sum(depths))) if ms_direct else None,
         "kernels": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
                         "GBps": v["bytes"] / v["ms"] / 1e6, "layout_GBps": v["layout_bytes"] / v["ms"] / 1e6}
                     for k, v in st.items()},
