@@ -192,7 +192,7 @@ def bench_serving(torch, B, ctx, arena_mb):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="aniso200", choices=sorted(WORKLOADS))
     ap.add_argument("--N", type=int, default=None, help="override grid side (testing only)")
@@ -265,14 +265,16 @@ def main():
     log(f"stream copy {copy_gbps:.0f} GB/s")
 
     def timed(fn, label):
-        """Warm up, then time the steps with per-launch HIP events on; returns
-        (ms per application, algorithmic bytes per application, per-kernel stats)."""
+        """Warm up, time the steps (no instrumentation), then run them again with
+        per-launch HIP events on for the per-kernel figures; returns (ms per
+        application, algorithmic bytes per application, per-kernel stats)."""
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
+        ms_ = time_steps(torch, fn, args.steps, 0)
         ctx.stats_reset()
         ctx.set_timing(True)
-        ms_ = time_steps(torch, fn, args.steps, 0)
+        time_steps(torch, fn, args.steps, 0)
         ctx.set_timing(False)
         st_ = {k: v for k, v in ctx.stats().items() if v["launches"]}
         bytes_ = sum(v["bytes"] for v in st_.values()) / args.steps
