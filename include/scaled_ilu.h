@@ -313,8 +313,9 @@ int gs_scale_split(silu_ctx *ctx, const silu_csr *A, silu_factors *G, int flags)
  * G from gs_scale_split.  flags: SILU_MIXED runs the Richardson loop on
  * G->Ls_val32 with FP32 iterates and accumulation (the residual is computed
  * in FP64 and rounded to FP32 before the scaling; x += y in FP64);
- * SILU_CHECK_FINITE, SILU_VALIDATE and the layout flags as for ilu_smooth.
- * Workspace as for ilu_smooth.  Asynchronous.  Errors: ARG (nulls,
+ * SILU_CHECK_FINITE, SILU_VALIDATE, SILU_REORDER and the layout flags as for
+ * ilu_smooth (G->Us may be empty).  Workspace as for ilu_smooth.
+ * Asynchronous.  Errors: ARG (nulls,
  * outer_sweeps or terms < 1, SILU_DIRECT, G not from gs_scale_split), SHAPE,
  * NOMEM, UNSUPPORTED (MIXED without the FP32 copy), PATTERN, NONFINITE, HIP.
  */

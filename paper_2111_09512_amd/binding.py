@@ -422,10 +422,10 @@ class Context:
 
     def gs_smooth(self, A: Csr, G: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, terms: int,
                   mixed: bool = False, check_finite: bool = False, validate: bool = False, kernel: str | None = None,
-                  ws: torch.Tensor | None = None) -> torch.Tensor:
+                  ws: torch.Tensor | None = None, reorder: bool = False) -> torch.Tensor:
         """x <- x + sum_{j<terms} (-D^{-1}L)^j D^{-1}(b - A x), `outer_sweeps` times, in place."""
         flags = ((SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) |
-                 (SILU_VALIDATE if validate else 0) | KERNELS[kernel])
+                 (SILU_VALIDATE if validate else 0) | (SILU_REORDER if reorder else 0) | KERNELS[kernel])
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws

@@ -719,6 +719,10 @@ int get_reorder(silu_ctx *c, const silu_csr *A, const silu_factors *F, Reorder *
     const float *f32[2] = {F->Ls_val32, F->Us_val32};
     float **d32[2] = {&R.L32, &R.U32};
     for (int t = 0; t < 2; t++) {
+        if (!fac[t]->row_ptr) { // an absent factor (the Gauss-Seidel split has no U)
+            *dst[t] = *fac[t];
+            continue;
+        }
         if ((e = hipMemcpy(rp.data(), fac[t]->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost)) != hipSuccess)
             return fail_free(hip_fail(c, e));
         if ((st = relabel_csr(c, fac[t], rp, order, R.order, R.pos, dst[t], &rp2))) return fail_free(st);
@@ -1390,6 +1394,31 @@ int gs_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *G, const doubl
     if (flags & SILU_VALIDATE) {
         if ((st = validate(c, A, 0))) return st;
         if ((st = validate(c, &G->Ls, -1))) return st;
+    }
+    if (flags & SILU_REORDER) {
+        // the same steps on relabeled copies of A and Gs: b and x in, x out
+        Reorder *R = nullptr;
+        if ((st = get_reorder(c, A, G, &R))) return st;
+        Ws w{(char *)ws, ws_vec_bytes(n)};
+        double *b2 = (double *)w.slot(4), *x2 = (double *)w.slot(5);
+        st = timed_launch(c, 36.0 * (double)n, [&](const char **nm) {
+            *nm = "reorder_in";
+            return launch_permute_in((int)n, R->pos, b, x, b2, x2, c->stream);
+        });
+        if (st) return st;
+        silu_factors G2 = *G;
+        G2.Ls = R->L2;
+        G2.Us = R->U2;
+        G2.dinv = R->dinv2;
+        G2.Ls_val32 = R->L32;
+        const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
+        if ((st = gs_smooth(c, &R->A2, &G2, b2, x2, outer_sweeps, terms, inner, ws, ws_bytes))) return st;
+        st = timed_launch(c, 20.0 * (double)n, [&](const char **nm) {
+            *nm = "reorder_out";
+            return launch_scatter((int)n, R->order, x2, x, c->stream);
+        });
+        if (st) return st;
+        return (flags & SILU_CHECK_FINITE) ? check_finite(c, n, x) : SILU_OK;
     }
     Ws w{(char *)ws, ws_vec_bytes(n)};
     void *s = w.slot(1), *tmp[2] = {w.slot(2), w.slot(3)};

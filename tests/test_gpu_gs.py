@@ -141,3 +141,18 @@ def test_gs_errors(B, ctx, cases):
     with pytest.raises(B.SiluError) as e:  # ILU factors are not a Gauss-Seidel split
         ctx.gs_smooth(c.Ad, F, b, x, 1, 2)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("name", ["perm9", "poisson17", "mmatrix3000"])
+def test_gs_smooth_relabeled(orc, ctx, cases, name, mixed):
+    """SILU_REORDER: the Gauss-Seidel smoother on relabeled copies equals the
+    oracle (its emulation for the mixed form) bit for bit."""
+    c = cases[name]
+    b = W.rhs(c.A.n, 0)
+    x0 = W.rhs(c.A.n, 7)
+    ref = orc.gs_smooth(c.A, c.Gs, c.dinv, b, x0, 2, 3, mixed=mixed)
+    for rep in range(2):
+        x = dev(x0)
+        ctx.gs_smooth(c.Ad, c.G, dev(b), x, 2, 3, mixed=mixed, reorder=True)
+        np.testing.assert_array_equal(host(x), ref)
