@@ -406,13 +406,14 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch_args(BatchArgs ba)
 // short sleep): on expiry the op's index + 1 goes to ctl[1], the tile is
 // skipped and still counted, so every workgroup drains in bounded time and
 // the host reports the failure.
-// Memory order: every XCD has its own L2, so the counters are updated and
-// polled at system scope, which places them beyond the L2s (an agent-scope
-// atomic is performed in the issuing XCD's L2, where a poll from another XCD
-// need not see it).  A finished tile's stores reach memory through each
-// thread's fence (L2 write-back) before the barrier and the count; the
-// waiting thread fences (L2 invalidate) after observing the count, before the
-// barrier that releases its workgroup.
+// Memory order: every XCD has its own L2; the counters are updated and
+// polled at system scope so that their coherence does not rest on any one
+// L2.  A finished tile's stores reach memory through each thread's fence (L2
+// write-back) before the barrier and the count; the waiting thread fences (L2
+// invalidate) after observing the count, before the barrier that releases its
+// workgroup.  (The serving runtime does not launch this kernel: on MI355X its
+// launches did not finish, at agent and at system scope, for a cause not yet
+// found.)
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_persist(PersistPlan p)
 {
