@@ -460,3 +460,30 @@ def test_values_changed_in_place(orc, B, ctx):
     x = dev(np.zeros(A.n))
     ctx.ilu_smooth(Ad, F, dev(b), x, 1, 3, 3)
     np.testing.assert_array_equal(host(x), orc.smooth(A2, L2, Us, dinv, b, np.zeros(A.n), 1, 3, 3))
+
+
+@pytest.mark.parametrize("kernel", [None, "sliced16", "sliced32", "stream", "stream32", "blocked", "win"])
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 127, 129, 255, 257, 1000])
+def test_ragged_sizes_variable_rows(orc, B, ctx, n, kernel):
+    """Row counts around the 64-row slice and the 256-row block, with row
+    lengths from 0 to dozens in each factor (masked and unmasked slices side by
+    side): FP64 and the FP32-inner form bit for bit against the oracle and its
+    emulation."""
+    rng = np.random.default_rng(n)
+    M = np.zeros((n, n))
+    for i in range(n):
+        k = int(rng.integers(0, min(n, 40)))
+        cols = rng.choice(n, size=k, replace=False)
+        M[i, cols] = -rng.random(k)
+    np.fill_diagonal(M, 0.0)
+    M = M + M.T
+    np.fill_diagonal(M, np.abs(M).sum(axis=1) + 1.0)
+    A = W.CSR.from_dense(M)
+    c = Case(orc, B, ctx, A, "ilu0", {}, fp32=True)
+    b, x0 = W.rhs(n, 1), W.rhs(n, 2)
+    ref = orc.smooth(A, c.Ls, c.Us, c.dinv, b, x0, 2, 3, 4)
+    ref32 = orc.smooth_mixed(A, c.Ls, c.Us, c.dinv, b, x0, 2, 3, 4)
+    for mixed, want in ((False, ref), (True, ref32)):
+        x = dev(x0)
+        ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 3, 4, mixed=mixed, kernel=kernel)
+        np.testing.assert_array_equal(host(x), want)
