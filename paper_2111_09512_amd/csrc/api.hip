@@ -719,8 +719,10 @@ int get_reorder(silu_ctx *c, const silu_csr *A, const silu_factors *F, Reorder *
     const float *f32[2] = {F->Ls_val32, F->Us_val32};
     float **d32[2] = {&R.L32, &R.U32};
     for (int t = 0; t < 2; t++) {
-        if (!fac[t]->row_ptr) { // an absent factor (the Gauss-Seidel split has no U)
-            *dst[t] = *fac[t];
+        if (!fac[t]->row_ptr) { // an absent factor (the Gauss-Seidel split has no U): nothing to own
+            *dst[t] = silu_csr();
+            dst[t]->n_rows = dst[t]->n_cols = fac[t]->n_rows;
+            dst[t]->dtype = fac[t]->dtype;
             continue;
         }
         if ((e = hipMemcpy(rp.data(), fac[t]->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost)) != hipSuccess)
