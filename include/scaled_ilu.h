@@ -506,6 +506,13 @@ int silu_server_poll(silu_server *server, int64_t ticket, int *state);
  * array); *count receives how many.  One call replaces a poll per pending
  * request.  Done tickets are kept until returned here (8 bytes each). */
 int silu_server_completed(silu_server *server, int64_t *tickets, int capacity, int *count);
+/* Block until the ticket's request is done (state 3), stepping the server
+ * while it is queued or running, then waiting for its last launch.  The
+ * server's other requests advance with it. */
+int silu_server_wait(silu_server *server, int64_t ticket);
+/* Host steady-clock times in ns: when the ticket was submitted and when the
+ * server first found it done (-1 while it is not).  ARG for unknown tickets. */
+int silu_server_times(silu_server *server, int64_t ticket, int64_t *submitted_ns, int64_t *done_ns);
 int silu_server_last_hip_error(const silu_server *server);
 
 /*

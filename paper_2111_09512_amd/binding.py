@@ -127,6 +127,8 @@ _sig = {
     "silu_server_set_mode": (C.c_int, [_P, C.c_int, C.c_int]),
     "silu_server_completed": (C.c_int, [_P, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]),
     "silu_server_run": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "silu_server_wait": (C.c_int, [_P, C.c_int64]),
+    "silu_server_times": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "silu_reorder_rcm": (C.c_int, [C.c_int64, _P, _P, _P, C.c_double, _P]),
     "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
@@ -707,6 +709,17 @@ class Server:
         for t in out:
             self._req.pop(t, None)
         return out
+
+    def wait(self, ticket: int):
+        """Block until the request is done (steps the server as needed)."""
+        self._check(_lib.silu_server_wait(self._h, ticket), "silu_server_wait")
+        self._req.pop(ticket, None)
+
+    def times(self, ticket: int) -> tuple[float, float | None]:
+        """(submitted, found done) on the host's steady clock, in seconds."""
+        a, d = C.c_int64(), C.c_int64()
+        self._check(_lib.silu_server_times(self._h, ticket, C.byref(a), C.byref(d)), "silu_server_times")
+        return a.value * 1e-9, (d.value * 1e-9 if d.value >= 0 else None)
 
     def poll(self, ticket: int) -> int:
         st = C.c_int()

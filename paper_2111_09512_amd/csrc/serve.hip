@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -64,6 +65,13 @@ struct Request {
 
 size_t vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
 
+int64_t now_ns()
+{
+    return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
 } // namespace
 
 struct silu_server {
@@ -80,6 +88,7 @@ struct silu_server {
     std::map<int64_t, int64_t> finish_step;            // ticket -> step of its last op
     std::vector<std::pair<int64_t, int64_t>> to_report; // (step, ticket) not yet known done
     std::deque<int64_t> done_queue;                     // done, not yet returned by completed()
+    std::map<int64_t, std::pair<int64_t, int64_t>> times; // ticket -> (submitted, found done), steady ns
     int64_t next_ticket = 0, steps = 0, completed_through = -1;
     hipEvent_t ev[RING] = {};
     int64_t done_step[RING];   // the step a slot last held, once the GPU has passed it
@@ -179,9 +188,10 @@ void reap(silu_server *s)
     auto &rp = s->to_report;
     w = 0;
     for (size_t i = 0; i < rp.size(); i++) {
-        if (step_done(s, rp[i].first))
+        if (step_done(s, rp[i].first)) {
             s->done_queue.push_back(rp[i].second);
-        else
+            s->times[rp[i].second].second = now_ns();
+        } else
             rp[w++] = rp[i];
     }
     rp.resize(w);
@@ -502,6 +512,7 @@ int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x
     q.mU = m_U;
     q.total = outer * (1 + (m_L - 1) + (m_U - 1));
     s->queue.push_back(q);
+    s->times[q.ticket] = {now_ns(), -1};
     *ticket = q.ticket;
     return SILU_OK;
 }
@@ -644,6 +655,35 @@ int silu_server_completed(silu_server *s, int64_t *tickets, int capacity, int *c
     }
     *count = k;
     return SILU_OK;
+}
+
+int silu_server_times(silu_server *s, int64_t ticket, int64_t *submitted_ns, int64_t *done_ns)
+{
+    if (!s || !submitted_ns || !done_ns) return SILU_ERR_ARG;
+    reap(s);
+    auto it = s->times.find(ticket);
+    if (it == s->times.end()) return SILU_ERR_ARG;
+    *submitted_ns = it->second.first;
+    *done_ns = it->second.second;
+    return SILU_OK;
+}
+
+int silu_server_wait(silu_server *s, int64_t ticket)
+{
+    if (!s || ticket < 0 || ticket >= s->next_ticket) return SILU_ERR_ARG;
+    for (;;) {
+        int state = 0;
+        int st = silu_server_poll(s, ticket, &state);
+        if (st) return st;
+        if (state == 3) return SILU_OK;
+        if (state == 2) { // its last launch is enqueued: wait for that step's event
+            const int64_t k = s->finish_step[ticket];
+            const hipError_t e = hipEventSynchronize(s->ev[k % RING]);
+            if (e != hipSuccess) return fail(s, e);
+            continue;
+        }
+        if ((st = silu_server_step(s, nullptr, nullptr))) return st; // queued or running: advance
+    }
 }
 
 int silu_server_set_wait_limit(silu_server *s, int polls)

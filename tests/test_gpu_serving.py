@@ -339,3 +339,29 @@ def test_run_several_steps_per_call(B, ctx, pool):
     for i, r in enumerate(reqs):
         np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
     server.close()
+
+
+def test_wait_and_times(B, ctx, pool):
+    """silu_server_wait drives the server until the request is done; the
+    submit and completion times are ordered; results equal the lone runs."""
+    reqs = _requests(pool, 12, seed=17)
+    server = B.Server(ctx, arena_bytes=16 << 20, max_active=4)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    xs, tickets = [], []
+    for r in reqs:
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+    t0, d0 = server.times(tickets[-1])
+    assert d0 is None
+    server.wait(tickets[-1])  # the last one: everything before it is admitted first
+    assert server.poll(tickets[-1]) == server.DONE
+    for t in tickets:
+        server.wait(t)
+        a, d = server.times(t)
+        assert d is not None and d >= a
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
+    with pytest.raises(B.SiluError):
+        server.times(10 ** 6)
+    server.close()
