@@ -106,7 +106,7 @@ def cpu_baseline(W, nsample=100, reps=None):
         O.smooth(A, Ls, Us, dinv, b, x0, 2, 4, 4)
         k += 1
         el = time.perf_counter() - t0
-        if (reps and k >= reps) or (not reps and el > 8.0):
+        if (reps and k >= reps) or (not reps and el > 12.0):
             break
     per_app = el / k
     work_sample = A.nnz + 3 * Ls.nnz + 3 * Us.nnz
