@@ -32,6 +32,8 @@ codes), and `roofline.traffic` the HBM bytes the counters measured.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 import argparse
+import contextlib
+import gc
 import json
 import os
 import sys
@@ -59,17 +61,34 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+@contextlib.contextmanager
+def gc_paused():
+    """Python's cyclic garbage collector paused, after one full collection, for
+    a timed region: a generation-2 pass over this process's heap takes tens of
+    milliseconds and, landing inside a loop of short launches, would stall the
+    stream for that long."""
+    gc.collect()
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 def time_steps(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
+    with gc_paused():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
 
 
@@ -151,7 +170,8 @@ def bench_serving(torch, B, ctx, arena_mb):
     S.run_batched(server, mids, reqs[:8], realtime=False)
     for r in reqs:
         r.x.zero_()
-    lat_b, span_b, steps = S.run_batched(server, mids, reqs)
+    with gc_paused():
+        lat_b, span_b, steps = S.run_batched(server, mids, reqs)
     xb = [r.x.clone() for r in reqs]
     server.close()
     # two lanes: matrices up to 64^3 rows batched on the context's stream, larger
@@ -166,13 +186,15 @@ def bench_serving(torch, B, ctx, arena_mb):
     S.run_batched(None, None, reqs[:8], realtime=False, lanes=lanes)
     for r in reqs:
         r.x.zero_()
-    lat_l, span_l, steps_l = S.run_batched(None, None, reqs, lanes=lanes)
+    with gc_paused():
+        lat_l, span_l, steps_l = S.run_batched(None, None, reqs, lanes=lanes)
     same_l = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
     small.close()
     large.close()
     for r in reqs:
         r.x.zero_()
-    lat_1, span_1 = S.run_one_at_a_time(ctx, mats, reqs)
+    with gc_paused():
+        lat_1, span_1 = S.run_one_at_a_time(ctx, mats, reqs)
     same = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
     res = {"requests": len(reqs), "matrices": len(mats), "arrival_rate_per_s": 2000.0, "arena_MB": arena_mb,
            "batched": {"apps_per_s": len(reqs) / span_b, "makespan_s": span_b, "steps": steps,
@@ -293,13 +315,14 @@ def main():
     x64 = x.clone()
     # spread: the same applications timed one by one (after the timed region)
     per = []
-    for _ in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        app_f64()
-        e1.record()
-        torch.cuda.synchronize()
-        per.append(e0.elapsed_time(e1))
+    with gc_paused():
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            app_f64()
+            e1.record()
+            torch.cuda.synchronize()
+            per.append(e0.elapsed_time(e1))
     spread = {f"p{q}": float(np.percentile(per, q)) for q in (10, 50, 90)}
     log(f"per-application ms p10/p50/p90: {spread['p10']:.3f} / {spread['p50']:.3f} / {spread['p90']:.3f}")
     apps = 1e3 / ms
@@ -428,11 +451,12 @@ def main():
                        reorder=ro)
             x.zero_()
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=1e-8, outer=1, m_L=4, m_U=4,
-                                     mixed=mixed, reorder=ro)
-            torch.cuda.synchronize()
-            secs = time.perf_counter() - t0
+            with gc_paused():
+                t0 = time.perf_counter()
+                steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=1e-8, outer=1, m_L=4,
+                                         m_U=4, mixed=mixed, reorder=ro)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
             relres = float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / np.linalg.norm(bh))
             nrbe = ctx.nrbe(Ad, bvec, x, norm_a)
             log(f"fgmres {label}: {steps} steps, {secs * 1e3:.1f} ms, true relres {relres:.2e}, NRBE {nrbe:.2e}")
