@@ -975,12 +975,16 @@ int orc_smooth_until(int n, const int *Arp, const int *Acol, const double *Aval,
  *     for i = 1..j: h_ij = (w, v_i); w = w - h_ij v_i
  *     h_{j+1,j} = ||w||; v_{j+1} = w / h_{j+1,j}
  *     apply the previous rotations to column j, make the new one, update g
- *     stop when |g_{j+1}| / ||b|| < tol (or h_{j+1,j} == 0)
+ *     stop when |g_{j+1}| / (||b|| + norm_a ||x_j||) < tol (or h_{j+1,j} == 0)
  *   y = the solution of the triangular system H y = g;  x = x0 + sum_i y_i z_i
  *   restart from x while not converged and fewer than max_iters steps.
+ * |g_{j+1}| is the residual norm of the iterate x_j = x0 + Z_j y_j that the
+ * first j steps define.  norm_a = 0 gives the relative residual of eq. relres;
+ * norm_a = ||A||_2 the norm-wise relative backward error of eq. nbre, whose
+ * ||x_j|| is taken from x_j formed explicitly after every step.
  * Dot products and norms are summed in index order.  hist[k] receives the
- * relative residual estimate after k steps (hist[0] = ||b - A x0|| / ||b||);
- * returns the number of steps taken.  ws: (2m + 7) n + (m + 1)(m + 4) doubles.
+ * estimate after k steps (hist[0] from the true residual of x0); returns the
+ * number of steps taken.  ws: (2m + 8) n + (m + 1)(m + 4) doubles.
  * ========================================================================= */
 static double orc_dot(int n, const double *a, const double *b)
 {
@@ -989,11 +993,22 @@ static double orc_dot(int n, const double *a, const double *b)
     return s;
 }
 
+/* y = the solution of the leading j x j upper-triangular block of H (column-
+ * major with leading dimension m + 1) against g, by back substitution. */
+static void orc_fgmres_solve(int m, int j, const double *H, const double *g, double *y)
+{
+    for (int i = j - 1; i >= 0; i--) {
+        double t = g[i];
+        for (int c2 = i + 1; c2 < j; c2++) t = t - H[i + (size_t)(m + 1) * c2] * y[c2];
+        y[i] = t / H[i + (size_t)(m + 1) * i];
+    }
+}
+
 int orc_fgmres(int n, const int *Arp, const int *Acol, const double *Aval,
                const int *Lrp, const int *Lcol, const double *Lval,
                const int *Urp, const int *Ucol, const double *Uval, const double *dinv,
                int outer, int mL, int mU, const double *b, double *x, int m, int max_iters, double tol,
-               double *hist, double *ws)
+               double norm_a, double *hist, double *ws)
 {
     const size_t N = (size_t)n;
     double *V = ws;                          /* (m + 1) n */
@@ -1005,12 +1020,13 @@ int orc_fgmres(int n, const int *Arp, const int *Acol, const double *Aval,
     double *sn = cs + m;                     /* m */
     double *g = sn + m;                      /* m + 1 */
     double *y = g + m + 1;                   /* m */
+    double *xj = y + m;                      /* n: the iterate after each step (norm_a > 0) */
     const double nb = orc_nrm2(n, b);
     int k = 0;
     orc_residual(n, Arp, Acol, Aval, b, x, V);
     double beta = orc_nrm2(n, V);
-    hist[0] = beta / nb;
-    if (hist[0] < tol) return 0;
+    hist[0] = beta / (nb + norm_a * orc_nrm2(n, x));
+    if (!(hist[0] >= tol)) return 0;
     while (k < max_iters) {
         for (int i = 0; i < n; i++) V[i] = V[i] / beta;
         for (int i = 0; i <= m; i++) g[i] = 0.0;
@@ -1044,7 +1060,18 @@ int orc_fgmres(int n, const int *Arp, const int *Acol, const double *Aval,
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             k++;
-            hist[k] = fabs(g[j + 1]) / nb;
+            double xn = 0.0;
+            if (norm_a > 0.0) {
+                /* x_j = x0 + Z y from the first j + 1 columns of H and g */
+                orc_fgmres_solve(m, j + 1, H, g, y);
+                for (int t = 0; t < n; t++) xj[t] = x[t];
+                for (int i = 0; i <= j; i++) {
+                    const double *zi = Z + (size_t)i * N;
+                    for (int t = 0; t < n; t++) xj[t] = xj[t] + y[i] * zi[t];
+                }
+                xn = orc_nrm2(n, xj);
+            }
+            hist[k] = fabs(g[j + 1]) / (nb + norm_a * xn);
             if (hist[k] < tol || den == 0.0) {
                 done = 1;
                 j++;
@@ -1052,11 +1079,7 @@ int orc_fgmres(int n, const int *Arp, const int *Acol, const double *Aval,
             }
         }
         /* y = H^{-1} g (upper triangular, j x j), x = x + Z y */
-        for (int i = j - 1; i >= 0; i--) {
-            double t = g[i];
-            for (int c2 = i + 1; c2 < j; c2++) t = t - H[i + (size_t)(m + 1) * c2] * y[c2];
-            y[i] = t / H[i + (size_t)(m + 1) * i];
-        }
+        orc_fgmres_solve(m, j, H, g, y);
         for (int i = 0; i < j; i++) {
             const double *zi = Z + (size_t)i * N;
             for (int t = 0; t < n; t++) x[t] = x[t] + y[i] * zi[t];

@@ -69,7 +69,8 @@ def lib():
                                     C.c_int, C.c_int, C.c_int, _f64p, _f32p]
         L.orc_gs_smooth.restype = None
         L.orc_fgmres.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p,
-                                 C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int, C.c_int, C.c_double, _f64p, _f64p]
+                                 C.c_int, C.c_int, C.c_int, _f64p, _f64p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                 _f64p, _f64p]
         L.orc_ilu0_fixed_point.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, _f64p]
         L.orc_spmv.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p, _f64p]
         L.orc_spmv.restype = None
@@ -273,18 +274,25 @@ def gs_smooth(A, Gs, dinv, b, x0, outer: int, m: int, mixed: bool = False):
     return x
 
 
-def fgmres(A, Ls, Us, dinv, b, x0, m: int, max_iters: int, tol: float, outer: int = 1, mL: int = 3, mU: int = 3):
+def fgmres(A, Ls, Us, dinv, b, x0, m: int, max_iters: int, tol: float, outer: int = 1, mL: int = 3, mU: int = 3,
+           norm_a: float = 0.0):
     """FGMRES(m) with the ILU smoother (outer steps x m_L/m_U from z = 0) as right
-    preconditioner, stopped when the relative residual estimate drops below tol
-    (eq. relres).  Returns (steps, x, history of relative residual estimates)."""
+    preconditioner (Section 6).  Stops when the residual estimate over
+    (||b|| + norm_a ||x||) drops below tol: norm_a = 0 is the relative residual
+    of eq. relres, norm_a = ||A||_2 the norm-wise relative backward error of eq.
+    nbre (the iterate is formed after every step for its norm).  Returns
+    (steps, x, history of the estimates)."""
+    if not norm_a >= 0.0:
+        raise ValueError("norm_a must be >= 0")
     A, Ls, Us = _mat(A), _mat(Ls), _mat(Us)
     n = A.n
     x = np.array(x0, dtype=np.float64, copy=True)
-    ws = np.empty((2 * m + 7) * n + (m + 1) * (m + 4))
+    ws = np.empty((2 * m + 8) * n + (m + 1) * (m + 4))
     hist = np.zeros(max_iters + 1)
     k = lib().orc_fgmres(n, A.row_ptr, A.col, A.val, Ls.row_ptr, Ls.col, Ls.val, Us.row_ptr, Us.col, Us.val,
                          np.ascontiguousarray(dinv, np.float64), int(outer), int(mL), int(mU),
-                         np.ascontiguousarray(b, np.float64), x, int(m), int(max_iters), float(tol), hist, ws)
+                         np.ascontiguousarray(b, np.float64), x, int(m), int(max_iters), float(tol), float(norm_a),
+                         hist, ws)
     return k, x, hist[: k + 1].copy()
 
 

@@ -92,3 +92,62 @@ def test_initial_guess_already_converged(orc):
     b = A.to_dense() @ xs
     steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, xs, m=10, max_iters=10, tol=1e-8)
     assert steps == 0 and np.array_equal(x, xs)
+
+
+# ---- the norm-wise relative backward error as the stopping rule (eq. nbre) ----
+
+def _nrbe(Ad, b, x, norm_a):
+    return np.linalg.norm(b - Ad @ x) / (np.linalg.norm(b) + norm_a * np.linalg.norm(x))
+
+
+@pytest.mark.parametrize("k,m", [(1, 30), (4, 30), (7, 3)])
+def test_nrbe_history_is_the_backward_error_of_the_iterate(orc, k, m):
+    """After k steps (with a restart inside when m = 3) the estimate equals the
+    NRBE of the returned iterate computed from its definition, with ||A||_2 from
+    the dense SVD: a mistake in the denominator (||x0|| for ||x_k||, a missing
+    ||b||, a squared norm) moves it far from that."""
+    A = W.vardens7(6, seed_rho=3)
+    Ls, Us, dinv = _factors(orc, A, "iluk", k=1)
+    Ad = A.to_dense()
+    na = np.linalg.norm(Ad, 2)
+    b, x0 = W.rhs(A.n, 1), W.rhs(A.n, 2)
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, x0, m=m, max_iters=k, tol=1e-300, norm_a=na)
+    assert steps == k
+    assert hist[0] == pytest.approx(_nrbe(Ad, b, x0, na), rel=1e-12)
+    assert hist[k] == pytest.approx(_nrbe(Ad, b, x, na), rel=1e-6)
+    # the relative-residual run takes the same iterates
+    steps_r, x_r, hist_r = orc.fgmres(A, Ls, Us, dinv, b, x0, m=m, max_iters=k, tol=1e-300)
+    np.testing.assert_array_equal(x_r, x)
+    nb = np.linalg.norm(b)
+    assert hist_r[k] == pytest.approx(hist[k] * (nb + na * np.linalg.norm(x)) / nb, rel=1e-6)
+
+
+def test_nrbe_stops_at_the_first_step_below_tol(orc):
+    """On a variable-density operator (||A|| ||x|| >> ||b||) the backward error
+    reaches tol many steps before the relative residual does; the run stops
+    at the first step whose estimate is below tol, and the iterate's NRBE from
+    the definition is below tol there."""
+    A = W.vardens7(8, seed_rho=3)
+    Ls, Us, dinv = _factors(orc, A, "iluk", k=1)
+    Ad = A.to_dense()
+    na = np.linalg.norm(Ad, 2)
+    b = W.rhs(A.n, 0)
+    tol = 1e-10
+    steps, x, hist = orc.fgmres(A, Ls, Us, dinv, b, np.zeros(A.n), m=30, max_iters=400, tol=tol, norm_a=na)
+    assert 0 < steps < 400
+    assert hist[-1] < tol and np.all(hist[:-1] >= tol)
+    assert _nrbe(Ad, b, x, na) < tol * 1.01
+    steps_r, _, hist_r = orc.fgmres(A, Ls, Us, dinv, b, np.zeros(A.n), m=30, max_iters=400, tol=tol)
+    assert steps_r > steps
+    assert np.linalg.norm(b - Ad @ x) / np.linalg.norm(b) > tol
+
+
+def test_nrbe_zero_rhs_and_zero_guess_is_converged(orc):
+    A = W.poisson7(3)
+    Ls, Us, dinv = _factors(orc, A)
+    z = np.zeros(A.n)
+    for na in (0.0, 2.0):
+        steps, x, hist = orc.fgmres(A, Ls, Us, dinv, z, z, m=5, max_iters=5, tol=1e-8, norm_a=na)
+        assert steps == 0 and not np.any(x)
+    with pytest.raises(ValueError):
+        orc.fgmres(A, Ls, Us, dinv, z, z, m=5, max_iters=5, tol=1e-8, norm_a=-1.0)
