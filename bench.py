@@ -440,27 +440,31 @@ def main():
         Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(n, n))
         bh = bvec.cpu().numpy()
         norm_a = ctx.norm2_estimate(Ad, iters=50)
-        krylov = {"restart": 30, "tol": 1e-8, "precond": "1 outer x 4/4 ILU smoother", "norm2_A_estimate": norm_a}
+        krylov = {"restart": 30, "tol_relres": 1e-8, "tol_nrbe": 1e-12, "precond": "1 outer x 4/4 ILU smoother",
+                  "norm2_A_estimate": norm_a}
         use_reorder = args.reorder or (args.workload == "perm256" and not args.no_reorder)
-        runs = [("fp64", False, False), ("mixed", True, False)]
+        # (label, FP32-inner, relabeled, stopping rule): eq. relres to 1e-8, or eq. nbre to 1e-12
+        runs = [("fp64", False, False, None), ("mixed", True, False, None), ("fp64_nrbe", False, False, norm_a)]
         if use_reorder:
-            runs += [("fp64_reorder", False, True), ("mixed_reorder", True, True)]
-        for label, mixed, ro in runs:
+            runs += [("fp64_reorder", False, True, None), ("mixed_reorder", True, True, None)]
+        for label, mixed, ro, na in runs:
+            tol = 1e-8 if na is None else 1e-12
             x.zero_()
-            ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=5, tol=1e-8, outer=1, m_L=4, m_U=4, mixed=mixed,
-                       reorder=ro)
+            ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=5, tol=tol, outer=1, m_L=4, m_U=4, mixed=mixed,
+                       reorder=ro, norm_a=na)
             x.zero_()
             torch.cuda.synchronize()
             with gc_paused():
                 t0 = time.perf_counter()
-                steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=1e-8, outer=1, m_L=4,
-                                         m_U=4, mixed=mixed, reorder=ro)
+                steps, hist = ctx.fgmres(Ad, F, bvec, x, restart=30, max_iters=500, tol=tol, outer=1, m_L=4,
+                                         m_U=4, mixed=mixed, reorder=ro, norm_a=na)
                 torch.cuda.synchronize()
                 secs = time.perf_counter() - t0
             relres = float(np.linalg.norm(bh - Ah @ x.cpu().numpy()) / np.linalg.norm(bh))
             nrbe = ctx.nrbe(Ad, bvec, x, norm_a)
             log(f"fgmres {label}: {steps} steps, {secs * 1e3:.1f} ms, true relres {relres:.2e}, NRBE {nrbe:.2e}")
-            krylov[label] = {"steps": steps, "seconds": secs, "ms_per_step": secs * 1e3 / max(steps, 1),
+            krylov[label] = {"steps": steps, "seconds": secs, "ms_per_step": secs * 1e3 / max(steps, 1), "tol": tol,
+                             "stop": "relres" if na is None else "nrbe",
                              "relres": relres, "nrbe": nrbe, "estimate_history_every_5": hist[::5].tolist()}
         del Ah
 

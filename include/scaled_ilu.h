@@ -379,11 +379,51 @@ int silu_fgmres(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const d
                 int max_iters, double tol, int outer, int m_L, int m_U, int flags, void *ws, size_t ws_bytes,
                 int *iters, double *hist);
 
+/*
+ * silu_fgmres stopped on the norm-wise relative backward error instead (eq.
+ * nbre, the alternative that the numerical results of Section 6 set beside
+ * eq. relres): it stops when |g_{j+1}| / (||b|| + norm_a ||x_j||) falls below
+ * tol, x_j being the iterate that the first j steps define, and hist receives
+ * these estimates.  norm_a: ||A||_2 or an estimate of it (silu_norm2_estimate),
+ * >= 0 and finite; 0 gives exactly silu_fgmres.  ||x_j|| comes from the Gram
+ * matrix of the preconditioned directions, kept up to date with j + 2 more dot
+ * products per step: ||x_j||^2 = ||x_0||^2 + 2 y.(Z^T x_0) + y^T (Z^T Z) y
+ * (taken as 0 should rounding make it negative, which only delays the stop).
+ * Same arguments, workspace and errors as silu_fgmres, and ARG for a bad norm_a.
+ */
+int silu_fgmres_nrbe(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                     int restart, int max_iters, double tol, double norm_a, int outer, int m_L, int m_U, int flags,
+                     void *ws, size_t ws_bytes, int *iters, double *hist);
+
 /* y = A x (FP64, the sweep kernels' layout and row order).  Asynchronous. */
 int silu_spmv(silu_ctx *ctx, const silu_csr *A, const double *x, double *y, int flags);
 /* *result = a . b over n entries, reduced in the fixed order of the Krylov
  * solver; ws: device scratch of at least 8200 bytes.  Synchronous. */
 int silu_dot(silu_ctx *ctx, int64_t n, const double *a, const double *b, double *result, void *ws, size_t ws_bytes);
+
+/* Device scratch for silu_norm2_estimate and silu_nrbe: two n-vectors (8 n
+ * bytes each, rounded up to 256) and 8448 bytes for the dot products. */
+int silu_aux_workspace_size(int64_t n, size_t *bytes);
+/*
+ * Power-iteration estimate of ||A||_2 for the NRBE of eq. nbre: v = v0 /
+ * ||v0||, then `iters` times lam = ||A v||, v = A v / lam (stopping early if
+ * lam = 0).  *result = the last lam: ||A||_2 for a symmetric A as the iteration
+ * converges, a lower bound in general.  v0: device FP64 [n], nonzero (the
+ * caller's random start; not modified).  ws: device scratch of at least
+ * silu_aux_workspace_size(n) bytes, 256-byte aligned.  Synchronous.  Errors:
+ * ARG (null pointer, iters < 1, v0 zero or not finite), SHAPE, NOMEM.
+ */
+int silu_norm2_estimate(silu_ctx *ctx, const silu_csr *A, const double *v0, int iters, double *result, void *ws,
+                        size_t ws_bytes);
+/*
+ * Norm-wise relative backward error (eq. nbre) of x as a solution of A x = b:
+ * *result = ||b - A x|| / (||b|| + norm_a ||x||), the residual formed by the
+ * sweep kernel and the norms by the fixed-order dot product.  b, x: device
+ * FP64 [n].  norm_a >= 0, finite.  ws: as for silu_norm2_estimate.
+ * Synchronous.  Errors: ARG, SHAPE, NOMEM.
+ */
+int silu_nrbe(silu_ctx *ctx, const silu_csr *A, const double *b, const double *x, double norm_a, double *result,
+              void *ws, size_t ws_bytes);
 
 /* ---- triangular solves ------------------------------------------------- */
 

@@ -95,6 +95,12 @@ _sig = {
     "silu_fgmres": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
                               C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_size_t, C.POINTER(C.c_int),
                               C.POINTER(C.c_double)]),
+    "silu_fgmres_nrbe": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int,
+                                   C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int, _P, C.c_size_t,
+                                   C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "silu_aux_workspace_size": (C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
+    "silu_norm2_estimate": (C.c_int, [_P, C.POINTER(silu_csr), _P, C.c_int, C.POINTER(C.c_double), _P, C.c_size_t]),
+    "silu_nrbe": (C.c_int, [_P, C.POINTER(silu_csr), _P, _P, C.c_double, C.POINTER(C.c_double), _P, C.c_size_t]),
     "silu_spmv": (C.c_int, [_P, C.POINTER(silu_csr), _P, _P, C.c_int]),
     "silu_dot": (C.c_int, [_P, C.c_int64, _P, _P, C.POINTER(C.c_double), _P, C.c_size_t]),
     "ilu_smooth": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), _P, _P, C.c_int, C.c_int, C.c_int,
@@ -343,9 +349,12 @@ class Context:
     # ---- Krylov solver around the smoother ----
     def fgmres(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, restart: int = 30, max_iters: int = 300,
                tol: float = 1e-8, outer: int = 1, m_L: int = 3, m_U: int = 3, mixed: bool = False,
-               kernel: str | None = None, check_finite: bool = False, reorder: bool = False):
+               kernel: str | None = None, check_finite: bool = False, reorder: bool = False,
+               norm_a: float | None = None):
         """FGMRES(restart) with the smoother as right preconditioner, in place on x.
-        Returns (steps, history of relative residual estimates)."""
+        Stops on the relative residual (eq. relres), or, given norm_a = ||A||_2 (or
+        its estimate), on the norm-wise relative backward error (eq. nbre).
+        Returns (steps, history of the estimates)."""
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         flags = ((SILU_MIXED if mixed else 0) | (SILU_CHECK_FINITE if check_finite else 0) |
@@ -359,10 +368,15 @@ class Context:
         it = C.c_int()
         self._track(A, F.Ls, F.Us, values=((), (F.Ls_val32,), (F.Us_val32,)))
         Ac, Fc = A.c(), F.c()
-        self._check(_lib.silu_fgmres(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
-                                     C.c_void_p(x.data_ptr()), restart, max_iters, tol, outer, m_L, m_U, flags,
-                                     C.c_void_p(self._kws.data_ptr()), self._kws.numel(), C.byref(it),
-                                     hist.ctypes.data_as(C.POINTER(C.c_double))), "silu_fgmres")
+        tail = (outer, m_L, m_U, flags, C.c_void_p(self._kws.data_ptr()), self._kws.numel(), C.byref(it),
+                hist.ctypes.data_as(C.POINTER(C.c_double)))
+        if norm_a is None:
+            self._check(_lib.silu_fgmres(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
+                                         C.c_void_p(x.data_ptr()), restart, max_iters, tol, *tail), "silu_fgmres")
+        else:
+            self._check(_lib.silu_fgmres_nrbe(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
+                                              C.c_void_p(x.data_ptr()), restart, max_iters, tol, float(norm_a),
+                                              *tail), "silu_fgmres_nrbe")
         return it.value, hist[: it.value + 1].copy()
 
     def spmv(self, A: Csr, xin: torch.Tensor, y: torch.Tensor | None = None, kernel: str | None = None):
@@ -383,25 +397,36 @@ class Context:
                                   C.byref(out), C.c_void_p(self._dws.data_ptr()), self._dws.numel()), "silu_dot")
         return out.value
 
+    def _aux_ws(self, n: int) -> torch.Tensor:
+        nb = C.c_size_t()
+        self._check(_lib.silu_aux_workspace_size(n, C.byref(nb)), "silu_aux_workspace_size")
+        if getattr(self, "_aws", None) is None or self._aws.numel() < nb.value:
+            self._aws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        return self._aws
+
     def norm2_estimate(self, A: Csr, iters: int = 30, seed: int = 0) -> float:
-        """Power-iteration estimate of the largest |eigenvalue| of A (= ||A||_2 for a
-        symmetric A; a lower bound on it otherwise), for the NRBE of eq. nbre."""
+        """Power-iteration estimate of ||A||_2 (exact in the limit for a symmetric
+        A, a lower bound otherwise), for the NRBE of eq. nbre; the random start
+        vector is drawn here from `seed`."""
         g = torch.Generator(device="cpu").manual_seed(seed)
-        v = (torch.rand(A.n, generator=g, dtype=torch.float64) - 0.5).cuda()
-        v /= self.dot(v, v) ** 0.5
-        lam = 0.0
-        for _ in range(iters):
-            w = self.spmv(A, v)
-            lam = self.dot(w, w) ** 0.5
-            if lam == 0.0:
-                break
-            v = w / lam
-        return lam
+        v0 = (torch.rand(A.n, generator=g, dtype=torch.float64) - 0.5).cuda()
+        ws = self._aux_ws(A.n)
+        self._track(A)
+        Ac, out = A.c(), C.c_double()
+        self._check(_lib.silu_norm2_estimate(self._h, C.byref(Ac), C.c_void_p(v0.data_ptr()), iters, C.byref(out),
+                                             C.c_void_p(ws.data_ptr()), ws.numel()), "silu_norm2_estimate")
+        return out.value
 
     def nrbe(self, A: Csr, b: torch.Tensor, x: torch.Tensor, norm_a: float) -> float:
         """Norm-wise relative backward error ||b - A x|| / (||b|| + ||A|| ||x||) (eq. nbre)."""
-        r = b - self.spmv(A, x)
-        return self.dot(r, r) ** 0.5 / (self.dot(b, b) ** 0.5 + norm_a * self.dot(x, x) ** 0.5)
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        ws = self._aux_ws(A.n)
+        self._track(A)
+        Ac, out = A.c(), C.c_double()
+        self._check(_lib.silu_nrbe(self._h, C.byref(Ac), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                   float(norm_a), C.byref(out), C.c_void_p(ws.data_ptr()), ws.numel()), "silu_nrbe")
+        return out.value
 
     # ---- polynomial Gauss-Seidel ----
     def gs_split(self, A: Csr, fp32: bool = False, validate: bool = False) -> Factors:

@@ -1551,13 +1551,14 @@ struct KrylovWs {
     void *smoother() const { return base + vec * (size_t)(2 * m + 2); }                 // ss slots
     double *part() const { return (double *)(base + vec * (size_t)(2 * m + 2 + ss)); } // DOT_BLOCKS
     double *h() const { return part() + DOT_BLOCKS; }                                    // m + 2 scalars
+    double *gram() const { return h() + m + 2; }                                         // m + 2 scalars
 };
 
 size_t krylov_ws_bytes(int64_t n, int m, int flags)
 {
     const size_t vec = ws_vec_bytes(n);
-    return vec * (size_t)(2 * m + 2 + smoother_slots(flags)) + ((size_t)DOT_BLOCKS + (size_t)m + 2) * sizeof(double) +
-           256;
+    return vec * (size_t)(2 * m + 2 + smoother_slots(flags)) +
+           ((size_t)DOT_BLOCKS + 2 * ((size_t)m + 2)) * sizeof(double) + 256;
 }
 
 } // namespace
@@ -1569,9 +1570,13 @@ int silu_fgmres_workspace_size(silu_ctx *c, int64_t n, int restart, int flags, s
     return SILU_OK;
 }
 
-int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x, int restart,
-                int max_iters, double tol, int outer, int m_L, int m_U, int flags, void *ws, size_t ws_bytes,
-                int *iters, double *hist)
+namespace {
+
+// FGMRES(restart) stopped when |g_{j+1}| / (||b|| + norm_a ||x_j||) < tol:
+// norm_a = 0 is eq. relres, norm_a = ||A||_2 eq. nbre.
+int fgmres_impl(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x, int restart,
+                int max_iters, double tol, double norm_a, int outer, int m_L, int m_U, int flags, void *ws,
+                size_t ws_bytes, int *iters, double *hist)
 {
     if (!c || !A || !F || !b || !x || !ws || !iters) return SILU_ERR_ARG;
     c->bad_row = -1;
@@ -1603,16 +1608,28 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     };
     std::vector<double> H((size_t)(m + 1) * (size_t)m), cs((size_t)m), sn((size_t)m), g((size_t)m + 1),
         y((size_t)m), hcol((size_t)m + 2);
-    double nb = 0.0, beta = 0.0;
+    // eq. nbre: ||x_j||^2 = ||x_0||^2 + 2 y.c + y^T G y with G = Z^T Z, c = Z^T x_0
+    const bool nrbe = norm_a > 0.0;
+    std::vector<double> G(nrbe ? (size_t)m * (size_t)m : 0), cz(nrbe ? (size_t)m : 0), yt(nrbe ? (size_t)m : 0),
+        grow(nrbe ? (size_t)m + 2 : 0);
+    double nb = 0.0, beta = 0.0, xx0 = 0.0;
+    auto norm_x0 = [&]() -> int { // ||x||^2 of the cycle's start
+        int e;
+        if (!nrbe) return SILU_OK;
+        if ((e = dot(x, x, K.gram(), false))) return e;
+        return fetch(&xx0, K.gram(), 1);
+    };
     // ||b|| and the first residual
     if ((st = dot(b, b, K.h(), true))) return st;
     if ((st = fetch(&nb, K.h(), 1))) return st;
     if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, K.V(0), nullptr, nullptr, nullptr))) return st;
     if ((st = dot(K.V(0), K.V(0), K.h(), true))) return st;
     if ((st = fetch(&beta, K.h(), 1))) return st;
+    if ((st = norm_x0())) return st;
     int k = 0;
-    if (hist) hist[0] = beta / nb;
-    if (!(beta / nb >= tol)) { // converged (or b = 0)
+    const double est0 = beta / (nb + norm_a * std::sqrt(xx0));
+    if (hist) hist[0] = est0;
+    if (!(est0 >= tol)) { // converged (or b = 0 and x = 0)
         *iters = 0;
         return SILU_OK;
     }
@@ -1627,6 +1644,13 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             // z_j = M^{-1} v_j: one smoother call from z = 0
             HIPCHK(c, launch_fill((int)n, zj, 0.0, nullptr, 0.0, c->stream));
             if ((st = ilu_smooth2(c, A, F, K.V(j), zj, outer, m_L, m_U, pflags, K.smoother(), sws_bytes))) return st;
+            if (nrbe) { // row j of G and c_j, fetched with the Hessenberg column
+                for (int i = 0; i <= j; i++)
+                    if ((st = dot(zj, K.Z(i), K.gram() + i, false))) return st;
+                if ((st = dot(zj, x, K.gram() + j + 1, false))) return st;
+                HIPCHK(c, hipMemcpyAsync(grow.data(), K.gram(), sizeof(double) * (size_t)(j + 2),
+                                         hipMemcpyDeviceToHost, c->stream));
+            }
             // w = A z_j, then modified Gram-Schmidt against v_0..v_j
             if ((st = sweep(c, Prec::F64, gA, A, A->val, zj, nullptr, EPI_SPMV, w, nullptr, nullptr, nullptr)))
                 return st;
@@ -1657,7 +1681,28 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
             g[(size_t)j + 1] = -sn[(size_t)j] * g[(size_t)j];
             g[(size_t)j] = cs[(size_t)j] * g[(size_t)j];
             k++;
-            const double est = std::fabs(g[(size_t)j + 1]) / nb;
+            double xn = 0.0;
+            if (nrbe) {
+                for (int i = 0; i <= j; i++) {
+                    G[(size_t)j * (size_t)m + (size_t)i] = grow[(size_t)i];
+                    G[(size_t)i * (size_t)m + (size_t)j] = grow[(size_t)i];
+                }
+                cz[(size_t)j] = grow[(size_t)j + 1];
+                // y of the first j + 1 steps (back substitution), then the quadratic form
+                for (int i = j; i >= 0; i--) {
+                    double t = g[(size_t)i];
+                    for (int c2 = i + 1; c2 <= j; c2++) t -= H[(size_t)i + (size_t)(m + 1) * (size_t)c2] * yt[(size_t)c2];
+                    yt[(size_t)i] = t / H[(size_t)i + (size_t)(m + 1) * (size_t)i];
+                }
+                double q = xx0;
+                for (int i = 0; i <= j; i++) {
+                    double gi = 0.0;
+                    for (int l = 0; l <= j; l++) gi += G[(size_t)i * (size_t)m + (size_t)l] * yt[(size_t)l];
+                    q += yt[(size_t)i] * (2.0 * cz[(size_t)i] + gi);
+                }
+                xn = std::sqrt(std::max(q, 0.0));
+            }
+            const double est = std::fabs(g[(size_t)j + 1]) / (nb + norm_a * xn);
             if (hist) hist[k] = est;
             if (est < tol || den == 0.0) {
                 done = true;
@@ -1676,11 +1721,31 @@ int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
         if ((st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, K.V(0), nullptr, nullptr, nullptr))) return st;
         if ((st = dot(K.V(0), K.V(0), K.h(), true))) return st;
         if ((st = fetch(&beta, K.h(), 1))) return st;
+        if ((st = norm_x0())) return st;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *iters = k;
     if (flags & SILU_CHECK_FINITE) return check_finite(c, n, x);
     return SILU_OK;
+}
+
+} // namespace
+
+int silu_fgmres(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x, int restart,
+                int max_iters, double tol, int outer, int m_L, int m_U, int flags, void *ws, size_t ws_bytes,
+                int *iters, double *hist)
+{
+    return fgmres_impl(c, A, F, b, x, restart, max_iters, tol, 0.0, outer, m_L, m_U, flags, ws, ws_bytes, iters,
+                       hist);
+}
+
+int silu_fgmres_nrbe(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                     int restart, int max_iters, double tol, double norm_a, int outer, int m_L, int m_U, int flags,
+                     void *ws, size_t ws_bytes, int *iters, double *hist)
+{
+    if (!(norm_a >= 0.0) || !std::isfinite(norm_a)) return SILU_ERR_ARG;
+    return fgmres_impl(c, A, F, b, x, restart, max_iters, tol, norm_a, outer, m_L, m_U, flags, ws, ws_bytes, iters,
+                       hist);
 }
 
 int silu_spmv(silu_ctx *c, const silu_csr *A, const double *xin, double *y, int flags)
@@ -1704,6 +1769,91 @@ int silu_dot(silu_ctx *c, int64_t n, const double *a, const double *b, double *r
     HIPCHK(c, launch_dot(n, a, b, part, out, false, c->stream));
     HIPCHK(c, hipMemcpyAsync(result, out, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SILU_OK;
+}
+
+int silu_aux_workspace_size(int64_t n, size_t *bytes)
+{
+    if (!bytes || n < 0) return SILU_ERR_ARG;
+    *bytes = 2 * ws_vec_bytes(n) + (DOT_BLOCKS + 32) * sizeof(double);
+    return SILU_OK;
+}
+
+namespace {
+
+struct AuxWs {
+    double *v, *w, *part, *s; // two n-vectors, the dot partials, 8 scalars
+};
+
+int aux_ws(int64_t n, void *ws, size_t ws_bytes, AuxWs *a)
+{
+    size_t need = 0;
+    silu_aux_workspace_size(n, &need);
+    if (((uintptr_t)ws & 255) != 0) return SILU_ERR_ARG;
+    if (ws_bytes < need) return SILU_ERR_NOMEM;
+    const size_t vec = ws_vec_bytes(n);
+    a->v = (double *)ws;
+    a->w = (double *)((char *)ws + vec);
+    a->part = (double *)((char *)ws + 2 * vec);
+    a->s = a->part + DOT_BLOCKS;
+    return SILU_OK;
+}
+
+} // namespace
+
+int silu_norm2_estimate(silu_ctx *c, const silu_csr *A, const double *v0, int iters, double *result, void *ws,
+                        size_t ws_bytes)
+{
+    if (!c || !A || !v0 || !result || !ws || iters < 1) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    const int64_t n = A->n_rows;
+    AuxWs a;
+    if ((st = aux_ws(n, ws, ws_bytes, &a))) return st;
+    const SweepGeom gA = pick_geom(n, A->nnz, 0);
+    double nv = 0.0, lam = 0.0;
+    auto norm = [&](const double *u, double *out) -> int {
+        HIPCHK(c, launch_dot(n, u, u, a.part, a.s, true, c->stream));
+        HIPCHK(c, hipMemcpyAsync(out, a.s, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SILU_OK;
+    };
+    if ((st = norm(v0, &nv))) return st;
+    if (!(nv > 0.0) || !std::isfinite(nv)) return SILU_ERR_ARG;
+    HIPCHK(c, launch_div_host(n, v0, nv, a.v, c->stream));
+    // power iteration: lam = ||A v||, v = A v / lam
+    for (int it = 0; it < iters; it++) {
+        if ((st = sweep(c, Prec::F64, gA, A, A->val, a.v, nullptr, EPI_SPMV, a.w, nullptr, nullptr, nullptr)))
+            return st;
+        if ((st = norm(a.w, &lam))) return st;
+        if (lam == 0.0) break;
+        HIPCHK(c, launch_div_host(n, a.w, lam, a.v, c->stream));
+    }
+    *result = lam;
+    return SILU_OK;
+}
+
+int silu_nrbe(silu_ctx *c, const silu_csr *A, const double *b, const double *x, double norm_a, double *result,
+              void *ws, size_t ws_bytes)
+{
+    if (!c || !A || !b || !x || !result || !ws || !(norm_a >= 0.0) || !std::isfinite(norm_a)) return SILU_ERR_ARG;
+    c->bad_row = -1;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    const int64_t n = A->n_rows;
+    AuxWs a;
+    if ((st = aux_ws(n, ws, ws_bytes, &a))) return st;
+    if ((st = sweep(c, Prec::F64, pick_geom(n, A->nnz, 0), A, A->val, x, b, EPI_STORE, a.v, nullptr, nullptr,
+                    nullptr)))
+        return st;
+    HIPCHK(c, launch_dot(n, a.v, a.v, a.part, a.s, true, c->stream));
+    HIPCHK(c, launch_dot(n, b, b, a.part, a.s + 1, true, c->stream));
+    HIPCHK(c, launch_dot(n, x, x, a.part, a.s + 2, true, c->stream));
+    double h[3];
+    HIPCHK(c, hipMemcpyAsync(h, a.s, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *result = h[0] / (h[1] + norm_a * h[2]);
     return SILU_OK;
 }
 

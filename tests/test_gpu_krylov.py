@@ -167,3 +167,102 @@ def test_fgmres_with_relabeled_preconditioner(ctx, cases, name, mixed):
     assert k1 == k2
     np.testing.assert_array_equal(h1, h2)
     np.testing.assert_array_equal(host(x1), host(x2))
+
+
+# ---- FGMRES stopped on the norm-wise relative backward error (eq. nbre) ----
+
+def _norm2_host(A):
+    """||A||_2 on the host (largest singular value, ARPACK from a fixed start)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+
+    Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    return float(sla.svds(Ah, k=1, v0=np.ones(A.n), return_singular_vectors=False)[0])
+
+
+@pytest.mark.parametrize("restart", [30, 8])
+@pytest.mark.parametrize("name", list(SMALL))
+def test_fgmres_nrbe_matches_oracle(orc, ctx, cases, name, restart):
+    """Same steps, estimates and solution as the oracle, whose ||x_j|| comes from
+    the iterate formed after every step (the library's from the Gram matrix of
+    the directions).  tol = 1e-12: every estimate of these runs is at least 7%
+    away from it, far more than the two sides' rounding differences."""
+    say("fgmres nrbe", name, restart)
+    c = cases[name]
+    na = _norm2_host(c.A)
+    b = W.rhs(c.A.n, 0)
+    x0 = W.rhs(c.A.n, 3) * 0.01
+    k_ref, x_ref, h_ref = orc.fgmres(c.A, c.Ls, c.Us, c.dinv, b, x0, m=restart, max_iters=400, tol=1e-12,
+                                     norm_a=na)
+    assert 0 < k_ref < 400
+    x = dev(x0)
+    k, hist = ctx.fgmres(c.Ad, c.F, dev(b), x, restart=restart, max_iters=400, tol=1e-12, norm_a=na)
+    assert k == k_ref, f"{name}: GPU {k} steps, oracle {k_ref}"
+    # the Arnoldi residual |g_j| carries an absolute rounding error of order
+    # eps ||r_0|| on either side (not one relative to |g_j|), which matters once
+    # the estimates fall four decades below those of the relres runs: hence
+    # the absolute term, 1e-15 of the first estimate
+    np.testing.assert_allclose(hist, h_ref, rtol=1e-6, atol=1e-15 * h_ref[0])
+    assert_close(host(x), x_ref, 1e-7, f"fgmres nrbe {name}")
+    xh = host(x)
+    true = np.linalg.norm(orc.residual(c.A, b, xh)) / (np.linalg.norm(b) + na * np.linalg.norm(xh))
+    assert true < 1.01e-12
+
+
+def test_fgmres_nrbe_with_zero_norm_is_fgmres(ctx, cases):
+    """norm_a = 0 turns eq. nbre into eq. relres: the same run bit for bit."""
+    c = cases["vardens13_ilu1"]
+    b = dev(W.rhs(c.A.n, 1))
+    x1, x2 = torch.zeros_like(b), torch.zeros_like(b)
+    k1, h1 = ctx.fgmres(c.Ad, c.F, b, x1, restart=8, max_iters=50, tol=1e-9)
+    k2, h2 = ctx.fgmres(c.Ad, c.F, b, x2, restart=8, max_iters=50, tol=1e-9, norm_a=0.0)
+    assert k1 == k2
+    np.testing.assert_array_equal(h1, h2)
+    np.testing.assert_array_equal(host(x1), host(x2))
+
+
+def test_norm2_estimate_follows_its_definition(B, ctx, cases):
+    """The power iteration of silu_norm2_estimate from the binding's start
+    vector, repeated on the host with the same start: same value to rounding
+    (a non-symmetric operator, so it is not ||A||_2 itself)."""
+    import scipy.sparse as sp
+
+    c = cases["perm9"]
+    A = c.A
+    Ah = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    g = torch.Generator(device="cpu").manual_seed(4)
+    v = (torch.rand(A.n, generator=g, dtype=torch.float64) - 0.5).numpy()
+    v = v / np.linalg.norm(v)
+    lam = 0.0
+    for _ in range(7):
+        w = Ah @ v
+        lam = np.linalg.norm(w)
+        v = w / lam
+    assert ctx.norm2_estimate(c.Ad, iters=7, seed=4) == pytest.approx(lam, rel=1e-12)
+
+
+def test_nrbe_and_norm_errors(B, ctx, cases):
+    import ctypes as C
+
+    c = cases["poisson17"]
+    b = dev(W.rhs(c.A.n, 0))
+    with pytest.raises(B.SiluError) as e:
+        ctx.nrbe(c.Ad, b, b.clone(), -1.0)
+    assert e.value.status == -1
+    with pytest.raises(B.SiluError) as e:
+        ctx.fgmres(c.Ad, c.F, b, torch.zeros_like(b), norm_a=float("inf"))
+    assert e.value.status == -1
+    with pytest.raises(B.SiluError) as e:
+        ctx.norm2_estimate(c.Ad, iters=0)
+    assert e.value.status == -1
+    # a zero start vector has no direction
+    ws = ctx._aux_ws(c.A.n)
+    z = torch.zeros_like(b)
+    out = C.c_double()
+    Ac = c.Ad.c()
+    st = B._lib.silu_norm2_estimate(ctx._h, C.byref(Ac), C.c_void_p(z.data_ptr()), 5, C.byref(out),
+                                    C.c_void_p(ws.data_ptr()), ws.numel())
+    assert st == -1
+    st = B._lib.silu_nrbe(ctx._h, C.byref(Ac), C.c_void_p(b.data_ptr()), C.c_void_p(b.data_ptr()), 1.0,
+                          C.byref(out), C.c_void_p(ws.data_ptr()), 100)
+    assert st == -6  # workspace too small (SILU_ERR_NOMEM)
