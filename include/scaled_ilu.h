@@ -366,8 +366,11 @@ int silu_ilu0_fixed_point(silu_ctx *ctx, const silu_csr *A, int sweeps, silu_csr
  * a host array of max_iters + 1 doubles receiving the relative residual
  * estimates (hist[0] for the initial x).  Dot products reduce in a fixed order
  * (reproducible; not the sequential order).  flags: SILU_MIXED, SILU_REORDER
- * (the preconditioner sweeps relabeled copies; same iterates bit for bit),
- * the kernel choices, SILU_VALIDATE; SILU_GRAPH is ignored.  ws: at least
+ * (the whole solve runs on the relabeled copies of A and the factors: b and x
+ * are permuted in once and x out once, so the products with A gather locally
+ * too; the iterates equal those of the given order up to rounding, since the
+ * dot products then sum in the relabeled order), the kernel choices,
+ * SILU_VALIDATE; SILU_GRAPH is ignored.  ws: at least
  * silu_fgmres_workspace_size(ctx, n, restart, flags) bytes (2 restart + 6
  * n-vectors, 2 more with SILU_REORDER, and a few KB), 256-byte aligned.  Synchronous (the small
  * least-squares problem is solved on the host every step).  Errors: ARG,

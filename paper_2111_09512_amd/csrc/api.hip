@@ -748,6 +748,20 @@ int get_reorder(silu_ctx *c, const silu_csr *A, const silu_factors *F, Reorder *
     return SILU_OK;
 }
 
+// The factors of F with every array replaced by its relabeled copy.
+silu_factors relabeled_factors(const silu_factors *F, const Reorder *R)
+{
+    silu_factors F2 = *F;
+    F2.Ls = R->L2;
+    F2.Us = R->U2;
+    F2.dinv = R->dinv2;
+    if (F->scaled == 0) F2.d = R->aux2;
+    if (F->scaled == 2) F2.dc = R->aux2;
+    F2.Ls_val32 = R->L32;
+    F2.Us_val32 = R->U32;
+    return F2;
+}
+
 // ---- level analysis (Section 4: level-set scheduling) ----------------------
 int get_levels(silu_ctx *c, const silu_csr *T, int uplo, LevelInfo **out)
 {
@@ -1127,14 +1141,7 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
                 return launch_fill((int)n, x2, 0.0, nullptr, 0.0, c->stream);
             });
         if (st) return st;
-        silu_factors F2 = *F;
-        F2.Ls = R->L2;
-        F2.Us = R->U2;
-        F2.dinv = R->dinv2;
-        if (F->scaled == 0) F2.d = R->aux2;
-        if (F->scaled == 2) F2.dc = R->aux2;
-        F2.Ls_val32 = R->L32;
-        F2.Us_val32 = R->U32;
+        const silu_factors F2 = relabeled_factors(F, R);
         const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
         if ((st = smooth_plain(c, &R->A2, &F2, b2, x2, outer_sweeps, m_L, m_U, inner, ws, ws_bytes))) return st;
         st = timed_launch(c, vb, [&](const char **nm) {
@@ -1408,11 +1415,7 @@ int gs_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *G, const doubl
             return launch_permute_in((int)n, R->pos, b, x, b2, x2, c->stream);
         });
         if (st) return st;
-        silu_factors G2 = *G;
-        G2.Ls = R->L2;
-        G2.Us = R->U2;
-        G2.dinv = R->dinv2;
-        G2.Ls_val32 = R->L32;
+        const silu_factors G2 = relabeled_factors(G, R);
         const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
         if ((st = gs_smooth(c, &R->A2, &G2, b2, x2, outer_sweeps, terms, inner, ws, ws_bytes))) return st;
         st = timed_launch(c, 20.0 * (double)n, [&](const char **nm) {
@@ -1589,6 +1592,32 @@ int fgmres_impl(silu_ctx *c, const silu_csr *A, const silu_factors *F, const dou
     if (ws_bytes < krylov_ws_bytes(n, restart, flags)) return SILU_ERR_NOMEM;
     if (flags & SILU_VALIDATE) {
         if ((st = validate(c, A, 0))) return st;
+    }
+    if (flags & SILU_REORDER) {
+        // the whole solve on the relabeled copies: b and x in once, x out once,
+        // so the products with A and the sweeps gather locally (the two extra
+        // smoother slots hold the relabeled b and x)
+        Reorder *R = nullptr;
+        if ((st = get_reorder(c, A, F, &R))) return st;
+        const size_t vec = ws_vec_bytes(n);
+        double *b2 = (double *)ws, *x2 = (double *)((char *)ws + vec);
+        st = timed_launch(c, 36.0 * (double)n, [&](const char **nm) {
+            *nm = "reorder_in";
+            return launch_permute_in((int)n, R->pos, b, x, b2, x2, c->stream);
+        });
+        if (st) return st;
+        const silu_factors F2 = relabeled_factors(F, R);
+        const int inner = flags & ~(SILU_REORDER | SILU_CHECK_FINITE | SILU_VALIDATE);
+        if ((st = fgmres_impl(c, &R->A2, &F2, b2, x2, restart, max_iters, tol, norm_a, outer, m_L, m_U, inner,
+                              (char *)ws + 2 * vec, ws_bytes - 2 * vec, iters, hist)))
+            return st;
+        st = timed_launch(c, 20.0 * (double)n, [&](const char **nm) {
+            *nm = "reorder_out";
+            return launch_scatter((int)n, R->order, x2, x, c->stream);
+        });
+        if (st) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return (flags & SILU_CHECK_FINITE) ? check_finite(c, n, x) : SILU_OK;
     }
     const int m = restart;
     KrylovWs K{ws_vec_bytes(n), (char *)ws, m, smoother_slots(flags)};
