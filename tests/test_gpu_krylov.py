@@ -296,3 +296,30 @@ def test_nrbe_and_norm_errors(B, ctx, cases):
     st = B._lib.silu_nrbe(ctx._h, C.byref(Ac), C.c_void_p(b.data_ptr()), C.c_void_p(b.data_ptr()), 1.0,
                           C.byref(out), C.c_void_p(ws.data_ptr()), 100)
     assert st == -6  # workspace too small (SILU_ERR_NOMEM)
+
+
+@pytest.mark.parametrize("case", ["one_row", "restart1", "no_steps"])
+def test_fgmres_nrbe_edge_cases(orc, B, ctx, case):
+    """A 1 x 1 system (exact after one step, estimate 0), restart = 1 (every
+    step a restart, so ||x_0|| is refreshed each time) and max_iters = 0 (only
+    the initial estimate): against the oracle."""
+    if case == "one_row":
+        A, m, iters, bh = W.CSR.from_dense(np.array([[4.0]])), 1, 5, np.array([2.0])
+    else:
+        A = W.poisson7(5)
+        m, iters, bh = (1, 40, W.rhs(A.n, 0)) if case == "restart1" else (5, 0, W.rhs(A.n, 0))
+    Ls, U = orc.ilu0(A)
+    _, dinv, Us = orc.scale_rows(U)
+    F = ctx.ilu_scale_factors(B.Csr.from_host(Ls), B.Csr.from_host(U))
+    Ad = B.Csr.from_host(A)
+    na = 4.0 if case == "one_row" else _norm2_host(A)
+    x0 = np.zeros(A.n) if case == "one_row" else W.rhs(A.n, 2) * 0.01
+    k_ref, x_ref, h_ref = orc.fgmres(A, Ls, Us, dinv, bh, x0, m=m, max_iters=iters, tol=1e-12, norm_a=na)
+    x = dev(x0)
+    k, hist = ctx.fgmres(Ad, F, dev(bh), x, restart=m, max_iters=iters, tol=1e-12, norm_a=na)
+    assert k == k_ref
+    np.testing.assert_allclose(hist, h_ref, rtol=1e-6, atol=1e-15 * h_ref[0])
+    assert_close(host(x), x_ref, 1e-7, f"fgmres nrbe {case}")
+    if case == "one_row":
+        assert ctx.norm2_estimate(Ad, iters=3) == 4.0
+        assert ctx.nrbe(Ad, dev(bh), x, 4.0) == 0.0
