@@ -43,6 +43,11 @@ constexpr int DEFAULT_MAX_WG = 1024;
 // exit), with the dependency counters at agent scope and again at system
 // scope, for a cause not yet shown.  Until it is, set_mode refuses the mode.
 constexpr bool PERSISTENT_AVAILABLE = false;
+// Stepwise mode: an event at least every MARK_EVERY steps, and at most
+// MAX_AHEAD steps enqueued past the last step known complete, so that a newly
+// admitted request joins a launch within a few steps.
+constexpr int MARK_EVERY = 4;
+constexpr int MAX_AHEAD = 8;
 
 struct Matrix {
     silu_csr A;
@@ -91,7 +96,13 @@ struct silu_server {
     std::map<int64_t, std::pair<int64_t, int64_t>> times; // ticket -> (submitted, found done), steady ns
     int64_t next_ticket = 0, steps = 0, completed_through = -1;
     hipEvent_t ev[RING] = {};
-    int64_t done_step[RING];   // the step a slot last held, once the GPU has passed it
+    int64_t done_step[RING];   // persistent mode: the step a slot last held, once the GPU has passed it
+    // stepwise mode: events are recorded only at steps that need one (a request
+    // finishes, the op table was staged through host memory, or MARK_EVERY
+    // steps have passed), round-robin over ev[]; marks = (step, slot) recorded
+    // and not yet seen complete, in order
+    std::deque<std::pair<int64_t, int>> marks;
+    int64_t nmarks = 0, last_mark_step = -1;
     SweepArgs *h_ops[RING] = {};
     int32_t *h_first[RING] = {};
     SweepArgs *d_ops = nullptr;
@@ -162,7 +173,11 @@ bool step_done(const silu_server *s, int64_t k) { return k <= s->completed_throu
 // order): reclaim the workspace they held.
 void reap(silu_server *s)
 {
-    for (int64_t k = s->completed_through + 1; k < s->steps; k++) {
+    while (s->mode == 0 && !s->marks.empty() && hipEventQuery(s->ev[s->marks.front().second]) == hipSuccess) {
+        s->completed_through = std::max(s->completed_through, s->marks.front().first);
+        s->marks.pop_front();
+    }
+    for (int64_t k = s->completed_through + 1; s->mode == 1 && k < s->steps; k++) {
         const int slot = (int)(k % RING);
         if (s->done_step[slot] == k) continue;
         if (hipEventQuery(s->ev[slot]) != hipSuccess) {
@@ -289,7 +304,43 @@ int grow(silu_server *s, int need)
     return SILU_OK;
 }
 
-// Wait for a staging slot's previous launch before reusing it.
+// Stepwise mode: the event slot for the next mark, after the mark that last
+// used it (RING marks ago) has completed; its staging buffers are free then too.
+int claim_mark(silu_server *s, int *slot_out)
+{
+    if ((int)s->marks.size() >= RING) {
+        const hipError_t e = hipEventSynchronize(s->ev[s->marks.front().second]);
+        if (e != hipSuccess) return fail(s, e);
+        reap(s);
+    }
+    *slot_out = (int)(s->nmarks % RING);
+    return SILU_OK;
+}
+
+int record_mark(silu_server *s, int slot, int64_t step)
+{
+    const hipError_t e = hipEventRecord(s->ev[slot], s->stream);
+    if (e != hipSuccess) return fail(s, e);
+    s->marks.push_back({step, slot});
+    s->nmarks++;
+    s->last_mark_step = step;
+    return SILU_OK;
+}
+
+// Stepwise mode: hold the host back while more than MAX_AHEAD steps are
+// enqueued past the last one known complete.
+int throttle(silu_server *s)
+{
+    reap(s);
+    while (s->steps - 1 - s->completed_through > MAX_AHEAD && !s->marks.empty()) {
+        const hipError_t e = hipEventSynchronize(s->ev[s->marks.front().second]);
+        if (e != hipSuccess) return fail(s, e);
+        reap(s);
+    }
+    return SILU_OK;
+}
+
+// Persistent mode: wait for a staging slot's previous launch before reusing it.
 int take_slot(silu_server *s, int *slot_out)
 {
     const int slot = (int)(s->steps % RING);
@@ -558,13 +609,16 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
     }
     if (!s->active.empty()) {
         const int nops = (int)s->active.size();
-        int st = nops > BATCH_ARG_OPS ? grow(s, nops) : SILU_OK;
+        const bool staged = nops > BATCH_ARG_OPS;
+        int st = staged ? grow(s, nops) : SILU_OK;
         if (st) return st;
-        int slot;
-        st = take_slot(s, &slot); // the staging slot was used RING steps ago
-        if (st) return st;
+        if ((st = throttle(s))) return st;
+        int slot = -1;
+        if (staged && (st = claim_mark(s, &slot))) return st; // its staging buffers are free
+        bool finishing = false;
+        for (const Request &q : s->active) finishing |= q.op + 1 == q.total;
         hipError_t e;
-        if (nops <= BATCH_ARG_OPS) { // the op table travels in the kernel arguments
+        if (!staged) { // the op table travels in the kernel arguments
             BatchArgs ba;
             int total = 0;
             for (int i = 0; i < nops; i++) {
@@ -591,9 +645,11 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
                                    s->stream);
             if (e == hipSuccess) e = launch_sweep_batch(SERVE_RPB, s->d_ops, s->d_first, nops, total, s->stream);
         }
-        if (e == hipSuccess) e = hipEventRecord(s->ev[slot], s->stream);
         if (e != hipSuccess) return fail(s, e);
         const int64_t step = s->steps++;
+        if (slot < 0 && (finishing || step - s->last_mark_step >= MARK_EVERY) && (st = claim_mark(s, &slot)))
+            return st;
+        if (slot >= 0 && (st = record_mark(s, slot, step))) return st;
         size_t w = 0;
         for (size_t i = 0; i < s->active.size(); i++) {
             Request &q = s->active[i];
@@ -678,7 +734,15 @@ int silu_server_wait(silu_server *s, int64_t ticket)
         if (state == 3) return SILU_OK;
         if (state == 2) { // its last launch is enqueued: wait for that step's event
             const int64_t k = s->finish_step[ticket];
-            const hipError_t e = hipEventSynchronize(s->ev[k % RING]);
+            hipError_t e = hipSuccess;
+            if (s->mode == 1) {
+                e = hipEventSynchronize(s->ev[k % RING]);
+            } else { // the step that finishes a request always records a mark
+                auto m = std::find_if(s->marks.begin(), s->marks.end(),
+                                      [k](const std::pair<int64_t, int> &v) { return v.first >= k; });
+                e = m != s->marks.end() ? hipEventSynchronize(s->ev[m->second]) : hipStreamSynchronize(s->stream);
+                if (e == hipSuccess && m == s->marks.end()) s->completed_through = s->steps - 1;
+            }
             if (e != hipSuccess) return fail(s, e);
             continue;
         }
@@ -699,7 +763,14 @@ int silu_server_set_mode(silu_server *s, int mode, int max_workgroups)
         max_workgroups > 65535)
         return SILU_ERR_ARG;
     reap(s);
-    if (!s->queue.empty() || !s->active.empty() || s->completed_through + 1 < s->steps) return SILU_ERR_ARG;
+    if (!s->queue.empty() || !s->active.empty()) return SILU_ERR_ARG;
+    if (s->mode == 0) { // steps after the last mark are not tracked: finish them
+        const hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return fail(s, e);
+        s->completed_through = s->steps - 1;
+        reap(s);
+    }
+    if (s->completed_through + 1 < s->steps) return SILU_ERR_ARG;
     if (mode == SILU_SERVE_PERSISTENT && !PERSISTENT_AVAILABLE) return SILU_ERR_UNSUPPORTED;
     if (mode == SILU_SERVE_PERSISTENT) {
         const int st = create_persistent(s);
