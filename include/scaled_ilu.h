@@ -516,7 +516,13 @@ int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
  * each is at; requests that arrive later join at the next step.  A request's
  * workspace returns to the arena once the GPU has passed its last launch.
  * Each row is summed in a fixed order by one lane, so a request's result is
- * bit-identical to ilu_smooth on its own.  At most 8 steps are in flight.
+ * bit-identical to ilu_smooth on its own.  silu_server_register copies A, Ls
+ * and Us into the sliced layout the sweeps read (synchronous; device memory
+ * about that of the CSR arrays, held until silu_server_destroy): values
+ * changed afterwards take effect only for a matrix registered again.  A
+ * matrix without diagonal or offset structure is streamed from its CSR
+ * arrays instead.  The host keeps at most 8 steps enqueued beyond the last
+ * one known to be complete.
  *
  * arena: device memory owned by the caller, 256-byte aligned, alive until
  * silu_server_destroy.  b and x of a request: device FP64 [n], alive until

@@ -444,21 +444,11 @@ int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, int win_policy, Comp
 // code_min: 1 allows the diagonal table, 2 starts at 16-bit offsets, 4 uses
 // columns.  *out->ok is false when the matrix has no entries or the copy
 // would not fit 32-bit slot indices (the caller then streams the CSR).
-int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced **out)
+int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced &S)
 {
-    SlicedKey key{N->row_ptr, N->col_idx, val, N->n_rows, N->nnz, vbytes, code_min};
-    auto it = c->sliced.find(key);
-    if (it != c->sliced.end()) {
-        *out = &it->second;
-        return SILU_OK;
-    }
-    Sliced S;
     const int n = (int)N->n_rows;
     const int nslice = (n + 63) / 64;
-    auto store = [&]() {
-        *out = &c->sliced.emplace(key, S).first->second;
-        return SILU_OK;
-    };
+    auto store = [&]() { return SILU_OK; }; // S.ok stays false unless the copy was built
     if (N->nnz <= 0 || n <= 0) return store();
     // per-slice K and mask bit, then slot offsets
     HIPCHK(c, hipMalloc(&S.sk, (size_t)nslice * 4));
@@ -577,6 +567,24 @@ int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int 
     S.v.slots = slots;
     S.ok = true;
     return store();
+}
+
+int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced **out)
+{
+    SlicedKey key{N->row_ptr, N->col_idx, val, N->n_rows, N->nnz, vbytes, code_min};
+    auto it = c->sliced.find(key);
+    if (it != c->sliced.end()) {
+        *out = &it->second;
+        return SILU_OK;
+    }
+    Sliced S;
+    const int st = build_sliced(c, N, val, vbytes, code_min, S);
+    if (st) {
+        free_sliced(S); // whatever a failed build had allocated
+        return st;
+    }
+    *out = &c->sliced.emplace(key, S).first->second;
+    return SILU_OK;
 }
 
 int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
@@ -920,6 +928,35 @@ int check_finite(silu_ctx *c, int64_t n, const double *x)
 }
 
 } // namespace
+
+namespace silu {
+
+int make_owned_sliced(silu_ctx *c, const silu_csr *N, SlicedView *view, void **owner)
+{
+    *view = SlicedView();
+    *owner = nullptr;
+    Sliced *S = new (std::nothrow) Sliced();
+    if (!S) return SILU_ERR_NOMEM;
+    const int st = build_sliced(c, N, N->val, 8, 1, *S);
+    if (st || !S->ok) {
+        free_sliced(*S);
+        delete S;
+        return st;
+    }
+    *view = S->v;
+    *owner = S;
+    return SILU_OK;
+}
+
+void free_owned_sliced(void *owner)
+{
+    if (!owner) return;
+    Sliced *S = (Sliced *)owner;
+    free_sliced(*S);
+    delete S;
+}
+
+} // namespace silu
 
 extern "C" {
 

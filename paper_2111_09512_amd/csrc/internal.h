@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/scaled_ilu.h"
+
 namespace silu {
 
 // What a CSR sweep kernel does with t_i = rhs_i - sum_j N_ij xin_j (after
@@ -66,6 +68,7 @@ struct SweepArgs {
     double *x;            // EPI_UPDATE / EPI_SCALE_UPDATE
     const double *dshift; // unscaled variant: adds (d_i - 1) * xin_i to the row sum (FP64 only)
     const double *dcol = nullptr; // EPI_UPDATE / EPI_SCALE_UPDATE: column factors c_i, or null (c_i = 1)
+    const SlicedView *sv = nullptr; // batched sweeps: the op's sliced copy (device), or null: CSR-stream
 };
 
 // Kernel geometry for a sweep, picked from the mean row length.
@@ -157,15 +160,23 @@ constexpr double REORDER_THETA = 0.25;
 constexpr int WIN_MAX_SLOTS = 3072;
 
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);
+
+// A sliced-ELL copy of N's FP64 values owned by the caller (the serving
+// runtime), outside the context's cache, so that releasing cached layouts
+// never frees it.  view->nslice stays 0 (and *owner null) when N is better
+// streamed as CSR.  free_owned_sliced frees it; null is ignored.
+int make_owned_sliced(silu_ctx *c, const silu_csr *N, SlicedView *view, void **owner);
+void free_owned_sliced(void *owner);
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name);
 
-// Batched FP64 CSR-stream sweeps (serving): d_ops[i] is one request's sweep,
-// d_first[i] its first workgroup (ceil(n_i / rpb) workgroups each), total the
-// sum.  Both arrays live in device memory.
-hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
-                              hipStream_t s);
+// Batched FP64 sweeps (serving): d_ops[i] is one request's sweep, d_first[i]
+// its first workgroup (ceil(n_i / SERVE_TILE_ROWS) workgroups each), total
+// the sum.  Both arrays live in device memory.  An op whose sv points to a
+// sliced copy (device memory) is swept through it, else as a CSR stream.
+constexpr int SERVE_TILE_ROWS = 256;
+hipError_t launch_sweep_batch(const SweepArgs *d_ops, const int32_t *d_first, int nops, int total, hipStream_t s);
 // The same with the op table passed in the kernel arguments (no copy to the
-// device first): at most BATCH_ARG_OPS ops, 256 rows per workgroup.
+// device first): at most BATCH_ARG_OPS ops.
 constexpr int BATCH_ARG_OPS = 24;
 struct BatchArgs {
     SweepArgs op[BATCH_ARG_OPS];

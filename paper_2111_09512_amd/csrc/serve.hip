@@ -35,7 +35,7 @@ using namespace silu;
 namespace {
 
 constexpr int RING = 8;        // op-table staging slots = steps in flight
-constexpr int SERVE_RPB = 256; // rows per workgroup of the batched sweep
+constexpr int SERVE_RPB = SERVE_TILE_ROWS; // rows per workgroup of the batched sweep
 constexpr int PSTREAMS = 3;    // persistent mode: streams the launches rotate over
 constexpr int DEFAULT_MAX_WG = 1024;
 // The persistent mode is switched off: on MI355X its launches did not finish
@@ -52,7 +52,23 @@ constexpr int MAX_AHEAD = 8;
 struct Matrix {
     silu_csr A;
     silu_factors F;
+    // the server's own sliced copies of A, Ls, Us (device views; null where
+    // the CSR stream is used) and their owners
+    const SlicedView *sv[3] = {nullptr, nullptr, nullptr};
+    void *own[3] = {nullptr, nullptr, nullptr};
+    SlicedView *d_views = nullptr;
 };
+
+void free_matrix_copies(Matrix &M)
+{
+    for (int k = 0; k < 3; k++) free_owned_sliced(M.own[k]);
+    (void)hipFree(M.d_views);
+    M.d_views = nullptr;
+    for (int k = 0; k < 3; k++) {
+        M.own[k] = nullptr;
+        M.sv[k] = nullptr;
+    }
+}
 
 struct Range {
     size_t off, bytes;
@@ -233,6 +249,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
         a.rp = M.A.row_ptr;
         a.col = M.A.col_idx;
         a.val = M.A.val;
+        a.sv = M.sv[0];
         a.xin = q.x;
         a.rhs = q.b;
         if (q.mL >= 2) {
@@ -247,6 +264,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
         a.rp = M.F.Ls.row_ptr;
         a.col = M.F.Ls.col_idx;
         a.val = M.F.Ls.val;
+        a.sv = M.sv[1];
         a.xin = k == 2 ? (const void *)r : (const void *)tmp[(k - 1) & 1];
         a.rhs = r;
         if (k < q.mL) {
@@ -263,6 +281,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
         a.rp = M.F.Us.row_ptr;
         a.col = M.F.Us.col_idx;
         a.val = M.F.Us.val;
+        a.sv = M.sv[2];
         a.xin = k == 2 ? (const void *)sv : (const void *)tmp[(k - 1) & 1];
         a.rhs = sv;
         if (k < q.mU) {
@@ -524,6 +543,7 @@ int silu_server_destroy(silu_server *s)
     }
     (void)hipFree(s->d_ops);
     (void)hipFree(s->d_first);
+    for (Matrix &M : s->mats) free_matrix_copies(M);
     delete s;
     return SILU_OK;
 }
@@ -536,7 +556,25 @@ int silu_server_register(silu_server *s, const silu_csr *A, const silu_factors *
     if (A->dtype != SILU_F64 || F->Ls.dtype != SILU_F64 || F->Us.dtype != SILU_F64 || !F->dinv || !F->scaled)
         return SILU_ERR_UNSUPPORTED;
     if (F->scaled == 2 && !F->dc) return SILU_ERR_ARG;
-    s->mats.push_back({*A, *F});
+    // the sliced copies the batched sweeps read (built now, owned by the server)
+    Matrix M;
+    M.A = *A;
+    M.F = *F;
+    const silu_csr *parts[3] = {A, &F->Ls, &F->Us};
+    SlicedView views[3];
+    int st = SILU_OK;
+    for (int k = 0; k < 3 && st == SILU_OK; k++) st = make_owned_sliced(s->ctx, parts[k], &views[k], &M.own[k]);
+    hipError_t e = hipSuccess;
+    if (st == SILU_OK) {
+        e = hipMalloc((void **)&M.d_views, sizeof(views));
+        if (e == hipSuccess) e = hipMemcpy(M.d_views, views, sizeof(views), hipMemcpyHostToDevice);
+    }
+    if (st != SILU_OK || e != hipSuccess) {
+        free_matrix_copies(M);
+        return st != SILU_OK ? st : fail(s, e);
+    }
+    for (int k = 0; k < 3; k++) M.sv[k] = views[k].nslice > 0 ? M.d_views + k : nullptr;
+    s->mats.push_back(M);
     *matrix_id = (int)s->mats.size() - 1;
     return SILU_OK;
 }
@@ -643,7 +681,7 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(s->d_first, first, sizeof(int32_t) * (size_t)(nops + 1), hipMemcpyHostToDevice,
                                    s->stream);
-            if (e == hipSuccess) e = launch_sweep_batch(SERVE_RPB, s->d_ops, s->d_first, nops, total, s->stream);
+            if (e == hipSuccess) e = launch_sweep_batch(s->d_ops, s->d_first, nops, total, s->stream);
         }
         if (e != hipSuccess) return fail(s, e);
         const int64_t step = s->steps++;

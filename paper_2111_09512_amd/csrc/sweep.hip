@@ -260,19 +260,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-template <class T, int CODE, int WPB, int UNR>
-__global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
+// One wavefront's slice (wave = slice index); dtab: the diagonal table in LDS
+// (code 1).
+template <class T, int CODE, int UNR>
+__device__ __forceinline__ void sliced_wave(const SweepArgs &a, const SlicedView &s, int wave,
+                                            const int32_t *dtab)
 {
     using VT = typename T::VT;
     using XT = typename T::XT;
     using RT = typename T::RT;
     using AT = typename T::AT;
-    __shared__ int32_t dtab[256];
-    if (CODE == 1) {
-        for (int t = (int)threadIdx.x; t < s.ndiag; t += 64 * WPB) dtab[t] = s.dtab[t];
-        __syncthreads();
-    }
-    const int wave = xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * WPB + ((int)threadIdx.x >> 6);
     if (wave >= s.nslice) return;
     const int lane = (int)threadIdx.x & 63;
     const int row = wave * 64 + lane;
@@ -361,14 +358,52 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
     if (live) epilogue_pre<T>(a, row, a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum, aux, aux2, cf);
 }
 
+template <class T, int CODE, int WPB, int UNR>
+__global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
+{
+    __shared__ int32_t dtab[256];
+    if (CODE == 1) {
+        for (int t = (int)threadIdx.x; t < s.ndiag; t += 64 * WPB) dtab[t] = s.dtab[t];
+        __syncthreads();
+    }
+    const int wave = xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * WPB + ((int)threadIdx.x >> 6);
+    sliced_wave<T, CODE, UNR>(a, s, wave, dtab);
+}
+
+// One 256-row tile of a batched op, run by a workgroup of 256 lanes: as four
+// 64-row slices of the op's sliced copy when it has one (a.sv), else as the
+// CSR stream.  Either way each row is summed in ascending column order, so
+// the result is the single-request one bit for bit.
+template <class T>
+__device__ __forceinline__ void batch_tile(const SweepArgs &a, int tile)
+{
+    static_assert(SERVE_TILE_ROWS == 256, "four slices per workgroup");
+    if (!a.sv) {
+        stream_rows<T, 256, 256, 1024, IDX32>(a, tile, nullptr, 0, nullptr, 0);
+        return;
+    }
+    __shared__ int32_t dtab[256];
+    const SlicedView s = *a.sv;
+    const int wave = tile * 4 + ((int)threadIdx.x >> 6);
+    if (s.code == 1) {
+        for (int t = (int)threadIdx.x; t < s.ndiag; t += 256) dtab[t] = s.dtab[t];
+        __syncthreads();
+        sliced_wave<T, 1, 2>(a, s, wave, dtab);
+    } else if (s.code == 2) {
+        sliced_wave<T, 2, 2>(a, s, wave, dtab);
+    } else {
+        sliced_wave<T, 4, 2>(a, s, wave, dtab);
+    }
+}
+
 // Batched CSR-stream: one launch runs one sweep for each of `nops`
 // independent requests (different matrices, sizes and epilogues).  Op i owns
 // workgroups [first[i], first[i+1]); each workgroup finds its op by binary
 // search and runs exactly the single-request body, so a request's result does
 // not depend on what else shares the launch.
-template <class T, int BLOCK, int RPB, int CAP>
-__global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch(const SweepArgs *__restrict__ ops,
-                                                              const int32_t *__restrict__ first, int nops)
+template <class T>
+__global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *__restrict__ ops,
+                                                     const int32_t *__restrict__ first, int nops)
 {
     const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, hi = nops - 1; // largest i with first[i] <= b
@@ -377,12 +412,12 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch(const SweepArgs *_
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stream_rows<T, BLOCK, RPB, CAP, IDX32>(ops[lo], b - first[lo], nullptr, 0, nullptr, 0);
+    batch_tile<T>(ops[lo], b - first[lo]);
 }
 
 // The same with the op table in the kernel arguments.
-template <class T, int BLOCK, int RPB, int CAP>
-__global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch_args(BatchArgs ba)
+template <class T>
+__global__ void __launch_bounds__(256) k_sweep_batch_args(BatchArgs ba)
 {
     const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
     int lo = 0, hi = ba.nops - 1;
@@ -391,7 +426,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_stream_batch_args(BatchArgs ba)
         if (ba.first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    stream_rows<T, BLOCK, RPB, CAP, IDX32>(ba.op[lo], b - ba.first[lo], nullptr, 0, nullptr, 0);
+    batch_tile<T>(ba.op[lo], b - ba.first[lo]);
 }
 
 // Persistent batched CSR-stream: one launch runs whole chains of sweeps (all
@@ -641,29 +676,6 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
     }
 }
 
-template <class T>
-hipError_t dispatch_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
-                          hipStream_t s)
-{
-    if (nops <= 0 || total <= 0) return hipSuccess;
-    switch (rpb) {
-    case 256:
-        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 256, 1024>), dim3(total), dim3(256), 0, s, d_ops, d_first,
-                           nops);
-        break;
-    case 128:
-        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 128, 1024>), dim3(total), dim3(256), 0, s, d_ops, d_first,
-                           nops);
-        break;
-    case 64:
-        hipLaunchKernelGGL((k_sweep_stream_batch<T, 256, 64, 2048>), dim3(total), dim3(256), 0, s, d_ops, d_first,
-                           nops);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 const char *kname16(Prec p)
 {
     static const char *names[5] = {"sweep_stream16_f64", "sweep_stream16_mixres", "sweep_stream16_mixL",
@@ -775,16 +787,17 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     return g;
 }
 
-hipError_t launch_sweep_batch(int rpb, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
-                              hipStream_t s)
+hipError_t launch_sweep_batch(const SweepArgs *d_ops, const int32_t *d_first, int nops, int total, hipStream_t s)
 {
-    return dispatch_batch<TF64>(rpb, d_ops, d_first, nops, total, s);
+    if (nops <= 0 || total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_sweep_batch<TF64>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s)
 {
     if (b.nops <= 0 || b.nops > BATCH_ARG_OPS || b.first[b.nops] <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep_stream_batch_args<TF64, 256, 256, 1024>), dim3(b.first[b.nops]), dim3(256), 0, s, b);
+    hipLaunchKernelGGL((k_sweep_batch_args<TF64>), dim3(b.first[b.nops]), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
