@@ -235,8 +235,9 @@ def main():
     ap.add_argument("--serving-arena-mb", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the smoother shards as block-Jacobi ILU "
-                                   "(see the design notes), but multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the smoother would shard as block-Jacobi "
+                                   "ILU (one diagonal block per GPU, a halo exchange of x per outer step), which "
+                                   "is not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

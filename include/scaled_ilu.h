@@ -45,7 +45,7 @@ extern "C" {
 #define SILU_ERR_NONFINITE (-5)   /* SILU_CHECK_FINITE found a NaN/Inf in x */
 #define SILU_ERR_NOMEM (-6)       /* caller workspace smaller than silu_workspace_size() */
 #define SILU_ERR_HIP (-7)         /* a HIP runtime call failed */
-#define SILU_ERR_UNSUPPORTED (-8) /* valid request this build does not implement */
+#define SILU_ERR_UNSUPPORTED (-8) /* valid request this library version does not implement */
 #define SILU_ERR_TIMEOUT (-9)     /* a persistent serving launch gave up a bounded wait */
 
 /* ---- value types of silu_csr.val ------------------------------------- */
@@ -568,7 +568,7 @@ int silu_server_last_hip_error(const silu_server *server);
  * Scheduling mode of a server (the serving form; Algorithm 2 per request).
  *   SILU_SERVE_STEPWISE (default): as above, one batched launch per step, one
  *     sweep per active request.
- *   SILU_SERVE_PERSISTENT: NOT AVAILABLE in this build -- set_mode returns
+ *   SILU_SERVE_PERSISTENT: NOT AVAILABLE in this version -- set_mode returns
  *     SILU_ERR_UNSUPPORTED (its launches did not finish on MI355X, for a
  *     cause not yet found).  As designed: a step hands the requests it admits, with all of
  *     their sweeps, to ONE persistent launch on the next of three streams the

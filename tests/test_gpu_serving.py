@@ -278,7 +278,7 @@ def test_set_mode_rules(B, ctx, pool):
     assert e.value.status == -1
     _drain(server, [t])
     torch.cuda.synchronize()
-    with pytest.raises(B.SiluError) as e:  # switched off in this build
+    with pytest.raises(B.SiluError) as e:  # switched off in the library
         server.set_mode(server.PERSISTENT, 16)
     assert e.value.status == -8
     server.set_mode(server.STEPWISE)
