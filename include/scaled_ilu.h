@@ -510,7 +510,7 @@ int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
  * smoother requests on them (each request: `outer` steps of ilu_smooth's
  * iteration, FP64).  silu_server_step() first admits queued requests in
  * arrival order while their workspace (silu_server_request_bytes: four
- * n-vectors) fits in the caller's arena and fewer than max_active are
+ * n-vectors and 16 bytes per 256 rows) fits in the caller's arena and fewer than max_active are
  * running, then enqueues ONE batched launch that advances every active
  * request by one sweep (residual, an L sweep or a U sweep), whatever sweep
  * each is at; requests that arrive later join at the next step.  A request's
@@ -540,6 +540,28 @@ int silu_server_register(silu_server *server, const silu_csr *A, const silu_fact
 int64_t silu_server_request_bytes(const silu_server *server, int matrix_id);
 int silu_server_submit(silu_server *server, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
                        int64_t *ticket);
+/*
+ * A solve request: the smoother iterated until the relative residual of eq.
+ * relres, ||b - A x|| / ||b||, falls below tol, checked for the initial x and
+ * after each outer step, at most max_outer steps.  It is scheduled like a
+ * smoother request of max_outer steps plus one final residual; the residual
+ * at the start of each outer step is the check: its tile sums of r_i^2 are
+ * closed by one small launch per step, which sets the request's stop flag on
+ * the device, and every later sweep of a stopped request does nothing, so x
+ * keeps the first iterate that passed.  The request is reported done after
+ * its scheduled sweeps either way.  Each sweep is the one ilu_smooth makes, so
+ * x equals that many ilu_smooth outer steps bit for bit; the norms are summed
+ * in a fixed order (not the sequential one).  tol > 0, 0 <= max_outer <=
+ * 2^20; stepwise mode only (UNSUPPORTED otherwise).
+ * silu_server_solve_result, once the request is done: *outer_steps = the
+ * number of outer steps after which the test first passed (0: x0 already
+ * did), or max_outer + 1 if it never did; *relres = the relative residual of
+ * the last check made.  ARG for an unknown ticket, one that is not a solve
+ * request, or one not yet done.
+ */
+int silu_server_submit_solve(silu_server *server, int matrix_id, const double *b, double *x, double tol,
+                             int max_outer, int m_L, int m_U, int64_t *ticket);
+int silu_server_solve_result(silu_server *server, int64_t ticket, int *outer_steps, double *relres);
 /* One scheduling step (asynchronous; blocks only when 8 steps are in flight). */
 int silu_server_step(silu_server *server, int *n_active, int *n_queued);
 /* Up to max_steps steps in one call (each one admits and launches as above),

@@ -127,6 +127,9 @@ _sig = {
     "silu_server_register": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.POINTER(C.c_int)]),
     "silu_server_request_bytes": (C.c_int64, [_P, C.c_int]),
     "silu_server_submit": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64)]),
+    "silu_server_submit_solve": (C.c_int, [_P, C.c_int, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
+                                           C.POINTER(C.c_int64)]),
+    "silu_server_solve_result": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "silu_server_step": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "silu_server_poll": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int)]),
     "silu_server_last_hip_error": (C.c_int, [_P]),
@@ -711,6 +714,25 @@ class Server:
                                             m_L, m_U, C.byref(t)), "silu_server_submit")
         self._req[t.value] = (b, x)
         return t.value
+
+    def submit_solve(self, mid: int, b: torch.Tensor, x: torch.Tensor, tol: float, max_outer: int, m_L: int,
+                     m_U: int) -> int:
+        """A solve request: outer steps until ||b - A x|| / ||b|| < tol (checked for x0 and
+        after each step), at most max_outer."""
+        t = C.c_int64()
+        self._check(_lib.silu_server_submit_solve(self._h, mid, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                                  float(tol), max_outer, m_L, m_U, C.byref(t)),
+                    "silu_server_submit_solve")
+        self._req[t.value] = (b, x)
+        return t.value
+
+    def solve_result(self, ticket: int) -> tuple[int, float]:
+        """(outer steps after which the test passed, or max_outer + 1; relative residual of
+        the last check) of a finished solve request."""
+        k, rel = C.c_int(), C.c_double()
+        self._check(_lib.silu_server_solve_result(self._h, ticket, C.byref(k), C.byref(rel)),
+                    "silu_server_solve_result")
+        return k.value, rel.value
 
     def step(self) -> tuple[int, int]:
         a, q = C.c_int(), C.c_int()

@@ -69,7 +69,42 @@ struct SweepArgs {
     const double *dshift; // unscaled variant: adds (d_i - 1) * xin_i to the row sum (FP64 only)
     const double *dcol = nullptr; // EPI_UPDATE / EPI_SCALE_UPDATE: column factors c_i, or null (c_i = 1)
     const SlicedView *sv = nullptr; // batched sweeps: the op's sliced copy (device), or null: CSR-stream
+    // batched sweeps of a solve request (null / 0 otherwise): the op does
+    // nothing once sctl->stop is set; a check op (the residual at the start of
+    // an outer step) also writes its tile's sums of r_i^2 (and, scheck == 2,
+    // of b_i^2) to spart[2 tile], spart[2 tile + 1]
+    const struct SolveCtl *sctl = nullptr;
+    double *spart = nullptr;
+    int scheck = 0;
 };
+
+// Device state of a solve request: the convergence test of eq. relres on the
+// residual at the start of each outer step (its squared norm rr, that of b, bb,
+// from the first check), the number of checks made, and the stop flag.
+struct SolveCtl {
+    int32_t stop;
+    int32_t checks;
+    double rr;
+    double bb;
+    double pad;
+};
+
+// One launch that closes the checks of a step: workgroup i sums the tile
+// partials of check i in a fixed order and updates its SolveCtl (unless it
+// has stopped already): stop when sqrt(rr) / sqrt(bb) < tol.
+constexpr int SOLVE_CHECKS_PER_LAUNCH = 32;
+struct SolveCheck {
+    SolveCtl *ctl;
+    const double *part;
+    int tiles;
+    int first; // the first check: bb comes from this one's partials
+    double tol;
+};
+struct SolveCheckArgs {
+    SolveCheck c[SOLVE_CHECKS_PER_LAUNCH];
+    int count;
+};
+hipError_t launch_solve_check(const SolveCheckArgs &a, hipStream_t s);
 
 // Kernel geometry for a sweep, picked from the mean row length.
 struct SweepGeom {

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -82,9 +83,24 @@ struct Request {
     int outer, mL, mU;
     int op = 0, total = 0;
     Range ws{0, 0};
+    double tol = 0.0; // > 0: a solve request (outer = its largest number of outer steps)
+    int result = -1;  // solve requests: slot of its SolveCtl copy in the pinned result blocks
 };
 
 size_t vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
+
+// Workspace of a request: r, s and two iterates (n-vectors each), then the
+// SolveCtl of a solve request and its per-tile partial sums.
+size_t ctl_bytes(int64_t n)
+{
+    const size_t tiles = (size_t)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS);
+    return ((sizeof(SolveCtl) + 16 * tiles + 255) / 256) * 256;
+}
+size_t request_bytes(int64_t n) { return 4 * vec_bytes(n) + ctl_bytes(n); }
+
+// Pinned host copies of finished solve requests' SolveCtl, in blocks that are
+// never moved while the server lives.
+constexpr int RESULTS_PER_BLOCK = 1024;
 
 int64_t now_ns()
 {
@@ -96,6 +112,9 @@ int64_t now_ns()
 } // namespace
 
 struct silu_server {
+    std::vector<SolveCtl *> result_blocks; // pinned, RESULTS_PER_BLOCK each
+    int64_t nresults = 0;
+    std::map<int64_t, std::pair<int64_t, int>> solve_result; // ticket -> (result slot, max outer steps)
     silu_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     char *arena = nullptr;
@@ -289,6 +308,14 @@ SweepArgs op_of(const silu_server *s, const Request &q)
             a.out = tmp[k & 1];
         } else {
             a.epi = EPI_UPDATE;
+        }
+    }
+    if (q.tol > 0.0) {
+        char *cb = w + 4 * vb;
+        a.sctl = (const SolveCtl *)cb;
+        if (j == 0) { // the residual at the start of an outer step (or the final one) is a check
+            a.spart = (double *)(cb + sizeof(SolveCtl));
+            a.scheck = q.op == 0 ? 2 : 1;
         }
     }
     return a;
@@ -544,6 +571,7 @@ int silu_server_destroy(silu_server *s)
     (void)hipFree(s->d_ops);
     (void)hipFree(s->d_first);
     for (Matrix &M : s->mats) free_matrix_copies(M);
+    for (SolveCtl *blk : s->result_blocks) (void)hipHostFree(blk);
     delete s;
     return SILU_OK;
 }
@@ -582,7 +610,7 @@ int silu_server_register(silu_server *s, const silu_csr *A, const silu_factors *
 int64_t silu_server_request_bytes(const silu_server *s, int matrix_id)
 {
     if (!s || matrix_id < 0 || matrix_id >= (int)s->mats.size()) return -1;
-    return (int64_t)(4 * vec_bytes(s->mats[(size_t)matrix_id].A.n_rows));
+    return (int64_t)request_bytes(s->mats[(size_t)matrix_id].A.n_rows);
 }
 
 int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
@@ -603,6 +631,34 @@ int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x
     s->queue.push_back(q);
     s->times[q.ticket] = {now_ns(), -1};
     *ticket = q.ticket;
+    return SILU_OK;
+}
+
+int silu_server_submit_solve(silu_server *s, int matrix_id, const double *b, double *x, double tol, int max_outer,
+                             int m_L, int m_U, int64_t *ticket)
+{
+    if (!s || !(tol > 0.0) || max_outer < 0 || max_outer > (1 << 20)) return SILU_ERR_ARG;
+    if (s->mode != 0) return SILU_ERR_UNSUPPORTED;
+    const int st = silu_server_submit(s, matrix_id, b, x, std::max(max_outer, 1), m_L, m_U, ticket);
+    if (st) return st;
+    Request &q = s->queue.back();
+    q.outer = max_outer;
+    q.tol = tol;
+    q.total = max_outer * (1 + (m_L - 1) + (m_U - 1)) + 1; // and the check of the last iterate
+    return SILU_OK;
+}
+
+int silu_server_solve_result(silu_server *s, int64_t ticket, int *outer_steps, double *relres)
+{
+    if (!s || !outer_steps || !relres) return SILU_ERR_ARG;
+    reap(s);
+    auto it = s->solve_result.find(ticket);
+    auto fs = s->finish_step.find(ticket);
+    if (it == s->solve_result.end() || fs == s->finish_step.end() || !step_done(s, fs->second)) return SILU_ERR_ARG;
+    const int64_t slot = it->second.first;
+    const SolveCtl &c = s->result_blocks[(size_t)slot / RESULTS_PER_BLOCK][slot % RESULTS_PER_BLOCK];
+    *outer_steps = c.stop ? c.checks - 1 : it->second.second + 1;
+    *relres = std::sqrt(c.rr) / std::sqrt(c.bb);
     return SILU_OK;
 }
 
@@ -642,6 +698,12 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         Range r;
         if (!allocate(s, (size_t)silu_server_request_bytes(s, q.mid), &r)) break;
         q.ws = r;
+        if (q.tol > 0.0) { // a fresh SolveCtl: not stopped, no checks yet
+            const size_t vb = vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
+            const hipError_t e = launch_fill((int)(sizeof(SolveCtl) / 8), (double *)(s->arena + r.off + 4 * vb),
+                                             0.0, nullptr, 0.0, s->stream);
+            if (e != hipSuccess) return fail(s, e);
+        }
         s->active.push_back(q);
         s->queue.pop_front();
     }
@@ -684,6 +746,37 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             if (e == hipSuccess) e = launch_sweep_batch(s->d_ops, s->d_first, nops, total, s->stream);
         }
         if (e != hipSuccess) return fail(s, e);
+        // close the convergence checks of solve requests made in this launch
+        SolveCheckArgs ca;
+        ca.count = 0;
+        for (const Request &q : s->active) {
+            if (q.tol <= 0.0 || q.op % (1 + (q.mL - 1) + (q.mU - 1)) != 0) continue;
+            const int64_t n = s->mats[(size_t)q.mid].A.n_rows;
+            char *cb = s->arena + q.ws.off + 4 * vec_bytes(n);
+            ca.c[ca.count++] = {(SolveCtl *)cb, (const double *)(cb + sizeof(SolveCtl)),
+                                (int)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS), q.op == 0 ? 1 : 0, q.tol};
+            if (ca.count == SOLVE_CHECKS_PER_LAUNCH) {
+                if ((e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
+                ca.count = 0;
+            }
+        }
+        if (ca.count && (e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
+        // a finishing solve request's state goes to pinned host memory before the mark
+        for (Request &q : s->active) {
+            if (q.tol <= 0.0 || q.op + 1 != q.total) continue;
+            if (s->nresults == (int64_t)s->result_blocks.size() * RESULTS_PER_BLOCK) {
+                SolveCtl *blk = nullptr;
+                if ((e = hipHostMalloc((void **)&blk, sizeof(SolveCtl) * RESULTS_PER_BLOCK)) != hipSuccess)
+                    return fail(s, e);
+                s->result_blocks.push_back(blk);
+            }
+            q.result = (int)s->nresults++;
+            SolveCtl *dst = s->result_blocks[(size_t)q.result / RESULTS_PER_BLOCK] + q.result % RESULTS_PER_BLOCK;
+            const char *src = s->arena + q.ws.off + 4 * vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
+            if ((e = hipMemcpyAsync(dst, src, sizeof(SolveCtl), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+                return fail(s, e);
+            s->solve_result[q.ticket] = {q.result, q.outer};
+        }
         const int64_t step = s->steps++;
         if (slot < 0 && (finishing || step - s->last_mark_step >= MARK_EVERY) && (st = claim_mark(s, &slot)))
             return st;

@@ -151,9 +151,10 @@ __device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typena
 // pipeline one 8-byte word at a time.  Banded factors use a few hundred slots.
 enum IdxMode : int { IDX32 = 0, OFF16 = 1, WIN = 2 };
 
+// Returns the lane's row value t (0 for a lane without a row).
 template <class T, int BLOCK, int RPB, int CAP, int MODE>
-__device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const uint16_t *__restrict__ code, int shift,
-                                            const int32_t *__restrict__ wo, int lw)
+__device__ __forceinline__ double stream_rows(const SweepArgs &a, int blk, const uint16_t *__restrict__ code,
+                                              int shift, const int32_t *__restrict__ wo, int lw)
 {
     using VT = typename T::VT;
     using XT = typename T::XT;
@@ -218,7 +219,9 @@ __device__ __forceinline__ void stream_rows(const SweepArgs &a, int blk, const u
         for (int k = lo; k < hi; ++k) sum = sum + prod[k - c0];
         __syncthreads();
     }
-    if (tid < nr) epilogue_pre<T>(a, r0 + tid, a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum, aux, aux2, cf);
+    const AT t = a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum;
+    if (tid < nr) epilogue_pre<T>(a, r0 + tid, t, aux, aux2, cf);
+    return tid < nr ? (double)t : 0.0;
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
@@ -261,16 +264,16 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // One wavefront's slice (wave = slice index); dtab: the diagonal table in LDS
-// (code 1).
+// (code 1).  Returns the lane's row value t (0 for a lane without a row).
 template <class T, int CODE, int UNR>
-__device__ __forceinline__ void sliced_wave(const SweepArgs &a, const SlicedView &s, int wave,
-                                            const int32_t *dtab)
+__device__ __forceinline__ double sliced_wave(const SweepArgs &a, const SlicedView &s, int wave,
+                                              const int32_t *dtab)
 {
     using VT = typename T::VT;
     using XT = typename T::XT;
     using RT = typename T::RT;
     using AT = typename T::AT;
-    if (wave >= s.nslice) return;
+    if (wave >= s.nslice) return 0.0;
     const int lane = (int)threadIdx.x & 63;
     const int row = wave * 64 + lane;
     const bool live = row < a.n;
@@ -355,7 +358,9 @@ __device__ __forceinline__ void sliced_wave(const SweepArgs &a, const SlicedView
             }
         }
     }
-    if (live) epilogue_pre<T>(a, row, a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum, aux, aux2, cf);
+    const AT t = a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum;
+    if (live) epilogue_pre<T>(a, row, t, aux, aux2, cf);
+    return live ? (double)t : 0.0;
 }
 
 template <class T, int CODE, int WPB, int UNR>
@@ -374,25 +379,81 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
 // 64-row slices of the op's sliced copy when it has one (a.sv), else as the
 // CSR stream.  Either way each row is summed in ascending column order, so
 // the result is the single-request one bit for bit.
+// A solve request's op is skipped once its request has stopped (the flag was
+// set by an earlier launch); a check op then reduces r_i^2 (and b_i^2 on the
+// first check) over its tile in a fixed order (lane i holds row 256 tile + i
+// in both paths) and writes the two sums for the step's check launch.
 template <class T>
 __device__ __forceinline__ void batch_tile(const SweepArgs &a, int tile)
 {
     static_assert(SERVE_TILE_ROWS == 256, "four slices per workgroup");
+    if (a.sctl && *(const volatile int32_t *)&a.sctl->stop) return;
+    double t;
     if (!a.sv) {
-        stream_rows<T, 256, 256, 1024, IDX32>(a, tile, nullptr, 0, nullptr, 0);
-        return;
-    }
-    __shared__ int32_t dtab[256];
-    const SlicedView s = *a.sv;
-    const int wave = tile * 4 + ((int)threadIdx.x >> 6);
-    if (s.code == 1) {
-        for (int t = (int)threadIdx.x; t < s.ndiag; t += 256) dtab[t] = s.dtab[t];
-        __syncthreads();
-        sliced_wave<T, 1, 2>(a, s, wave, dtab);
-    } else if (s.code == 2) {
-        sliced_wave<T, 2, 2>(a, s, wave, dtab);
+        t = stream_rows<T, 256, 256, 1024, IDX32>(a, tile, nullptr, 0, nullptr, 0);
     } else {
-        sliced_wave<T, 4, 2>(a, s, wave, dtab);
+        __shared__ int32_t dtab[256];
+        const SlicedView s = *a.sv;
+        const int wave = tile * 4 + ((int)threadIdx.x >> 6);
+        if (s.code == 1) {
+            for (int k = (int)threadIdx.x; k < s.ndiag; k += 256) dtab[k] = s.dtab[k];
+            __syncthreads();
+            t = sliced_wave<T, 1, 2>(a, s, wave, dtab);
+        } else if (s.code == 2) {
+            t = sliced_wave<T, 2, 2>(a, s, wave, dtab);
+        } else {
+            t = sliced_wave<T, 4, 2>(a, s, wave, dtab);
+        }
+    }
+    if (!a.scheck) return;
+    __shared__ double red[2][256];
+    const int tid = (int)threadIdx.x, row = tile * 256 + tid;
+    red[0][tid] = t * t;
+    double bv = 0.0;
+    if (a.scheck == 2 && row < a.n) bv = ((const double *)a.rhs)[row];
+    red[1][tid] = bv * bv;
+    for (int off = 128; off > 0; off >>= 1) {
+        __syncthreads();
+        if (tid < off) {
+            red[0][tid] = red[0][tid] + red[0][tid + off];
+            red[1][tid] = red[1][tid] + red[1][tid + off];
+        }
+    }
+    if (tid == 0) {
+        a.spart[2 * tile] = red[0][0];
+        a.spart[2 * tile + 1] = red[1][0];
+    }
+}
+
+// Closes the checks of one step (one workgroup per check): the tile partials
+// summed in a fixed order, then the test of eq. relres.
+__global__ void __launch_bounds__(256) k_solve_check(SolveCheckArgs ca)
+{
+    const SolveCheck c = ca.c[blockIdx.x];
+    if (*(const volatile int32_t *)&c.ctl->stop) return; // its check op did nothing
+    __shared__ double red[2][256];
+    const int tid = (int)threadIdx.x;
+    double rr = 0.0, bb = 0.0;
+    for (int k = tid; k < c.tiles; k += 256) {
+        rr = rr + c.part[2 * k];
+        bb = bb + c.part[2 * k + 1];
+    }
+    red[0][tid] = rr;
+    red[1][tid] = bb;
+    for (int off = 128; off > 0; off >>= 1) {
+        __syncthreads();
+        if (tid < off) {
+            red[0][tid] = red[0][tid] + red[0][tid + off];
+            red[1][tid] = red[1][tid] + red[1][tid + off];
+        }
+    }
+    if (tid == 0) {
+        SolveCtl *ctl = c.ctl;
+        const double b2 = c.first ? red[1][0] : ctl->bb;
+        ctl->rr = red[0][0];
+        ctl->bb = b2;
+        ctl->checks = ctl->checks + 1;
+        if (sqrt(red[0][0]) / sqrt(b2) < c.tol) ctl->stop = 1;
     }
 }
 
@@ -798,6 +859,13 @@ hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s)
 {
     if (b.nops <= 0 || b.nops > BATCH_ARG_OPS || b.first[b.nops] <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_sweep_batch_args<TF64>), dim3(b.first[b.nops]), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_check(const SolveCheckArgs &a, hipStream_t s)
+{
+    if (a.count <= 0 || a.count > SOLVE_CHECKS_PER_LAUNCH) return a.count == 0 ? hipSuccess : hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_solve_check, dim3(a.count), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -403,3 +403,75 @@ def test_sliced_and_streamed_matrices_in_one_batch(orc, B, ctx):
         ref = orc.smooth(p["A"], p["Ls"], p["Us"], p["dinv"], r["b"], r["x0"], r["outer"], r["mL"], r["mU"])
         np.testing.assert_array_equal(got, ref)
     server.close()
+
+
+def _tol_with_margin(hist_fn, tol):
+    """A tolerance at least 1e-6 (relative) away from every residual the
+    oracle's run checks, so that the two sides' different summation orders
+    cannot flip a decision."""
+    for _ in range(20):
+        k, x, hist = hist_fn(tol)
+        if np.all(np.abs(hist / tol - 1.0) > 1e-6):
+            return tol, (k, x, hist)
+        tol *= 1.37
+    raise AssertionError("no tolerance with a margin")
+
+
+def test_solve_requests_match_the_oracle(orc, B, ctx, pool):
+    """Solve requests (iterate until eq. relres < tol) in the same steps as
+    smoother requests: the outer-step count and x equal the oracle's
+    smooth_until bit for bit, the reported relative residual to rounding;
+    including x0 already converged (0 steps), max_outer = 0, a request that
+    never converges (max_outer + 1) and m_L = 1 (the residual fused with
+    D^{-1})."""
+    say("serving: solve requests")
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=64)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    # (matrix, m_L, m_U, tol, max_outer): the two smallest pool matrices converge
+    # (tens of steps), the larger ones do not within these limits
+    plan = [(0, 3, 3, 1e-3, 60), (0, 6, 6, 1e-8, 80), (1, 4, 4, 1e-6, 200), (1, 1, 6, 1e-4, 200),
+            (0, 6, 1, 1e-5, 120), (3, 3, 3, 1e-8, 5), (4, 2, 2, 1e-6, 0), (2, 4, 2, 1e-12, 3), (1, 3, 3, 1e-2, 50),
+            (0, 2, 4, 1e-7, 100)]
+    cases = []
+    for k, (mid, mL, mU, tol, max_outer) in enumerate(plan):
+        p = pool[mid]
+        n = p["A"].n
+        b = W.rhs(n, 300 + k)
+        x0 = W.rhs(n, 400 + k) * (k % 2)
+        if k == 7:  # already converged: b = A x0 exactly
+            x0 = W.rhs(n, 400 + k)
+            b = orc.spmv(p["A"], x0)
+
+        def run(t, p=p, b=b, x0=x0, mL=mL, mU=mU, max_outer=max_outer):
+            return orc.smooth_until(p["A"], p["Ls"], p["Us"], p["dinv"], b, x0, mL, mU, t, max_outer)
+
+        tol, ref = (tol, run(tol)) if k == 7 else _tol_with_margin(run, tol)
+        cases.append(dict(mid=mid, b=b, x0=x0, mL=mL, mU=mU, tol=tol, max_outer=max_outer, ref=ref))
+    tickets, xs = [], []
+    for k, c in enumerate(cases):
+        x = dev(c["x0"])
+        xs.append(x)
+        tickets.append(server.submit_solve(mids[c["mid"]], dev(c["b"]), x, c["tol"], c["max_outer"], c["mL"], c["mU"]))
+        # a smoother request between the solve requests shares their steps
+        n = pool[c["mid"]]["A"].n
+        server.submit(mids[c["mid"]], dev(W.rhs(n, 900 + k)), torch.zeros(n, dtype=torch.float64, device="cuda"),
+                      2, 3, 3)
+    _drain(server, tickets)
+    seen = set()
+    for k, c in enumerate(cases):
+        k_ref, x_ref, hist = c["ref"]
+        steps, rel = server.solve_result(tickets[k])
+        seen.add(k_ref if k_ref <= c["max_outer"] else "never")
+        assert steps == k_ref, f"case {k}: {steps} steps, oracle {k_ref}"
+        np.testing.assert_array_equal(host(xs[k]), x_ref)
+        assert rel == pytest.approx(hist[-1], rel=1e-12)
+    assert 0 in seen and "never" in seen and len(seen) >= 6
+    with pytest.raises(B.SiluError) as e:  # not a solve request
+        t = server.submit(mids[0], dev(W.rhs(pool[0]["A"].n, 1)), dev(np.zeros(pool[0]["A"].n)), 1, 3, 3)
+        server.wait(t)
+        server.solve_result(t)
+    assert e.value.status == -1
+    with pytest.raises(B.SiluError) as e:
+        server.submit_solve(mids[0], dev(W.rhs(pool[0]["A"].n, 1)), dev(np.zeros(pool[0]["A"].n)), 0.0, 5, 3, 3)
+    assert e.value.status == -1
+    server.close()
