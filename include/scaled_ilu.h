@@ -548,8 +548,10 @@ int silu_server_submit(silu_server *server, int matrix_id, const double *b, doub
  * at the start of each outer step is the check: its tile sums of r_i^2 are
  * closed by one small launch per step, which sets the request's stop flag on
  * the device, and every later sweep of a stopped request does nothing, so x
- * keeps the first iterate that passed.  The request is reported done after
- * its scheduled sweeps either way.  Each sweep is the one ilu_smooth makes, so
+ * keeps the first iterate that passed.  The same launch sets a pinned host
+ * word, which the next steps read: a stopped request gets no more sweeps and
+ * is reported done with the step after that (otherwise after its scheduled
+ * sweeps).  Each sweep is the one ilu_smooth makes, so
  * x equals that many ilu_smooth outer steps bit for bit; the norms are summed
  * in a fixed order (not the sequential one).  tol > 0, 0 <= max_outer <=
  * 2^20; stepwise mode only (UNSUPPORTED otherwise).

@@ -99,6 +99,7 @@ struct SolveCheck {
     int tiles;
     int first; // the first check: bb comes from this one's partials
     double tol;
+    int32_t *hflag; // pinned host word set to 1 with the stop flag (or null)
 };
 struct SolveCheckArgs {
     SolveCheck c[SOLVE_CHECKS_PER_LAUNCH];

@@ -85,6 +85,7 @@ struct Request {
     Range ws{0, 0};
     double tol = 0.0; // > 0: a solve request (outer = its largest number of outer steps)
     int result = -1;  // solve requests: slot of its SolveCtl copy in the pinned result blocks
+    int flag = -1;    // solve requests: its word in the pinned stop flags
 };
 
 size_t vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
@@ -115,6 +116,11 @@ struct silu_server {
     std::vector<SolveCtl *> result_blocks; // pinned, RESULTS_PER_BLOCK each
     int64_t nresults = 0;
     std::map<int64_t, std::pair<int64_t, int>> solve_result; // ticket -> (result slot, max outer steps)
+    int32_t *hflags = nullptr;                  // pinned stop flags of solve requests (max_active words)
+    int32_t *d_hflags = nullptr;                // the same words as the device addresses them
+    std::vector<int> free_flags;
+    std::map<int64_t, int> ticket_flag;         // ticket -> flag word, until the request is reported done
+    bool force_mark = false;                    // the next step must record a mark
     silu_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     char *arena = nullptr;
@@ -241,6 +247,11 @@ void reap(silu_server *s)
         if (step_done(s, rp[i].first)) {
             s->done_queue.push_back(rp[i].second);
             s->times[rp[i].second].second = now_ns();
+            auto fl = s->ticket_flag.find(rp[i].second);
+            if (fl != s->ticket_flag.end()) {
+                s->free_flags.push_back(fl->second);
+                s->ticket_flag.erase(fl);
+            }
         } else
             rp[w++] = rp[i];
     }
@@ -550,10 +561,12 @@ int silu_server_create(silu_ctx *ctx, void *hip_stream, void *arena, size_t aren
             return SILU_ERR_HIP;
         }
     }
-    if (grow(s, 64)) {
+    if (grow(s, 64) || hipHostMalloc((void **)&s->hflags, sizeof(int32_t) * (size_t)max_active) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->d_hflags, s->hflags, 0) != hipSuccess) {
         silu_server_destroy(s);
         return SILU_ERR_HIP;
     }
+    for (int i = max_active - 1; i >= 0; i--) s->free_flags.push_back(i);
     *out = s;
     return SILU_OK;
 }
@@ -572,6 +585,7 @@ int silu_server_destroy(silu_server *s)
     (void)hipFree(s->d_first);
     for (Matrix &M : s->mats) free_matrix_copies(M);
     for (SolveCtl *blk : s->result_blocks) (void)hipHostFree(blk);
+    (void)hipHostFree(s->hflags);
     delete s;
     return SILU_OK;
 }
@@ -634,6 +648,26 @@ int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x
     return SILU_OK;
 }
 
+// A finishing solve request: its SolveCtl is copied to the pinned result
+// blocks after everything enqueued so far (the mark that ends its step covers
+// the copy).
+int save_result(silu_server *s, Request &q)
+{
+    hipError_t e;
+    if (s->nresults == (int64_t)s->result_blocks.size() * RESULTS_PER_BLOCK) {
+        SolveCtl *blk = nullptr;
+        if ((e = hipHostMalloc((void **)&blk, sizeof(SolveCtl) * RESULTS_PER_BLOCK)) != hipSuccess) return fail(s, e);
+        s->result_blocks.push_back(blk);
+    }
+    q.result = (int)s->nresults++;
+    SolveCtl *dst = s->result_blocks[(size_t)q.result / RESULTS_PER_BLOCK] + q.result % RESULTS_PER_BLOCK;
+    const char *src = s->arena + q.ws.off + 4 * vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
+    if ((e = hipMemcpyAsync(dst, src, sizeof(SolveCtl), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+        return fail(s, e);
+    s->solve_result[q.ticket] = {q.result, q.outer};
+    return SILU_OK;
+}
+
 int silu_server_submit_solve(silu_server *s, int matrix_id, const double *b, double *x, double tol, int max_outer,
                              int m_L, int m_U, int64_t *ticket)
 {
@@ -692,17 +726,43 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         if (n_queued) *n_queued = (int)s->queue.size();
         return SILU_OK;
     }
+    // solve requests the device has stopped: no more sweeps; they finish with
+    // the next step, whose mark covers their last (skipped) sweeps and the copy
+    // of their state
+    {
+        size_t w = 0;
+        for (size_t i = 0; i < s->active.size(); i++) {
+            Request &q = s->active[i];
+            if (q.flag >= 0 && __atomic_load_n(&s->hflags[q.flag], __ATOMIC_ACQUIRE) != 0) {
+                const int st = save_result(s, q);
+                if (st) return st;
+                s->finish_step[q.ticket] = s->steps;
+                s->to_release.push_back({s->steps, q.ws});
+                s->to_report.push_back({s->steps, q.ticket});
+                s->force_mark = true;
+                continue;
+            }
+            s->active[w++] = s->active[i];
+        }
+        s->active.resize(w);
+    }
     // admission in arrival order while the workspace fits (no overtaking)
     while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
         Request &q = s->queue.front();
         Range r;
         if (!allocate(s, (size_t)silu_server_request_bytes(s, q.mid), &r)) break;
         q.ws = r;
-        if (q.tol > 0.0) { // a fresh SolveCtl: not stopped, no checks yet
+        if (q.tol > 0.0) { // a fresh SolveCtl: not stopped, no checks yet; and a clear host flag
             const size_t vb = vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
             const hipError_t e = launch_fill((int)(sizeof(SolveCtl) / 8), (double *)(s->arena + r.off + 4 * vb),
                                              0.0, nullptr, 0.0, s->stream);
             if (e != hipSuccess) return fail(s, e);
+            if (!s->free_flags.empty()) {
+                q.flag = s->free_flags.back();
+                s->free_flags.pop_back();
+                __atomic_store_n(&s->hflags[q.flag], 0, __ATOMIC_RELEASE);
+                s->ticket_flag[q.ticket] = q.flag;
+            }
         }
         s->active.push_back(q);
         s->queue.pop_front();
@@ -754,7 +814,8 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             const int64_t n = s->mats[(size_t)q.mid].A.n_rows;
             char *cb = s->arena + q.ws.off + 4 * vec_bytes(n);
             ca.c[ca.count++] = {(SolveCtl *)cb, (const double *)(cb + sizeof(SolveCtl)),
-                                (int)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS), q.op == 0 ? 1 : 0, q.tol};
+                                (int)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS), q.op == 0 ? 1 : 0, q.tol,
+                                q.flag >= 0 ? s->d_hflags + q.flag : nullptr};
             if (ca.count == SOLVE_CHECKS_PER_LAUNCH) {
                 if ((e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
                 ca.count = 0;
@@ -762,22 +823,11 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         }
         if (ca.count && (e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
         // a finishing solve request's state goes to pinned host memory before the mark
-        for (Request &q : s->active) {
-            if (q.tol <= 0.0 || q.op + 1 != q.total) continue;
-            if (s->nresults == (int64_t)s->result_blocks.size() * RESULTS_PER_BLOCK) {
-                SolveCtl *blk = nullptr;
-                if ((e = hipHostMalloc((void **)&blk, sizeof(SolveCtl) * RESULTS_PER_BLOCK)) != hipSuccess)
-                    return fail(s, e);
-                s->result_blocks.push_back(blk);
-            }
-            q.result = (int)s->nresults++;
-            SolveCtl *dst = s->result_blocks[(size_t)q.result / RESULTS_PER_BLOCK] + q.result % RESULTS_PER_BLOCK;
-            const char *src = s->arena + q.ws.off + 4 * vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
-            if ((e = hipMemcpyAsync(dst, src, sizeof(SolveCtl), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
-                return fail(s, e);
-            s->solve_result[q.ticket] = {q.result, q.outer};
-        }
+        for (Request &q : s->active)
+            if (q.tol > 0.0 && q.op + 1 == q.total && (st = save_result(s, q))) return st;
         const int64_t step = s->steps++;
+        finishing |= s->force_mark;
+        s->force_mark = false;
         if (slot < 0 && (finishing || step - s->last_mark_step >= MARK_EVERY) && (st = claim_mark(s, &slot)))
             return st;
         if (slot >= 0 && (st = record_mark(s, slot, step))) return st;
@@ -794,6 +844,13 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             }
         }
         s->active.resize(w);
+    } else if (s->force_mark) { // stopped solve requests and nothing to launch: an empty step ends them
+        s->force_mark = false;
+        const int64_t step = s->steps++;
+        int slot;
+        int st = claim_mark(s, &slot);
+        if (!st) st = record_mark(s, slot, step);
+        if (st) return st;
     }
     if (n_active) *n_active = (int)s->active.size();
     if (n_queued) *n_queued = (int)s->queue.size();

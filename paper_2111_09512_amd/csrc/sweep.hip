@@ -453,7 +453,13 @@ __global__ void __launch_bounds__(256) k_solve_check(SolveCheckArgs ca)
         ctl->rr = red[0][0];
         ctl->bb = b2;
         ctl->checks = ctl->checks + 1;
-        if (sqrt(red[0][0]) / sqrt(b2) < c.tol) ctl->stop = 1;
+        if (sqrt(red[0][0]) / sqrt(b2) < c.tol) {
+            ctl->stop = 1;
+            if (c.hflag) { // tells the host, which then schedules no more sweeps for the request
+                __threadfence_system();
+                *(volatile int32_t *)c.hflag = 1;
+            }
+        }
     }
 }
 

@@ -475,3 +475,31 @@ def test_solve_requests_match_the_oracle(orc, B, ctx, pool):
         server.submit_solve(mids[0], dev(W.rhs(pool[0]["A"].n, 1)), dev(np.zeros(pool[0]["A"].n)), 0.0, 5, 3, 3)
     assert e.value.status == -1
     server.close()
+
+
+def test_solve_request_finishes_when_converged(orc, B, ctx, pool):
+    """A solve request with a step limit far beyond what it needs is retired
+    a few steps after the device's check passes (the host reads the request's
+    stop flag), not after max_outer steps; with and without other work in the
+    server, and the result still equals the oracle's."""
+    say("serving: solve request retired when converged")
+    p = pool[0]
+    n = p["A"].n
+    b = W.rhs(n, 11)
+    k_ref, x_ref, _ = orc.smooth_until(p["A"], p["Ls"], p["Us"], p["dinv"], b, np.zeros(n), 3, 3, 1e-6, 1 << 20)
+    assert k_ref < 100
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=8)
+    mid = server.register(p["Ad"], p["F"])
+    other = server.register(pool[4]["Ad"], pool[4]["F"])
+    for busy in (False, True):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        t = server.submit_solve(mid, dev(b), x, 1e-6, 1 << 20, 3, 3)
+        if busy:
+            n4 = pool[4]["A"].n
+            server.submit(other, dev(W.rhs(n4, 3)), torch.zeros(n4, dtype=torch.float64, device="cuda"), 4, 3, 3)
+        steps = _drain(server, [t], max_steps=5 * k_ref + 200)
+        assert steps <= 5 * k_ref + 40
+        k, _ = server.solve_result(t)
+        assert k == k_ref
+        np.testing.assert_array_equal(host(x), x_ref)
+    server.close()
