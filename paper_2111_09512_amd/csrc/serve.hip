@@ -116,7 +116,7 @@ struct silu_server {
     std::vector<SolveCtl *> result_blocks; // pinned, RESULTS_PER_BLOCK each
     int64_t nresults = 0;
     std::map<int64_t, std::pair<int64_t, int>> solve_result; // ticket -> (result slot, max outer steps)
-    int32_t *hflags = nullptr;                  // pinned stop flags of solve requests (max_active words)
+    int32_t *hflags = nullptr;                  // pinned stop flags of solve requests (2 max_active words)
     int32_t *d_hflags = nullptr;                // the same words as the device addresses them
     std::vector<int> free_flags;
     std::map<int64_t, int> ticket_flag;         // ticket -> flag word, until the request is reported done
@@ -561,12 +561,17 @@ int silu_server_create(silu_ctx *ctx, void *hip_stream, void *arena, size_t aren
             return SILU_ERR_HIP;
         }
     }
-    if (grow(s, 64) || hipHostMalloc((void **)&s->hflags, sizeof(int32_t) * (size_t)max_active) != hipSuccess ||
+    // stop-flag words: one per running solve request, held until it is reported
+    // done (twice max_active, so that finished requests not yet reaped leave
+    // words for new ones; without a word a request still runs, only not retired
+    // early)
+    const size_t nflags = 2 * (size_t)max_active;
+    if (grow(s, 64) || hipHostMalloc((void **)&s->hflags, sizeof(int32_t) * nflags) != hipSuccess ||
         hipHostGetDevicePointer((void **)&s->d_hflags, s->hflags, 0) != hipSuccess) {
         silu_server_destroy(s);
         return SILU_ERR_HIP;
     }
-    for (int i = max_active - 1; i >= 0; i--) s->free_flags.push_back(i);
+    for (size_t i = nflags; i-- > 0;) s->free_flags.push_back((int)i);
     *out = s;
     return SILU_OK;
 }
