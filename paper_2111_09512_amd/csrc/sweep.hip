@@ -406,22 +406,26 @@ __device__ __forceinline__ void batch_tile(const SweepArgs &a, int tile)
         }
     }
     if (!a.scheck) return;
-    __shared__ double red[2][256];
+    // butterfly sums within each wave (every lane ends with the same bits:
+    // both operands of each addition are the same on all lanes), then the
+    // four wave sums in order
+    __shared__ double wsum[2][4];
     const int tid = (int)threadIdx.x, row = tile * 256 + tid;
-    red[0][tid] = t * t;
     double bv = 0.0;
     if (a.scheck == 2 && row < a.n) bv = ((const double *)a.rhs)[row];
-    red[1][tid] = bv * bv;
-    for (int off = 128; off > 0; off >>= 1) {
-        __syncthreads();
-        if (tid < off) {
-            red[0][tid] = red[0][tid] + red[0][tid + off];
-            red[1][tid] = red[1][tid] + red[1][tid + off];
-        }
+    double r2 = t * t, b2 = bv * bv;
+    for (int off = 32; off > 0; off >>= 1) {
+        r2 = r2 + __shfl_xor(r2, off, 64);
+        b2 = b2 + __shfl_xor(b2, off, 64);
     }
+    if ((tid & 63) == 0) {
+        wsum[0][tid >> 6] = r2;
+        wsum[1][tid >> 6] = b2;
+    }
+    __syncthreads();
     if (tid == 0) {
-        a.spart[2 * tile] = red[0][0];
-        a.spart[2 * tile + 1] = red[1][0];
+        a.spart[2 * tile] = ((wsum[0][0] + wsum[0][1]) + wsum[0][2]) + wsum[0][3];
+        a.spart[2 * tile + 1] = ((wsum[1][0] + wsum[1][1]) + wsum[1][2]) + wsum[1][3];
     }
 }
 
@@ -468,32 +472,66 @@ __global__ void __launch_bounds__(256) k_solve_check(SolveCheckArgs ca)
 // workgroups [first[i], first[i+1]); each workgroup finds its op by binary
 // search and runs exactly the single-request body, so a request's result does
 // not depend on what else shares the launch.
-template <class T>
-__global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *__restrict__ ops,
-                                                     const int32_t *__restrict__ first, int nops)
+// The op owning workgroup b: the largest i < nops with first[i] <= b (first
+// increases strictly from first[0] = 0).  Up to 64 ops each lane of the wave
+// tests one entry and a ballot counts those at or below b, so the wave issues
+// one load instead of a chain of dependent ones; beyond that, bisection.
+__device__ __forceinline__ int find_op(const int32_t *first, int nops, int b)
 {
-    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
-    int lo = 0, hi = nops - 1; // largest i with first[i] <= b
+    if (nops <= 64) {
+        const int lane = (int)threadIdx.x & 63;
+        bool le = false;
+        if (lane < nops) le = first[lane] <= b; // lanes past the table load nothing
+        return __popcll(__ballot(le)) - 1;
+    }
+    int lo = 0, hi = nops - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (first[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    batch_tile<T>(ops[lo], b - first[lo]);
+    return lo;
 }
 
-// The same with the op table in the kernel arguments.
 template <class T>
-__global__ void __launch_bounds__(256) k_sweep_batch_args(BatchArgs ba)
+__global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *__restrict__ ops,
+                                                     const int32_t *__restrict__ first, int nops)
 {
     const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
-    int lo = 0, hi = ba.nops - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (ba.first[mid] <= b) lo = mid;
-        else hi = mid - 1;
+    const int i = find_op(first, nops, b);
+    batch_tile<T>(ops[i], b - first[i]);
+}
+
+// The same with the op table in the kernel arguments, sized for at most CAP
+// ops (the argument block is copied at every launch, so small batches use a
+// small one).
+template <int CAP>
+struct BatchArgsN {
+    SweepArgs op[CAP];
+    int32_t first[CAP + 1];
+    int nops;
+};
+
+template <class T, int CAP>
+__global__ void __launch_bounds__(256) k_sweep_batch_args(BatchArgsN<CAP> ba)
+{
+    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int i = find_op(ba.first, ba.nops, b);
+    batch_tile<T>(ba.op[i], b - ba.first[i]);
+}
+
+template <int CAP>
+hipError_t go_batch_args(const BatchArgs &b, hipStream_t s)
+{
+    BatchArgsN<CAP> n;
+    for (int i = 0; i < b.nops; i++) {
+        n.op[i] = b.op[i];
+        n.first[i] = b.first[i];
     }
-    batch_tile<T>(ba.op[lo], b - ba.first[lo]);
+    n.first[b.nops] = b.first[b.nops];
+    n.nops = b.nops;
+    hipLaunchKernelGGL((k_sweep_batch_args<TF64, CAP>), dim3(b.first[b.nops]), dim3(256), 0, s, n);
+    return hipGetLastError();
 }
 
 // Persistent batched CSR-stream: one launch runs whole chains of sweeps (all
@@ -864,8 +902,9 @@ hipError_t launch_sweep_batch(const SweepArgs *d_ops, const int32_t *d_first, in
 hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s)
 {
     if (b.nops <= 0 || b.nops > BATCH_ARG_OPS || b.first[b.nops] <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep_batch_args<TF64>), dim3(b.first[b.nops]), dim3(256), 0, s, b);
-    return hipGetLastError();
+    if (b.nops <= 2) return go_batch_args<2>(b, s);
+    if (b.nops <= 8) return go_batch_args<8>(b, s);
+    return go_batch_args<BATCH_ARG_OPS>(b, s);
 }
 
 hipError_t launch_solve_check(const SolveCheckArgs &a, hipStream_t s)
