@@ -503,3 +503,29 @@ def test_solve_request_finishes_when_converged(orc, B, ctx, pool):
         assert k == k_ref
         np.testing.assert_array_equal(host(x), x_ref)
     server.close()
+
+
+def test_more_than_64_requests_in_one_step(B, ctx, pool):
+    """Over 64 requests active at once (the launch finds a workgroup's op by
+    bisection there, by one ballot per wave up to 64): each result equals the
+    request alone."""
+    say("serving: > 64 active requests")
+    server = B.Server(ctx, arena_bytes=256 << 20, max_active=160)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    reqs = []
+    for k in range(150):
+        mid = k % 3  # the small matrices, so that all fit at once
+        n = pool[mid]["A"].n
+        reqs.append(dict(mid=mid, b=W.rhs(n, 1000 + k), x0=W.rhs(n, 2000 + k) * (k % 3 == 0), outer=1 + k % 3,
+                         mL=3, mU=3))
+    xs, tickets = [], []
+    for r in reqs:
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
+    a, q = server.step()
+    assert a > 64 and q == 0
+    _drain(server, tickets)
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
+    server.close()
