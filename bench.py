@@ -208,7 +208,48 @@ def bench_serving(torch, B, ctx, arena_mb):
         f"p99 {res['batched_two_lanes']['p99_ms']:.2f} ms; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
         f"p99 {res['one_at_a_time']['p99_ms']:.2f} ms {res['one_at_a_time']['apps_per_s']:.0f} apps/s; "
         f"identical={same} {same_l}")
+    res["solve_requests"] = bench_solve_requests(torch, B, ctx)
     return res
+
+
+def bench_solve_requests(torch, B, ctx):
+    """64 solve requests (the smoother iterated until eq. relres < 1e-6, at most 400
+    outer steps of 3/3) on 7-point Poisson matrices of 16^3 and 24^3 rows, all
+    submitted at once: time from submission to completion (a converged request is
+    retired a few steps after its device-side check) and the outer-step counts."""
+    from paper_2111_09512_amd import serve as S
+    from paper_2111_09512_amd import workloads as W
+
+    mats = []
+    for N in (16, 24):
+        A = W.poisson7(N)
+        L, U = B.factor_iluk(A, 0)
+        Ad = B.Csr.from_host(A)
+        mats.append((Ad, ctx.ilu_scale_factors(B.Csr.from_host(L), B.Csr.from_host(U)), A.n))
+    server = B.Server(ctx, arena_bytes=256 << 20, max_active=64)
+    mids = [server.register(Ad, F) for (Ad, F, _) in mats]
+    bs = [torch.from_numpy(W.rhs(mats[k % 2][2], 500 + k)).cuda() for k in range(64)]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    with gc_paused():
+        t0 = time.perf_counter()
+        tickets = [server.submit_solve(mids[k % 2], bs[k], xs[k], 1e-6, 400, 3, 3) for k in range(64)]
+        done_at = {}
+        while len(done_at) < len(tickets):
+            server.step()
+            now = time.perf_counter() - t0
+            for t in server.completed():
+                done_at[t] = now
+    lat = np.array([done_at[t] for t in tickets])
+    steps = np.array([server.solve_result(t)[0] for t in tickets])
+    rel = np.array([server.solve_result(t)[1] for t in tickets])
+    server.close()
+    out = {"requests": 64, "tol": 1e-6, "max_outer": 400, "m": 3, "sides": [16, 24],
+           "outer_steps_min": int(steps.min()), "outer_steps_max": int(steps.max()),
+           "all_converged": bool((steps <= 400).all() and (rel < 1e-6).all()), **S.percentiles(lat)}
+    log(f"serving solve requests: 64 at once, outer steps {steps.min()}-{steps.max()}, all converged "
+        f"{out['all_converged']}, completion p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms")
+    return out
 
 
 def main():
