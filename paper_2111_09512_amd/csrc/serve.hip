@@ -1,17 +1,20 @@
-// Serving runtime: continuous batching of smoother requests on resident
-// matrices (the serving form of the scaled-ILU smoother).
+// Serving runtime: continuous batching of smoother and solve requests on
+// resident matrices (the serving form of the scaled-ILU smoother).
 //
 // Each request is the op sequence of `outer` smoothing steps of eq.
 // ILUsplit / Algorithm 2: a residual sweep on A, m_L - 1 sweeps on Ls (the
 // last fused with D^{-1}), m_U - 1 sweeps on U~s (the last fused with the
-// update of x).  A step admits queued requests in arrival order while their
-// workspace fits in the caller's arena, then launches ONE batched kernel that
-// advances every active request by one op, whatever op each is at (with up to
-// 24 active requests the op table goes in the kernel arguments, else it is
-// copied to the device first).  A request's workspace returns to the arena
-// once the GPU has passed its last launch.  Each row is summed by one lane in
-// a fixed order, so a request's result does not depend on which requests
-// shared its launches.
+// update of x); a solve request adds a final residual and makes every
+// residual a convergence check (eq. relres).  A step admits queued requests
+// in arrival order while their workspace fits in the caller's arena, then
+// launches ONE batched kernel that advances every active request by one op,
+// whatever op each is at (with up to 24 active requests the op table goes in
+// the kernel arguments, else it is copied to the device first), through the
+// server's sliced copies of the matrices; a small second launch closes the
+// step's convergence checks.  A request's workspace returns to the arena once
+// the GPU has passed its last launch (known from events recorded at the
+// steps that need one).  Each row is summed by one lane in a fixed order, so
+// a request's result does not depend on which requests shared its launches.
 //
 // Persistent mode (switched off, see PERSISTENT_AVAILABLE): a step would hand
 // the requests it admits, with all of their ops, to one persistent launch
@@ -35,7 +38,7 @@ using namespace silu;
 
 namespace {
 
-constexpr int RING = 8;        // op-table staging slots = steps in flight
+constexpr int RING = 8;        // events and op-table staging slots
 constexpr int SERVE_RPB = SERVE_TILE_ROWS; // rows per workgroup of the batched sweep
 constexpr int PSTREAMS = 3;    // persistent mode: streams the launches rotate over
 constexpr int DEFAULT_MAX_WG = 1024;
