@@ -540,6 +540,15 @@ int silu_server_register(silu_server *server, const silu_csr *A, const silu_fact
 int64_t silu_server_request_bytes(const silu_server *server, int matrix_id);
 int silu_server_submit(silu_server *server, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
                        int64_t *ticket);
+/* The same with flags: 0, or SILU_MIXED for the FP32-inner form of
+ * ilu_smooth (the L and U~ sweeps on FP32 copies of the factor values, the
+ * residual and the update of x in FP64), bit-identical to that call.  The
+ * matrix must have been registered with factors that carry FP32 values
+ * (register then also builds their sliced copies); UNSUPPORTED otherwise, or
+ * outside the stepwise mode.  Each step launches one batch per precision
+ * present. */
+int silu_server_submit_flags(silu_server *server, int matrix_id, const double *b, double *x, int outer, int m_L,
+                             int m_U, int flags, int64_t *ticket);
 /*
  * A solve request: the smoother iterated until the relative residual of eq.
  * relres, ||b - A x|| / ||b||, falls below tol, checked for the initial x and

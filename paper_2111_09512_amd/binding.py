@@ -127,6 +127,8 @@ _sig = {
     "silu_server_register": (C.c_int, [_P, C.POINTER(silu_csr), C.POINTER(silu_factors), C.POINTER(C.c_int)]),
     "silu_server_request_bytes": (C.c_int64, [_P, C.c_int]),
     "silu_server_submit": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int64)]),
+    "silu_server_submit_flags": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int,
+                                           C.POINTER(C.c_int64)]),
     "silu_server_submit_solve": (C.c_int, [_P, C.c_int, _P, _P, C.c_double, C.c_int, C.c_int, C.c_int,
                                            C.POINTER(C.c_int64)]),
     "silu_server_solve_result": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
@@ -708,10 +710,17 @@ class Server:
     def request_bytes(self, mid: int) -> int:
         return int(_lib.silu_server_request_bytes(self._h, mid))
 
-    def submit(self, mid: int, b: torch.Tensor, x: torch.Tensor, outer: int, m_L: int, m_U: int) -> int:
+    def submit(self, mid: int, b: torch.Tensor, x: torch.Tensor, outer: int, m_L: int, m_U: int,
+               mixed: bool = False) -> int:
+        """A smoother request; mixed: the FP32-inner form (factors with FP32 values)."""
         t = C.c_int64()
-        self._check(_lib.silu_server_submit(self._h, mid, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), outer,
-                                            m_L, m_U, C.byref(t)), "silu_server_submit")
+        if mixed:
+            self._check(_lib.silu_server_submit_flags(self._h, mid, C.c_void_p(b.data_ptr()),
+                                                      C.c_void_p(x.data_ptr()), outer, m_L, m_U, SILU_MIXED,
+                                                      C.byref(t)), "silu_server_submit_flags")
+        else:
+            self._check(_lib.silu_server_submit(self._h, mid, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                                                outer, m_L, m_U, C.byref(t)), "silu_server_submit")
         self._req[t.value] = (b, x)
         return t.value
 

@@ -931,13 +931,14 @@ int check_finite(silu_ctx *c, int64_t n, const double *x)
 
 namespace silu {
 
-int make_owned_sliced(silu_ctx *c, const silu_csr *N, SlicedView *view, void **owner)
+int make_owned_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, SlicedView *view, void **owner)
 {
     *view = SlicedView();
     *owner = nullptr;
+    if (vbytes != 8 && vbytes != 4) return SILU_ERR_ARG;
     Sliced *S = new (std::nothrow) Sliced();
     if (!S) return SILU_ERR_NOMEM;
-    const int st = build_sliced(c, N, N->val, 8, 1, *S);
+    const int st = build_sliced(c, N, val, vbytes, 1, *S);
     if (st || !S->ok) {
         free_sliced(*S);
         delete S;

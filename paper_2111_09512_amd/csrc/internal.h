@@ -197,20 +197,23 @@ constexpr int WIN_MAX_SLOTS = 3072;
 
 SweepGeom pick_geom(int64_t n, int64_t nnz, int flags);
 
-// A sliced-ELL copy of N's FP64 values owned by the caller (the serving
-// runtime), outside the context's cache, so that releasing cached layouts
-// never frees it.  view->nslice stays 0 (and *owner null) when N is better
-// streamed as CSR.  free_owned_sliced frees it; null is ignored.
-int make_owned_sliced(silu_ctx *c, const silu_csr *N, SlicedView *view, void **owner);
+// A sliced-ELL copy of N with the values `val` (vbytes 8: FP64, 4: FP32)
+// owned by the caller (the serving runtime), outside the context's cache, so
+// that releasing cached layouts never frees it.  view->nslice stays 0 (and
+// *owner null) when N is better streamed as CSR.  free_owned_sliced frees it;
+// null is ignored.
+int make_owned_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, SlicedView *view, void **owner);
 void free_owned_sliced(void *owner);
 hipError_t launch_sweep(Prec p, const SweepGeom &g, const SweepArgs &a, hipStream_t s, const char **name);
 
-// Batched FP64 sweeps (serving): d_ops[i] is one request's sweep, d_first[i]
-// its first workgroup (ceil(n_i / SERVE_TILE_ROWS) workgroups each), total
-// the sum.  Both arrays live in device memory.  An op whose sv points to a
-// sliced copy (device memory) is swept through it, else as a CSR stream.
+// Batched sweeps of one precision (serving): d_ops[i] is one request's sweep,
+// d_first[i] its first workgroup (ceil(n_i / SERVE_TILE_ROWS) workgroups
+// each), total the sum.  Both arrays live in device memory.  An op whose sv
+// points to a sliced copy (device memory) is swept through it, else as a CSR
+// stream.
 constexpr int SERVE_TILE_ROWS = 256;
-hipError_t launch_sweep_batch(const SweepArgs *d_ops, const int32_t *d_first, int nops, int total, hipStream_t s);
+hipError_t launch_sweep_batch(Prec p, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
+                              hipStream_t s);
 // The same with the op table passed in the kernel arguments (no copy to the
 // device first): at most BATCH_ARG_OPS ops.
 constexpr int BATCH_ARG_OPS = 24;
@@ -219,7 +222,7 @@ struct BatchArgs {
     int32_t first[BATCH_ARG_OPS + 1];
     int nops;
 };
-hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s);
+hipError_t launch_sweep_batch_args(Prec p, const BatchArgs &b, hipStream_t s);
 
 // Persistent batched FP64 CSR-stream sweeps (serving): one launch runs chains
 // of dependent sweeps.  Op i covers tiles [first[i], first[i+1]) of

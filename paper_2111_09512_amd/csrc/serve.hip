@@ -56,19 +56,21 @@ constexpr int MAX_AHEAD = 8;
 struct Matrix {
     silu_csr A;
     silu_factors F;
-    // the server's own sliced copies of A, Ls, Us (device views; null where
-    // the CSR stream is used) and their owners
-    const SlicedView *sv[3] = {nullptr, nullptr, nullptr};
-    void *own[3] = {nullptr, nullptr, nullptr};
+    // the server's own sliced copies (device views; null where the CSR stream
+    // is used) and their owners: A, Ls, Us, then Ls and Us with their FP32
+    // values (when the factors carry them: the FP32-inner form)
+    const SlicedView *sv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    void *own[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     SlicedView *d_views = nullptr;
+    bool fp32 = false; // the factors carry FP32 values
 };
 
 void free_matrix_copies(Matrix &M)
 {
-    for (int k = 0; k < 3; k++) free_owned_sliced(M.own[k]);
+    for (int k = 0; k < 5; k++) free_owned_sliced(M.own[k]);
     (void)hipFree(M.d_views);
     M.d_views = nullptr;
-    for (int k = 0; k < 3; k++) {
+    for (int k = 0; k < 5; k++) {
         M.own[k] = nullptr;
         M.sv[k] = nullptr;
     }
@@ -89,6 +91,7 @@ struct Request {
     double tol = 0.0; // > 0: a solve request (outer = its largest number of outer steps)
     int result = -1;  // solve requests: slot of its SolveCtl copy in the pinned result blocks
     int flag = -1;    // solve requests: its word in the pinned stop flags
+    bool mixed = false; // the FP32-inner form
 };
 
 size_t vec_bytes(int64_t n) { return (((size_t)n * 8 + 255) / 256) * 256; }
@@ -262,7 +265,7 @@ void reap(silu_server *s)
 }
 
 // The op request q runs at its current position.
-SweepArgs op_of(const silu_server *s, const Request &q)
+SweepArgs op_of(const silu_server *s, const Request &q, Prec *prec = nullptr)
 {
     const Matrix &M = s->mats[(size_t)q.mid];
     const int64_t n = M.A.n_rows;
@@ -272,6 +275,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
     const int per = 1 + (q.mL - 1) + (q.mU - 1);
     const int j = q.op % per;
     SweepArgs a;
+    Prec p = Prec::F64;
     a.n = (int)n;
     a.dinv = M.F.dinv;
     a.x = q.x;
@@ -291,13 +295,15 @@ SweepArgs op_of(const silu_server *s, const Request &q)
         } else {
             a.epi = EPI_SCALE;
             a.out = sv;
+            p = q.mixed ? Prec::MIX_RES : Prec::F64; // FP32-inner: the residual rounded before D^{-1}
         }
     } else if (j < q.mL) { // L sweep k = j + 1
         const int k = j + 1;
         a.rp = M.F.Ls.row_ptr;
         a.col = M.F.Ls.col_idx;
-        a.val = M.F.Ls.val;
-        a.sv = M.sv[1];
+        a.val = q.mixed ? (const void *)M.F.Ls_val32 : M.F.Ls.val;
+        a.sv = M.sv[q.mixed ? 3 : 1];
+        if (q.mixed) p = k == 2 ? Prec::MIX_L1 : Prec::MIX_L; // the first gathers r and rounds it
         a.xin = k == 2 ? (const void *)r : (const void *)tmp[(k - 1) & 1];
         a.rhs = r;
         if (k < q.mL) {
@@ -313,8 +319,9 @@ SweepArgs op_of(const silu_server *s, const Request &q)
         const int k = j - q.mL + 2;
         a.rp = M.F.Us.row_ptr;
         a.col = M.F.Us.col_idx;
-        a.val = M.F.Us.val;
-        a.sv = M.sv[2];
+        a.val = q.mixed ? (const void *)M.F.Us_val32 : M.F.Us.val;
+        a.sv = M.sv[q.mixed ? 4 : 2];
+        if (q.mixed) p = Prec::MIX_U;
         a.xin = k == 2 ? (const void *)sv : (const void *)tmp[(k - 1) & 1];
         a.rhs = sv;
         if (k < q.mU) {
@@ -332,6 +339,7 @@ SweepArgs op_of(const silu_server *s, const Request &q)
             a.scheck = q.op == 0 ? 2 : 1;
         }
     }
+    if (prec) *prec = p;
     return a;
 }
 
@@ -610,10 +618,14 @@ int silu_server_register(silu_server *s, const silu_csr *A, const silu_factors *
     Matrix M;
     M.A = *A;
     M.F = *F;
-    const silu_csr *parts[3] = {A, &F->Ls, &F->Us};
-    SlicedView views[3];
+    M.fp32 = (F->Ls.nnz == 0 || F->Ls_val32) && (F->Us.nnz == 0 || F->Us_val32);
+    const silu_csr *parts[5] = {A, &F->Ls, &F->Us, &F->Ls, &F->Us};
+    const void *vals[5] = {A->val, F->Ls.val, F->Us.val, F->Ls_val32, F->Us_val32};
+    SlicedView views[5];
     int st = SILU_OK;
-    for (int k = 0; k < 3 && st == SILU_OK; k++) st = make_owned_sliced(s->ctx, parts[k], &views[k], &M.own[k]);
+    for (int k = 0; k < 5 && st == SILU_OK; k++)
+        if (k < 3 || (M.fp32 && vals[k]))
+            st = make_owned_sliced(s->ctx, parts[k], vals[k], k < 3 ? 8 : 4, &views[k], &M.own[k]);
     hipError_t e = hipSuccess;
     if (st == SILU_OK) {
         e = hipMalloc((void **)&M.d_views, sizeof(views));
@@ -623,7 +635,7 @@ int silu_server_register(silu_server *s, const silu_csr *A, const silu_factors *
         free_matrix_copies(M);
         return st != SILU_OK ? st : fail(s, e);
     }
-    for (int k = 0; k < 3; k++) M.sv[k] = views[k].nslice > 0 ? M.d_views + k : nullptr;
+    for (int k = 0; k < 5; k++) M.sv[k] = views[k].nslice > 0 ? M.d_views + k : nullptr;
     s->mats.push_back(M);
     *matrix_id = (int)s->mats.size() - 1;
     return SILU_OK;
@@ -673,6 +685,20 @@ int save_result(silu_server *s, Request &q)
     if ((e = hipMemcpyAsync(dst, src, sizeof(SolveCtl), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
         return fail(s, e);
     s->solve_result[q.ticket] = {q.result, q.outer};
+    return SILU_OK;
+}
+
+int silu_server_submit_flags(silu_server *s, int matrix_id, const double *b, double *x, int outer, int m_L, int m_U,
+                             int flags, int64_t *ticket)
+{
+    if (!s || (flags & ~SILU_MIXED)) return SILU_ERR_ARG;
+    const bool mixed = (flags & SILU_MIXED) != 0;
+    if (mixed && (s->mode != 0 || matrix_id < 0 || matrix_id >= (int)s->mats.size() ||
+                  !s->mats[(size_t)matrix_id].fp32))
+        return matrix_id < 0 || matrix_id >= (int)s->mats.size() ? SILU_ERR_ARG : SILU_ERR_UNSUPPORTED;
+    const int st = silu_server_submit(s, matrix_id, b, x, outer, m_L, m_U, ticket);
+    if (st) return st;
+    s->queue.back().mixed = mixed;
     return SILU_OK;
 }
 
@@ -777,41 +803,61 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
     }
     if (!s->active.empty()) {
         const int nops = (int)s->active.size();
-        const bool staged = nops > BATCH_ARG_OPS;
-        int st = staged ? grow(s, nops) : SILU_OK;
+        // the step's ops, one launch per precision present (the ops of different
+        // requests are independent, so their launch order does not matter)
+        std::vector<SweepArgs> ops((size_t)nops);
+        std::vector<Prec> prec((size_t)nops);
+        for (int i = 0; i < nops; i++) ops[(size_t)i] = op_of(s, s->active[(size_t)i], &prec[(size_t)i]);
+        static const Prec kinds[5] = {Prec::F64, Prec::MIX_RES, Prec::MIX_L1, Prec::MIX_L, Prec::MIX_U};
+        int count[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < nops; i++)
+            for (int g = 0; g < 5; g++) count[g] += prec[(size_t)i] == kinds[g];
+        bool staged = false;
+        for (int g = 0; g < 5; g++) staged |= count[g] > BATCH_ARG_OPS;
+        int st = staged ? grow(s, nops + 5) : SILU_OK;
         if (st) return st;
         if ((st = throttle(s))) return st;
         int slot = -1;
         if (staged && (st = claim_mark(s, &slot))) return st; // its staging buffers are free
         bool finishing = false;
         for (const Request &q : s->active) finishing |= q.op + 1 == q.total;
-        hipError_t e;
-        if (!staged) { // the op table travels in the kernel arguments
-            BatchArgs ba;
-            int total = 0;
-            for (int i = 0; i < nops; i++) {
-                ba.op[i] = op_of(s, s->active[(size_t)i]);
-                ba.first[i] = total;
-                total += (ba.op[i].n + SERVE_RPB - 1) / SERVE_RPB;
-            }
-            ba.first[nops] = total;
-            ba.nops = nops;
-            e = launch_sweep_batch_args(ba, s->stream);
-        } else {
-            SweepArgs *ops = s->h_ops[slot];
-            int32_t *first = s->h_first[slot];
-            int total = 0;
-            for (int i = 0; i < nops; i++) {
-                ops[i] = op_of(s, s->active[(size_t)i]);
-                first[i] = total;
-                total += (ops[i].n + SERVE_RPB - 1) / SERVE_RPB;
-            }
-            first[nops] = total;
-            e = hipMemcpyAsync(s->d_ops, ops, sizeof(SweepArgs) * (size_t)nops, hipMemcpyHostToDevice, s->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s->d_first, first, sizeof(int32_t) * (size_t)(nops + 1), hipMemcpyHostToDevice,
+        hipError_t e = hipSuccess;
+        int off_ops = 0, off_first = 0; // packing of the staged groups
+        for (int g = 0; g < 5 && e == hipSuccess; g++) {
+            if (!count[g]) continue;
+            if (count[g] <= BATCH_ARG_OPS) { // the op table travels in the kernel arguments
+                BatchArgs ba;
+                int k = 0, total = 0;
+                for (int i = 0; i < nops; i++) {
+                    if (prec[(size_t)i] != kinds[g]) continue;
+                    ba.op[k] = ops[(size_t)i];
+                    ba.first[k++] = total;
+                    total += (ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
+                }
+                ba.first[k] = total;
+                ba.nops = k;
+                e = launch_sweep_batch_args(kinds[g], ba, s->stream);
+            } else { // through this step's staging buffers, copied to the device tables
+                SweepArgs *h_ops = s->h_ops[slot] + off_ops;
+                int32_t *h_first = s->h_first[slot] + off_first;
+                int k = 0, total = 0;
+                for (int i = 0; i < nops; i++) {
+                    if (prec[(size_t)i] != kinds[g]) continue;
+                    h_ops[k] = ops[(size_t)i];
+                    h_first[k++] = total;
+                    total += (ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
+                }
+                h_first[k] = total;
+                e = hipMemcpyAsync(s->d_ops + off_ops, h_ops, sizeof(SweepArgs) * (size_t)k, hipMemcpyHostToDevice,
                                    s->stream);
-            if (e == hipSuccess) e = launch_sweep_batch(s->d_ops, s->d_first, nops, total, s->stream);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(s->d_first + off_first, h_first, sizeof(int32_t) * (size_t)(k + 1),
+                                       hipMemcpyHostToDevice, s->stream);
+                if (e == hipSuccess)
+                    e = launch_sweep_batch(kinds[g], s->d_ops + off_ops, s->d_first + off_first, k, total, s->stream);
+                off_ops += k;
+                off_first += k + 1;
+            }
         }
         if (e != hipSuccess) return fail(s, e);
         // close the convergence checks of solve requests made in this launch

@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(256) k_sweep_batch_args(BatchArgsN<CAP> ba)
     batch_tile<T>(ba.op[i], b - ba.first[i]);
 }
 
-template <int CAP>
+template <class T, int CAP>
 hipError_t go_batch_args(const BatchArgs &b, hipStream_t s)
 {
     BatchArgsN<CAP> n;
@@ -530,8 +530,16 @@ hipError_t go_batch_args(const BatchArgs &b, hipStream_t s)
     }
     n.first[b.nops] = b.first[b.nops];
     n.nops = b.nops;
-    hipLaunchKernelGGL((k_sweep_batch_args<TF64, CAP>), dim3(b.first[b.nops]), dim3(256), 0, s, n);
+    hipLaunchKernelGGL((k_sweep_batch_args<T, CAP>), dim3(b.first[b.nops]), dim3(256), 0, s, n);
     return hipGetLastError();
+}
+
+template <class T>
+hipError_t go_batch_args_sized(const BatchArgs &b, hipStream_t s)
+{
+    if (b.nops <= 2) return go_batch_args<T, 2>(b, s);
+    if (b.nops <= 8) return go_batch_args<T, 8>(b, s);
+    return go_batch_args<T, BATCH_ARG_OPS>(b, s);
 }
 
 // Persistent batched CSR-stream: one launch runs whole chains of sweeps (all
@@ -892,19 +900,36 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
     return g;
 }
 
-hipError_t launch_sweep_batch(const SweepArgs *d_ops, const int32_t *d_first, int nops, int total, hipStream_t s)
+hipError_t launch_sweep_batch(Prec p, const SweepArgs *d_ops, const int32_t *d_first, int nops, int total,
+                              hipStream_t s)
 {
     if (nops <= 0 || total <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sweep_batch<TF64>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops);
+    switch (p) {
+    case Prec::F64: hipLaunchKernelGGL((k_sweep_batch<TF64>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops); break;
+    case Prec::MIX_RES:
+        hipLaunchKernelGGL((k_sweep_batch<TMixRes>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops);
+        break;
+    case Prec::MIX_L1:
+        hipLaunchKernelGGL((k_sweep_batch<TMixL1>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops);
+        break;
+    case Prec::MIX_L: hipLaunchKernelGGL((k_sweep_batch<TMixL>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops); break;
+    case Prec::MIX_U: hipLaunchKernelGGL((k_sweep_batch<TMixU>), dim3(total), dim3(256), 0, s, d_ops, d_first, nops); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_batch_args(const BatchArgs &b, hipStream_t s)
+hipError_t launch_sweep_batch_args(Prec p, const BatchArgs &b, hipStream_t s)
 {
     if (b.nops <= 0 || b.nops > BATCH_ARG_OPS || b.first[b.nops] <= 0) return hipSuccess;
-    if (b.nops <= 2) return go_batch_args<2>(b, s);
-    if (b.nops <= 8) return go_batch_args<8>(b, s);
-    return go_batch_args<BATCH_ARG_OPS>(b, s);
+    switch (p) {
+    case Prec::F64: return go_batch_args_sized<TF64>(b, s);
+    case Prec::MIX_RES: return go_batch_args_sized<TMixRes>(b, s);
+    case Prec::MIX_L1: return go_batch_args_sized<TMixL1>(b, s);
+    case Prec::MIX_L: return go_batch_args_sized<TMixL>(b, s);
+    case Prec::MIX_U: return go_batch_args_sized<TMixU>(b, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_solve_check(const SolveCheckArgs &a, hipStream_t s)

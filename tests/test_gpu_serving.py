@@ -529,3 +529,56 @@ def test_more_than_64_requests_in_one_step(B, ctx, pool):
     for i, r in enumerate(reqs):
         np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
     server.close()
+
+
+def test_fp32_inner_requests_equal_the_single_call(orc, B, ctx):
+    """FP32-inner requests (L and U~ sweeps on FP32 factor values) mixed in the
+    same steps with FP64 ones, on sliced and streamed matrices: each equals
+    ilu_smooth(mixed=True) alone bit for bit (the FP64 ones ilu_smooth), and
+    stays within the mixed form's 1e-5 of the FP64 oracle; the first step's 30
+    FP64 residuals (more than 24 ops of one precision) take the staged op
+    tables beside the kernel-argument batch of the others; a matrix
+    registered without FP32 values refuses them."""
+    say("serving: FP32-inner requests")
+    mats = [(W.vardens7(9, seed_rho=6, with_cuts=False), "ilu0", {}), (W.aniso27(7), "ilut", {"tau": 1e-3, "p": 20}),
+            (W.permuted_longrange7(6, seed=3), "ilu0", {})]
+    pool = []
+    for A, kind, params in mats:
+        Ls, U = orc.factor(A, kind, params)
+        _, dinv, Us = orc.scale_rows(U)
+        Ad = B.Csr.from_host(A)
+        F = ctx.ilu_scale_factors(B.Csr.from_host(Ls), B.Csr.from_host(U), fp32=True)
+        pool.append(dict(A=A, Ls=Ls, Us=Us, dinv=dinv, Ad=Ad, F=F))
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=64)
+    mids = [server.register(p["Ad"], p["F"]) for p in pool]
+    reqs = []
+    for k in range(40):
+        mid = k % 3
+        n = pool[mid]["A"].n
+        mL, mU = [(3, 3), (1, 3), (4, 2), (2, 1)][k % 4]
+        reqs.append(dict(mid=mid, b=W.rhs(n, 60 + k), x0=W.rhs(n, 80 + k) * (k % 2), outer=1 + k % 3, mL=mL, mU=mU,
+                         mixed=k % 5 != 0))
+    xs, tickets = [], []
+    for r in reqs:
+        x = dev(r["x0"])
+        xs.append(x)
+        tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"], mixed=r["mixed"]))
+    _drain(server, tickets)
+    for i, r in enumerate(reqs):
+        p = pool[r["mid"]]
+        xa = dev(r["x0"])
+        ctx.ilu_smooth(p["Ad"], p["F"], dev(r["b"]), xa, r["outer"], r["mL"], r["mU"], mixed=r["mixed"])
+        got = host(xs[i])
+        np.testing.assert_array_equal(got, host(xa))
+        ref = orc.smooth(p["A"], p["Ls"], p["Us"], p["dinv"], r["b"], r["x0"], r["outer"], r["mL"], r["mU"])
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= (1e-5 if r["mixed"] else 0.0)
+    plain = B.Server(ctx, arena_bytes=8 << 20, max_active=4)
+    m0 = plain.register(pool[0]["Ad"], ctx.ilu_scale_factors(B.Csr.from_host(pool[0]["Ls"]),
+                                                             B.Csr.from_host(orc.factor(pool[0]["A"], "ilu0", {})[1])))
+    n0 = pool[0]["A"].n
+    with pytest.raises(B.SiluError) as e:
+        plain.submit(m0, dev(W.rhs(n0, 1)), dev(np.zeros(n0)), 1, 3, 3, mixed=True)
+    assert e.value.status == -8
+    plain.close()
+    server.close()
