@@ -160,7 +160,7 @@ def bench_serving(torch, B, ctx, arena_mb):
 
     t = time.perf_counter()
     sides = S.pool_spec()
-    mats = S.build_pool(ctx, sides)
+    mats = S.build_pool(ctx, sides, fp32=True)
     log(f"serving pool: {len(mats)} matrices, n from {min(m[2] for m in mats)} to {max(m[2] for m in mats)}, "
         f"set-up {time.perf_counter() - t:.1f}s")
     reqs = S.make_requests(mats)
@@ -173,6 +173,13 @@ def bench_serving(torch, B, ctx, arena_mb):
     with gc_paused():
         lat_b, span_b, steps = S.run_batched(server, mids, reqs)
     xb = [r.x.clone() for r in reqs]
+    # the same stream in the FP32-inner form
+    S.run_batched(server, mids, reqs[:8], realtime=False, mixed=True)
+    for r in reqs:
+        r.x.zero_()
+    with gc_paused():
+        lat_m, span_m, steps_m = S.run_batched(server, mids, reqs, mixed=True)
+    mixed_err = max(float(torch.linalg.norm(reqs[i].x - xb[i]) / torch.linalg.norm(xb[i])) for i in range(len(reqs)))
     server.close()
     # two lanes: matrices up to 64^3 rows batched on the context's stream, larger
     # ones on a second stream of their own, each lane half of the arena
@@ -199,6 +206,8 @@ def bench_serving(torch, B, ctx, arena_mb):
     res = {"requests": len(reqs), "matrices": len(mats), "arrival_rate_per_s": 2000.0, "arena_MB": arena_mb,
            "batched": {"apps_per_s": len(reqs) / span_b, "makespan_s": span_b, "steps": steps,
                        **S.percentiles(lat_b)},
+           "batched_fp32_inner": {"apps_per_s": len(reqs) / span_m, "makespan_s": span_m, "steps": steps_m,
+                                  "max_rel_diff_vs_fp64": mixed_err, **S.percentiles(lat_m)},
            "batched_two_lanes": {"apps_per_s": len(reqs) / span_l, "makespan_s": span_l, "steps": steps_l,
                                  "small_lane_max_rows": 64 ** 3, **S.percentiles(lat_l)},
            "one_at_a_time": {"apps_per_s": len(reqs) / span_1, "makespan_s": span_1, **S.percentiles(lat_1)},
@@ -208,6 +217,9 @@ def bench_serving(torch, B, ctx, arena_mb):
         f"p99 {res['batched_two_lanes']['p99_ms']:.2f} ms; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
         f"p99 {res['one_at_a_time']['p99_ms']:.2f} ms {res['one_at_a_time']['apps_per_s']:.0f} apps/s; "
         f"identical={same} {same_l}")
+    log(f"serving FP32-inner: batched p50 {res['batched_fp32_inner']['p50_ms']:.2f} ms p99 "
+        f"{res['batched_fp32_inner']['p99_ms']:.2f} ms, largest relative difference from the FP64 results "
+        f"{mixed_err:.2e}")
     res["solve_requests"] = bench_solve_requests(torch, B, ctx)
     return res
 

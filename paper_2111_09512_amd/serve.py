@@ -42,14 +42,15 @@ def pool_spec(n_mat: int = 64, seed: int = 5, sides=SIDES):
     return [int(s) for s in rng.choice(np.asarray(sides), size=n_mat)]
 
 
-def build_pool(ctx: B.Context, sides, density_seed0: int = 5):
-    """Resident matrices: (A, factors) on the device for each side."""
+def build_pool(ctx: B.Context, sides, density_seed0: int = 5, fp32: bool = False):
+    """Resident matrices: (A, factors) on the device for each side (fp32: the factors
+    also carry FP32 values, for FP32-inner requests)."""
     mats = []
     for j, N in enumerate(sides):
         A = W.vardens7(N, seed_rho=density_seed0 + j, with_cuts=False)
         L, U = B.factor_iluk(A, 0)
         Ad, Ld, Ud = B.Csr.from_host(A), B.Csr.from_host(L), B.Csr.from_host(U)
-        F = ctx.ilu_scale_factors(Ld, Ud)
+        F = ctx.ilu_scale_factors(Ld, Ud, fp32=fp32)
         mats.append((Ad, F, A.n))
     return mats
 
@@ -82,14 +83,16 @@ def make_requests(mats, rhs_per_matrix: int = 20, rate: float = 2000.0, seed: in
     return reqs
 
 
-def run_batched(server: B.Server, mids, reqs, realtime: bool = True, lanes=None, steps_per_call: int = 1):
+def run_batched(server: B.Server, mids, reqs, realtime: bool = True, lanes=None, steps_per_call: int = 1,
+                mixed: bool = False):
     """Feed arrivals (in real time) to the server, step it, collect completions.
     lanes: optional list of (server, mids, max_rows) tried in order instead of
     the single server -- a request goes to the first lane whose max_rows covers
     its matrix, so each size class is batched on its own stream and small
     requests do not wait for the steps of large ones.  steps_per_call: scheduling
     steps per call into the library (silu_server_run), so the host loop does not
-    pace the GPU.  Returns (latencies in s, makespan in s, loop iterations)."""
+    pace the GPU.  mixed: every request in the FP32-inner form (the matrices' factors
+    must carry FP32 values).  Returns (latencies in s, makespan in s, loop iterations)."""
     lanes = lanes or [(server, mids, None)]
     n = len(reqs)
     index = {}
@@ -105,7 +108,7 @@ def run_batched(server: B.Server, mids, reqs, realtime: bool = True, lanes=None,
             r = reqs[nxt]
             li = next(k for k, (_, _, cap) in enumerate(lanes) if cap is None or r.b.numel() <= cap)
             sv, mv, _ = lanes[li]
-            index[(li, sv.submit(mv[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U))] = nxt
+            index[(li, sv.submit(mv[r.mid], r.b, r.x, r.outer, r.m_L, r.m_U, mixed=mixed))] = nxt
             pending.add(nxt)
             nxt += 1
         for li, (sv, _, _) in enumerate(lanes):
