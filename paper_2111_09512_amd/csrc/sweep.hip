@@ -467,11 +467,12 @@ __global__ void __launch_bounds__(256) k_solve_check(SolveCheckArgs ca)
     }
 }
 
-// Batched CSR-stream: one launch runs one sweep for each of `nops`
-// independent requests (different matrices, sizes and epilogues).  Op i owns
-// workgroups [first[i], first[i+1]); each workgroup finds its op by binary
-// search and runs exactly the single-request body, so a request's result does
-// not depend on what else shares the launch.
+// Batched sweeps: one launch runs one sweep of one precision for each of
+// `nops` independent requests (different matrices, sizes and epilogues).  Op
+// i owns workgroups [first[i], first[i+1]); each workgroup finds its op
+// (find_op) and runs exactly the single-request body for its tile
+// (batch_tile), so a request's result does not depend on what else shares
+// the launch.
 // The op owning workgroup b: the largest i < nops with first[i] <= b (first
 // increases strictly from first[0] = 0).  Up to 64 ops each lane of the wave
 // tests one entry and a ballot counts those at or below b, so the wave issues
