@@ -582,3 +582,28 @@ def test_fp32_inner_requests_equal_the_single_call(orc, B, ctx):
     assert e.value.status == -8
     plain.close()
     server.close()
+
+
+def test_solve_request_on_a_streamed_matrix(orc, B, ctx):
+    """A randomly permuted operator of 42^3 rows: its column offsets span more
+    than 16-bit codes reach and it has no diagonal structure, so the server
+    streams its CSR arrays, and the convergence checks take their row values
+    from the stream body.  Step count and x equal the oracle's."""
+    say("serving: solve request on a streamed matrix")
+    A = W.permuted_longrange7(42, seed=4)
+    Ls, U = orc.ilu0(A)
+    _, dinv, Us = orc.scale_rows(U)
+    F = ctx.ilu_scale_factors(B.Csr.from_host(Ls), B.Csr.from_host(U))
+    b = W.rhs(A.n, 7)
+    k_ref, x_ref, hist = orc.smooth_until(A, Ls, Us, dinv, b, np.zeros(A.n), 3, 3, 1e-6, 200)
+    assert k_ref < 200 and np.all(np.abs(hist / 1e-6 - 1.0) > 1e-6)
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=4)
+    mid = server.register(B.Csr.from_host(A), F)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    t = server.submit_solve(mid, dev(b), x, 1e-6, 200, 3, 3)
+    server.wait(t)
+    k, rel = server.solve_result(t)
+    assert k == k_ref
+    np.testing.assert_array_equal(host(x), x_ref)
+    assert rel == pytest.approx(hist[-1], rel=1e-12)
+    server.close()
