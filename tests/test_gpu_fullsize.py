@@ -57,6 +57,44 @@ def test_full_poisson32(orc, B, ctx):
 
 
 @pytest.mark.timeout(300)
+def test_full_poisson32_outer_convergence(orc, B, ctx):
+    """Repeated smoothing (1 outer x 3/3 per call, x0 = 0) on the 32^3 Poisson
+    operator until ||b - A x|| / ||b|| < 1e-8 (eq. relres): the FP64 and the
+    FP32-inner forms each stop at the oracle's `smooth_until` step count, the
+    two counts are equal, the residual histories and final iterates equal the
+    oracle's bit for bit (the FP32-inner ones its emulation of that form), and
+    the FP32-inner history stays within 1e-5 of the FP64 one."""
+    wl, c = build(orc, B, ctx, "poisson32")
+    n = c.A.n
+    b = wl.b
+    nb = orc.nrm2(b)
+    bd = dev(b)
+    cap = 2000
+    counts, hists = {}, {}
+    for mixed in (False, True):
+        k_ref, x_ref, h_ref = orc.smooth_until(c.A, c.Ls, c.Us, c.dinv, b, np.zeros(n), wl.m_L, wl.m_U, 1e-8,
+                                               cap, mixed=mixed)
+        assert k_ref < cap
+        x = dev(np.zeros(n))
+        hist = [1.0]
+        k = 0
+        while hist[-1] >= 1e-8 and k <= cap:
+            ctx.ilu_smooth(c.Ad, c.F, bd, x, wl.outer, wl.m_L, wl.m_U, mixed=mixed)
+            k += 1
+            hist.append(orc.nrm2(orc.residual(c.A, b, host(x))) / nb)
+        say(f"  mixed={mixed}: GPU {k} outer steps, oracle {k_ref}; last two relres {hist[-2]:.4e} {hist[-1]:.4e}")
+        assert k == k_ref, f"mixed={mixed}: GPU {k} steps, oracle {k_ref}"
+        # FP64: the oracle's iterate; FP32-inner: the oracle's emulation of it
+        np.testing.assert_array_equal(host(x), x_ref)
+        np.testing.assert_array_equal(np.asarray(hist), h_ref)
+        counts[mixed], hists[mixed] = k, np.asarray(hist)
+    assert counts[True] == counts[False]
+    worst = np.max(np.abs(hists[True] - hists[False]) / hists[False])
+    say(f"  FP32-inner vs FP64 residual history: max relative difference {worst:.3e}")
+    assert worst <= 1e-5
+
+
+@pytest.mark.timeout(300)
 def test_full_vardens128_inner_sweep(orc, B, ctx):
     """ILU(1) on the variable-density cut-cell operator, inner iterations
     1..8, scaled vs unscaled, iterative vs direct."""

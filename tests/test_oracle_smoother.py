@@ -312,6 +312,65 @@ def test_mixed_m1_closed_form(orc):
     np.testing.assert_array_equal(got, ref)
 
 
+def _mixed_by_scalars(A, Ls, Us, dinv, b, x0, outer, mL, mU):
+    """The FP32-inner smoother (reading 11's rounding points) written with
+    numpy scalars, one operation at a time: the residual summed in FP64 in
+    ascending column order; the Richardson loops on np.float32 values and
+    iterates, each row's products accumulated in np.float32 in ascending
+    column order from +0; s = fp32(dinv * y) in FP64; x += fp64(z)."""
+    f32 = np.float32
+
+    def rows(M):
+        return [(M.col[M.row_ptr[i]:M.row_ptr[i + 1]], M.val[M.row_ptr[i]:M.row_ptr[i + 1]]) for i in range(M.n)]
+
+    Ar, Lr, Ur = rows(A), rows(Ls), rows(Us)
+    Lr32 = [(c, [f32(v) for v in vals]) for c, vals in Lr]
+    Ur32 = [(c, [f32(v) for v in vals]) for c, vals in Ur]
+
+    def richardson32(R, rhs, m):
+        y = [f32(0.0)] * len(rhs)
+        for _ in range(m):
+            new = []
+            for i, (cols, vals) in enumerate(R):
+                t = f32(0.0)
+                for j, v in zip(cols, vals):
+                    t = f32(t + f32(v * y[j]))
+                new.append(f32(rhs[i] - t))
+            y = new
+        return y
+
+    x = [float(v) for v in x0]
+    for _ in range(outer):
+        r = []
+        for i, (cols, vals) in enumerate(Ar):
+            t = 0.0
+            for j, v in zip(cols, vals):
+                t = t + float(v) * x[j]
+            r.append(f32(float(b[i]) - t))
+        y = richardson32(Lr32, r, mL)
+        s = [f32(float(dinv[i]) * float(y[i])) for i in range(len(y))]
+        z = richardson32(Ur32, s, mU)
+        x = [x[i] + float(z[i]) for i in range(len(x))]
+    return np.array(x)
+
+
+@pytest.mark.parametrize("mL,mU", [(2, 2), (3, 3), (2, 3)])
+def test_mixed_fp32_loop_by_scalars(orc, mL, mU):
+    """The FP32 loop of the mixed emulation, re-derived with np.float32 scalar
+    arithmetic on a small ILUT case (many entries per row, so the order and
+    the precision of each row's accumulation decide the last bits): bit for
+    bit, over two outer steps from a nonzero guess.  Also differs from the
+    FP64 smoother, so the FP32 rounding really happens."""
+    A = W.aniso27(4)
+    Ls, U, d, dinv, Us = factors(orc, A, "ilut", tau=1e-3, p=20)
+    b = W.rhs(A.n, 0)
+    x0 = W.rhs(A.n, 2)
+    got = orc.smooth_mixed(A, Ls, Us, dinv, b, x0, 2, mL, mU)
+    want = _mixed_by_scalars(A, Ls, Us, dinv, b, x0, 2, mL, mU)
+    np.testing.assert_array_equal(got, want)
+    assert not np.array_equal(got, orc.smooth(A, Ls, Us, dinv, b, x0, 2, mL, mU))
+
+
 def test_mixed_close_to_fp64(orc):
     A = W.aniso27(8)
     Ls, U, d, dinv, Us = factors(orc, A, "ilut", tau=1e-3, p=20)
