@@ -1,4 +1,5 @@
-"""Build the oracle's shared library with gcc (plain C, no FMA contraction, no fast-math)."""
+"""Build the oracle's shared library with gcc (plain C, no FMA contraction, no fast-math; OpenMP
+only for the row-parallel timing variant of the smoother)."""
 import os
 import subprocess
 import sys
@@ -10,7 +11,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-        "-Wall", "-Wextra", "-Wno-unused-parameter",
+        "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
         "-o", LIB, os.path.join(HERE, "oracle.c"), "-lm",
     ]
     if verbose:

@@ -23,6 +23,7 @@
  *   3  pattern error (missing diagonal, entry on the wrong side, ...)
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -670,6 +671,70 @@ void orc_smooth(int n, const int *Arp, const int *Acol, const double *Aval,
             orc_richardson(n, Urp, Ucol, Uval, s, mU, z, tmp);
         for (int i = 0; i < n; i++) x[i] = x[i] + z[i];
     }
+}
+
+/* =========================================================================
+ * The same smoother step (iterative form only) with the row loops split
+ * among OpenMP threads: the residual, every Richardson update and the two
+ * vector updates.  A Richardson update reads only the previous iterate, so
+ * the rows of one update are independent; each row is still summed from 0.0
+ * in ascending column order by one thread, and the result equals orc_smooth
+ * bit for bit whatever the thread count.  Used to time the CPU baseline on
+ * all host cores (a substitution would not split this way: row i needs the
+ * rows before it).  ws: 5n doubles.
+ * ========================================================================= */
+static void orc_spmv_omp(int n, const int *rp, const int *col, const double *val, const double *x, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++) {
+        double t = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; p++) t = t + val[p] * x[col[p]];
+        y[i] = t;
+    }
+}
+
+static void orc_richardson_omp(int n, const int *rp, const int *col, const double *val,
+                               const double *rhs, int m, double *y, double *tmp)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; i++) y[i] = 0.0;
+    for (int k = 1; k <= m; k++) {
+        orc_spmv_omp(n, rp, col, val, y, tmp);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; i++) y[i] = rhs[i] - tmp[i];
+    }
+}
+
+void orc_smooth_omp(int n, const int *Arp, const int *Acol, const double *Aval,
+                    const int *Lrp, const int *Lcol, const double *Lval,
+                    const int *Urp, const int *Ucol, const double *Uval, const double *dinv,
+                    const double *b, double *x, int outer, int mL, int mU, double *ws)
+{
+    double *r = ws, *y = ws + n, *s = ws + 2 * (size_t)n, *z = ws + 3 * (size_t)n,
+           *tmp = ws + 4 * (size_t)n;
+    for (int it = 0; it < outer; it++) {
+        orc_spmv_omp(n, Arp, Acol, Aval, x, r);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; i++) r[i] = b[i] - r[i];
+        orc_richardson_omp(n, Lrp, Lcol, Lval, r, mL, y, tmp);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; i++) s[i] = dinv[i] * y[i];
+        orc_richardson_omp(n, Urp, Ucol, Uval, s, mU, z, tmp);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; i++) x[i] = x[i] + z[i];
+    }
+}
+
+/* Threads orc_smooth_omp uses (OMP_NUM_THREADS, else the host's). */
+int orc_omp_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
 }
 
 /* =========================================================================

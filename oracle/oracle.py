@@ -16,7 +16,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB points the wrapper at another build of oracle.c (the sanitizer build of the tests)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -83,6 +84,11 @@ def lib():
         L.orc_smooth.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _f64p,
                                  _f64p, _f64p, C.c_int, C.c_int, C.c_int, C.c_int, _f64p]
         L.orc_smooth.restype = None
+        L.orc_smooth_omp.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p,
+                                     _f64p, _f64p, _f64p, C.c_int, C.c_int, C.c_int, _f64p]
+        L.orc_smooth_omp.restype = None
+        L.orc_omp_threads.argtypes = []
+        L.orc_omp_threads.restype = C.c_int
         L.orc_unit_shift.argtypes = [C.c_int, _i32p, _i32p, _f64p, _f64p]
         L.orc_unit_shift.restype = None
         L.orc_smooth_unscaled.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, _i32p, _i32p,
@@ -364,6 +370,24 @@ def smooth(A, Ls, Us, dinv, b, x0, outer: int, mL: int, mU: int, direct: bool = 
                      np.ascontiguousarray(dinv, np.float64), np.ascontiguousarray(b, np.float64), x,
                      int(outer), int(mL), int(mU), 1 if direct else 0, ws)
     return x
+
+
+def smooth_omp(A, Ls, Us, dinv, b, x0, outer: int, mL: int, mU: int):
+    """`smooth` (iterative form) with its row loops split among OpenMP threads;
+    bit-identical to `smooth`.  For timing the CPU baseline on all host cores."""
+    A, Ls, Us = _mat(A), _mat(Ls), _mat(Us)
+    n = A.n
+    x = np.array(x0, dtype=np.float64, copy=True)
+    ws = np.empty(5 * n)
+    lib().orc_smooth_omp(n, A.row_ptr, A.col, A.val, Ls.row_ptr, Ls.col, Ls.val, Us.row_ptr, Us.col, Us.val,
+                         np.ascontiguousarray(dinv, np.float64), np.ascontiguousarray(b, np.float64), x,
+                         int(outer), int(mL), int(mU), ws)
+    return x
+
+
+def omp_threads():
+    """Threads `smooth_omp` runs on (OMP_NUM_THREADS, else every host thread)."""
+    return int(lib().orc_omp_threads())
 
 
 def unit_shift(U):

@@ -410,3 +410,16 @@ def test_golden_regression_poisson8(orc):
     x = orc.smooth(A, Ls, Us, dinv, b, np.zeros(A.n), 1, 3, 3)
     assert [float(v) for v in x[g["idx"]]] == g["x_at_idx"]
     assert float(orc.nrm2(x)) == g["nrm2"]
+
+
+@pytest.mark.parametrize("N,kind", [(9, "ilu0"), (7, "ilut")])
+def test_smooth_omp_equals_sequential(orc, N, kind):
+    """The row-parallel variant used for the CPU baseline sums every row in the
+    same order as the sequential smoother, so the two agree bit for bit."""
+    A = W.poisson7(N) if kind == "ilu0" else W.aniso27(N)
+    Ls, U, d, dinv, Us = factors(orc, A, kind, tau=1e-3, p=20)
+    b, x0 = W.rhs(A.n, 0), W.rhs(A.n, 3)
+    assert orc.omp_threads() >= 1
+    for outer, mL, mU in ((1, 1, 1), (2, 4, 4), (1, 3, 2)):
+        np.testing.assert_array_equal(orc.smooth_omp(A, Ls, Us, dinv, b, x0, outer, mL, mU),
+                                      orc.smooth(A, Ls, Us, dinv, b, x0, outer, mL, mU))
