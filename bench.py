@@ -106,30 +106,47 @@ def host_cpu():
     return f"{model}, {len(os.sched_getaffinity(0))} hardware threads visible"
 
 
-def cpu_baseline(W, nsample=100, reps=None):
-    """The oracle (plain C, one thread) on a bounded sample of the same operator:
-    the 27-pt anisotropic operator on an nsample^3 grid, its own ILUT factors,
-    smoother applications timed and scaled to the full grid by the matrix
-    entries streamed per application."""
+def host_lscpu():
+    """lscpu's model fields (model name, family, model, stepping, sockets, threads), as printed."""
+    import subprocess
+
+    keys = ("Model name", "CPU family", "Model", "Stepping", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+            "CPU(s)")
+    try:
+        outp = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    got = {}
+    for line in outp.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keys and k.strip() not in got:
+            got[k.strip()] = v.strip()
+    return got
+
+
+def cpu_baseline(A, Ls, Us, dinv, b, outer, mL, mU, x_gpu, budget_1t=10.0, budget_mt=5.0):
+    """The oracle (plain C) smoothing the benchmark's own operator at its full
+    size, from x0 = 0 with the same counts: timed on one thread (the oracle as
+    it stands) and with its row loops split over every host thread (OpenMP;
+    bit-identical), each for about `budget` seconds of whole applications."""
     from oracle import oracle as O
 
-    A = W.aniso27(nsample)
-    Ls, U = O.ilut(A, 1e-3, 20)
-    d, dinv, Us = O.scale_rows(U)
-    b = W.rhs(A.n, 0)
     x0 = np.zeros(A.n)
-    O.smooth(A, Ls, Us, dinv, b, x0, 2, 4, 4)  # warm
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        O.smooth(A, Ls, Us, dinv, b, x0, 2, 4, 4)
-        k += 1
-        el = time.perf_counter() - t0
-        if (reps and k >= reps) or (not reps and el > 12.0):
-            break
-    per_app = el / k
-    work_sample = A.nnz + 3 * Ls.nnz + 3 * Us.nnz
-    return per_app, work_sample, A.n, k
+
+    def run(fn, budget, min_k):
+        k, t0 = 0, time.perf_counter()
+        while True:
+            xo = fn(A, Ls, Us, dinv, b, x0, outer, mL, mU)
+            k += 1
+            el = time.perf_counter() - t0
+            if k >= min_k and el > budget:
+                return el / k, k, xo
+
+    per_1, k_1, x_1 = run(O.smooth, budget_1t, 2)
+    threads = O.omp_threads()
+    per_m, k_m, x_m = run(O.smooth_omp, budget_mt, 3)
+    return {"per_app_1t": per_1, "apps_1t": k_1, "per_app_mt": per_m, "apps_mt": k_m, "threads": threads,
+            "omp_identical": bool(np.array_equal(x_1, x_m)), "gpu_identical": bool(np.array_equal(x_1, x_gpu))}
 
 
 def measured_traffic(workload):
@@ -311,6 +328,12 @@ def main():
     ctx = B.Context()
     Ad, Ld, Ud = B.Csr.from_host(A), B.Csr.from_host(L), B.Csr.from_host(U)
     F = ctx.ilu_scale_factors(Ld, Ud, fp32=True)
+    orc_in = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        _, dinv_h, Us_h = O.scale_rows(U)
+        orc_in = (L, Us_h, dinv_h)
     del L, U
     bvec = torch.from_numpy(W.rhs(n, 0)).cuda()
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -598,17 +621,29 @@ def main():
         ms_direct = time_steps(torch, app_direct, max(3, min(args.steps, 10)), 2)
         log(f"direct: {ms_direct:.3f} ms/app, {ms_direct * 1e3 / (outer * (dL + dU)):.2f} us per level")
 
-    # ---- CPU oracle baseline on a bounded sample ----
+    # ---- CPU oracle baseline: the full operator, the same factors, a bounded number of applications ----
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "aniso200":
-        per_app, work_s, n_s, k = cpu_baseline(W)
-        work_full = nnzA + 3 * nnzL + 3 * nnzU
-        cpu_apps = 1.0 / (per_app * work_full / work_s)
-        cpu = {"value": cpu_apps, "unit": "apps/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
-               "sample": f"oracle (plain C, 1 thread): same 27-pt operator on a 100^3 grid (n={n_s}), its own "
-                         f"ILUT(1e-3,20) factors, {k} applications of 2x4 smoothing at {per_app * 1e3:.1f} ms each, "
-                         f"scaled to n=8M by matrix entries per application ({work_full}/{work_s})"}
-        log(f"cpu oracle: {per_app * 1e3:.1f} ms/app on the sample -> {cpu_apps:.3f} apps/s at full size")
+    if orc_in is not None:
+        t = time.perf_counter()
+        cb = cpu_baseline(A, *orc_in, W.rhs(n, 0), outer, mL, mU, x64.cpu().numpy())
+        lscpu = host_lscpu()
+        cpu = {"value": 1.0 / cb["per_app_mt"], "unit": "apps/s", "cores": cb["threads"], "kind": "oracle",
+               "host": host_cpu(), "lscpu": lscpu,
+               "sample": f"oracle (plain C, FP64) on the full operator (n={n}) with the benchmark's own factors "
+                         f"(the host factorization, bit-identical to the oracle's), {outer}x{mL}/{mU} smoothing "
+                         f"from x0=0: {cb['apps_mt']} applications with the row loops on {cb['threads']} OpenMP "
+                         f"threads, {cb['apps_1t']} on one thread",
+               "single_thread": {"value": 1.0 / cb["per_app_1t"], "cores": 1, "ms_per_app": cb["per_app_1t"] * 1e3,
+                                 "applications": cb["apps_1t"]},
+               "multi_thread": {"value": 1.0 / cb["per_app_mt"], "cores": cb["threads"],
+                                "ms_per_app": cb["per_app_mt"] * 1e3, "applications": cb["apps_mt"]},
+               "threaded_identical_to_single": cb["omp_identical"],
+               "identical_to_gpu_fp64": cb["gpu_identical"]}
+        log(f"cpu oracle at full size: 1 thread {cb['per_app_1t'] * 1e3:.1f} ms/app ({cb['apps_1t']} apps), "
+            f"{cb['threads']} threads {cb['per_app_mt'] * 1e3:.1f} ms/app ({cb['apps_mt']} apps); threaded identical "
+            f"{cb['omp_identical']}, identical to the GPU FP64 result {cb['gpu_identical']} "
+            f"({time.perf_counter() - t:.1f}s); host {host_cpu()}; lscpu {lscpu}")
+        del orc_in
 
     rec = measured_traffic(args.workload)
     traffic = rec["traffic_bytes_per_launch"] if rec and rec.get("kernel") == dname else None
