@@ -13,7 +13,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
 HIP_SOURCES = ["sweep.hip", "setup.hip", "krylov.hip", "fixedpoint.hip", "reorder.hip", "api.hip", "serve.hip"]
-CXX_SOURCES = ["factor.cpp"]
+CXX_SOURCES = ["factor.cpp", "order.cpp"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed-FP32 instructions anywhere in device code
@@ -30,17 +30,22 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([CLANGXX, *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([CLANGXX, *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
