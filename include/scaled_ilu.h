@@ -531,6 +531,9 @@ int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
  * are both served.  Errors: ARG, SHAPE, UNSUPPORTED (unscaled or non-FP64
  * factors), NOMEM (one request alone exceeds the arena), HIP
  * (silu_server_last_hip_error).  A server is used by one host thread.
+ * Per-ticket state is bounded: a ticket's record (its times, and a solve
+ * request's result) is kept until 65,536 later tickets have finished; after
+ * that poll and wait report it done and times / solve_result return ARG.
  */
 typedef struct silu_server silu_server;
 int silu_server_create(silu_ctx *ctx, void *hip_stream, void *arena, size_t arena_bytes, int max_active,
@@ -586,15 +589,21 @@ int silu_server_poll(silu_server *server, int64_t ticket, int *state);
 /* The tickets of requests found done (state 3) since the last call, each
  * returned once, oldest first, at most `capacity` of them in tickets[] (host
  * array); *count receives how many.  One call replaces a poll per pending
- * request.  Done tickets are kept until returned here (8 bytes each). */
+ * request.  Done tickets are kept until returned here (8 bytes each), at
+ * most the 65,536 most recent: older ones are dropped unreported. */
 int silu_server_completed(silu_server *server, int64_t *tickets, int capacity, int *count);
 /* Block until the ticket's request is done (state 3), stepping the server
  * while it is queued or running, then waiting for its last launch.  The
  * server's other requests advance with it. */
 int silu_server_wait(silu_server *server, int64_t ticket);
 /* Host steady-clock times in ns: when the ticket was submitted and when the
- * server first found it done (-1 while it is not).  ARG for unknown tickets. */
+ * server first found it done (-1 while it is not).  ARG for unknown tickets
+ * and for those whose record has been dropped (see above). */
 int silu_server_times(silu_server *server, int64_t ticket, int64_t *submitted_ns, int64_t *done_ns);
+/* What the server holds per ticket now: ticket records, pinned result slots
+ * for solve requests (allocated 1,024 at a time, reused once read), and done
+ * tickets not yet returned by silu_server_completed. */
+int silu_server_footprint(const silu_server *server, int64_t *records, int64_t *result_slots, int64_t *unreported);
 int silu_server_last_hip_error(const silu_server *server);
 
 /*

@@ -140,6 +140,7 @@ _sig = {
     "silu_server_run": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "silu_server_wait": (C.c_int, [_P, C.c_int64]),
     "silu_server_times": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "silu_server_footprint": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "silu_reorder_rcm": (C.c_int, [C.c_int64, _P, _P, _P, C.c_double, _P]),
     "silu_server_set_wait_limit": (C.c_int, [_P, C.c_int]),
 }
@@ -776,6 +777,12 @@ class Server:
         a, d = C.c_int64(), C.c_int64()
         self._check(_lib.silu_server_times(self._h, ticket, C.byref(a), C.byref(d)), "silu_server_times")
         return a.value * 1e-9, (d.value * 1e-9 if d.value >= 0 else None)
+
+    def footprint(self) -> tuple[int, int, int]:
+        """(ticket records, pinned result slots, done tickets not yet returned by completed)."""
+        r, p, u = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(_lib.silu_server_footprint(self._h, C.byref(r), C.byref(p), C.byref(u)), "silu_server_footprint")
+        return r.value, p.value, u.value
 
     def poll(self, ticket: int) -> int:
         st = C.c_int()

@@ -28,6 +28,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <vector>
 
@@ -105,9 +106,28 @@ size_t ctl_bytes(int64_t n)
 }
 size_t request_bytes(int64_t n) { return 4 * vec_bytes(n) + ctl_bytes(n); }
 
-// Pinned host copies of finished solve requests' SolveCtl, in blocks that are
-// never moved while the server lives.
+// Pinned host copies of finishing solve requests' SolveCtl, in blocks that are
+// never moved while the server lives; a slot is read and returned to a free
+// list once the step that wrote it is done, so the blocks only cover the solve
+// requests finishing at once.
 constexpr int RESULTS_PER_BLOCK = 1024;
+
+// What the server remembers of a ticket: kept from submission until
+// MAX_RECORDS later tickets have finished (a finished ticket without a
+// record is reported done by poll and wait; times and solve_result need its
+// record).  The tickets completed() has not handed out yet are bounded the
+// same way.
+constexpr size_t MAX_RECORDS = (size_t)1 << 16;
+
+struct Record {
+    int64_t submitted_ns = 0, done_ns = -1; // steady clock; done_ns once the host saw it finish
+    int64_t finish_step = -1;               // the step of its last op, once enqueued
+    int result = -1;                        // solve requests: pinned SolveCtl slot until read
+    int max_outer = 0;
+    bool solve = false;
+    int outer_steps = -1; // solve requests, once done
+    double relres = 0.0;
+};
 
 int64_t now_ns()
 {
@@ -120,8 +140,10 @@ int64_t now_ns()
 
 struct silu_server {
     std::vector<SolveCtl *> result_blocks; // pinned, RESULTS_PER_BLOCK each
-    int64_t nresults = 0;
-    std::map<int64_t, std::pair<int64_t, int>> solve_result; // ticket -> (result slot, max outer steps)
+    int64_t nresults = 0;                  // slots in result_blocks
+    std::vector<int> free_results;         // slots not holding a result still to be read
+    std::unordered_map<int64_t, Record> recs; // ticket -> record (bounded: MAX_RECORDS finished)
+    std::deque<int64_t> retired;               // finished tickets with a record, oldest first
     int32_t *hflags = nullptr;                  // pinned stop flags of solve requests (2 max_active words)
     int32_t *d_hflags = nullptr;                // the same words as the device addresses them
     std::vector<int> free_flags;
@@ -137,10 +159,8 @@ struct silu_server {
     std::vector<Request> active;
     std::vector<Range> free_list;                      // sorted by offset, coalesced
     std::vector<std::pair<int64_t, Range>> to_release; // (step, range)
-    std::map<int64_t, int64_t> finish_step;            // ticket -> step of its last op
     std::vector<std::pair<int64_t, int64_t>> to_report; // (step, ticket) not yet known done
     std::deque<int64_t> done_queue;                     // done, not yet returned by completed()
-    std::map<int64_t, std::pair<int64_t, int64_t>> times; // ticket -> (submitted, found done), steady ns
     int64_t next_ticket = 0, steps = 0, completed_through = -1;
     hipEvent_t ev[RING] = {};
     int64_t done_step[RING];   // persistent mode: the step a slot last held, once the GPU has passed it
@@ -252,7 +272,22 @@ void reap(silu_server *s)
     for (size_t i = 0; i < rp.size(); i++) {
         if (step_done(s, rp[i].first)) {
             s->done_queue.push_back(rp[i].second);
-            s->times[rp[i].second].second = now_ns();
+            if (s->done_queue.size() > MAX_RECORDS) s->done_queue.pop_front();
+            Record &rec = s->recs[rp[i].second];
+            rec.done_ns = now_ns();
+            if (rec.result >= 0) { // the SolveCtl copied when it finished
+                const SolveCtl &c = s->result_blocks[(size_t)rec.result / RESULTS_PER_BLOCK]
+                                                    [rec.result % RESULTS_PER_BLOCK];
+                rec.outer_steps = c.stop ? c.checks - 1 : rec.max_outer + 1;
+                rec.relres = std::sqrt(c.rr) / std::sqrt(c.bb);
+                s->free_results.push_back(rec.result);
+                rec.result = -1;
+            }
+            s->retired.push_back(rp[i].second);
+            while (s->retired.size() > MAX_RECORDS) {
+                s->recs.erase(s->retired.front());
+                s->retired.pop_front();
+            }
             auto fl = s->ticket_flag.find(rp[i].second);
             if (fl != s->ticket_flag.end()) {
                 s->free_flags.push_back(fl->second);
@@ -502,7 +537,7 @@ int launch_persistent(silu_server *s, std::vector<Request> &batch)
     s->inflight += (int)batch.size();
     const int64_t step = s->steps++;
     for (const Request &q : batch) {
-        s->finish_step[q.ticket] = step;
+        s->recs[q.ticket].finish_step = step;
         s->to_release.push_back({step, q.ws});
         s->to_report.push_back({step, q.ticket});
     }
@@ -663,7 +698,7 @@ int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x
     q.mU = m_U;
     q.total = outer * (1 + (m_L - 1) + (m_U - 1));
     s->queue.push_back(q);
-    s->times[q.ticket] = {now_ns(), -1};
+    s->recs[q.ticket].submitted_ns = now_ns();
     *ticket = q.ticket;
     return SILU_OK;
 }
@@ -674,17 +709,22 @@ int silu_server_submit(silu_server *s, int matrix_id, const double *b, double *x
 int save_result(silu_server *s, Request &q)
 {
     hipError_t e;
-    if (s->nresults == (int64_t)s->result_blocks.size() * RESULTS_PER_BLOCK) {
+    if (s->free_results.empty()) {
         SolveCtl *blk = nullptr;
         if ((e = hipHostMalloc((void **)&blk, sizeof(SolveCtl) * RESULTS_PER_BLOCK)) != hipSuccess) return fail(s, e);
         s->result_blocks.push_back(blk);
+        for (int k = RESULTS_PER_BLOCK - 1; k >= 0; k--) s->free_results.push_back((int)s->nresults + k);
+        s->nresults += RESULTS_PER_BLOCK;
     }
-    q.result = (int)s->nresults++;
+    q.result = s->free_results.back();
+    s->free_results.pop_back();
     SolveCtl *dst = s->result_blocks[(size_t)q.result / RESULTS_PER_BLOCK] + q.result % RESULTS_PER_BLOCK;
     const char *src = s->arena + q.ws.off + 4 * vec_bytes(s->mats[(size_t)q.mid].A.n_rows);
     if ((e = hipMemcpyAsync(dst, src, sizeof(SolveCtl), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
         return fail(s, e);
-    s->solve_result[q.ticket] = {q.result, q.outer};
+    Record &rec = s->recs[q.ticket];
+    rec.result = q.result;
+    rec.max_outer = q.outer;
     return SILU_OK;
 }
 
@@ -712,6 +752,7 @@ int silu_server_submit_solve(silu_server *s, int matrix_id, const double *b, dou
     Request &q = s->queue.back();
     q.outer = max_outer;
     q.tol = tol;
+    s->recs[q.ticket].solve = true;
     q.total = max_outer * (1 + (m_L - 1) + (m_U - 1)) + 1; // and the check of the last iterate
     return SILU_OK;
 }
@@ -720,13 +761,10 @@ int silu_server_solve_result(silu_server *s, int64_t ticket, int *outer_steps, d
 {
     if (!s || !outer_steps || !relres) return SILU_ERR_ARG;
     reap(s);
-    auto it = s->solve_result.find(ticket);
-    auto fs = s->finish_step.find(ticket);
-    if (it == s->solve_result.end() || fs == s->finish_step.end() || !step_done(s, fs->second)) return SILU_ERR_ARG;
-    const int64_t slot = it->second.first;
-    const SolveCtl &c = s->result_blocks[(size_t)slot / RESULTS_PER_BLOCK][slot % RESULTS_PER_BLOCK];
-    *outer_steps = c.stop ? c.checks - 1 : it->second.second + 1;
-    *relres = std::sqrt(c.rr) / std::sqrt(c.bb);
+    auto it = s->recs.find(ticket);
+    if (it == s->recs.end() || !it->second.solve || it->second.done_ns < 0) return SILU_ERR_ARG;
+    *outer_steps = it->second.outer_steps;
+    *relres = it->second.relres;
     return SILU_OK;
 }
 
@@ -770,7 +808,7 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             if (q.flag >= 0 && __atomic_load_n(&s->hflags[q.flag], __ATOMIC_ACQUIRE) != 0) {
                 const int st = save_result(s, q);
                 if (st) return st;
-                s->finish_step[q.ticket] = s->steps;
+                s->recs[q.ticket].finish_step = s->steps;
                 s->to_release.push_back({s->steps, q.ws});
                 s->to_report.push_back({s->steps, q.ticket});
                 s->force_mark = true;
@@ -890,7 +928,7 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
             Request &q = s->active[i];
             q.op++;
             if (q.op == q.total) {
-                s->finish_step[q.ticket] = step;
+                s->recs[q.ticket].finish_step = step;
                 s->to_release.push_back({step, q.ws});
                 s->to_report.push_back({step, q.ticket});
             } else {
@@ -928,16 +966,21 @@ int silu_server_run(silu_server *s, int max_steps, int *n_active, int *n_queued)
 int silu_server_poll(silu_server *s, int64_t ticket, int *state)
 {
     if (!s || !state || ticket < 0 || ticket >= s->next_ticket) return SILU_ERR_ARG;
-    auto it = s->finish_step.find(ticket);
-    if (it == s->finish_step.end()) {
+    auto it = s->recs.find(ticket);
+    if (it == s->recs.end()) { // finished long ago: its record has been dropped
+        *state = 3;
+        return SILU_OK;
+    }
+    const int64_t k = it->second.finish_step;
+    if (k < 0) {
         bool queued = false;
         for (const Request &q : s->queue) queued |= q.ticket == ticket;
         *state = queued ? 0 : 1;
         return SILU_OK;
     }
     reap(s);
-    *state = step_done(s, it->second) ? 3 : 2;
-    if (*state == 3 && std::find(s->failed.begin(), s->failed.end(), it->second) != s->failed.end())
+    *state = step_done(s, k) ? 3 : 2;
+    if (*state == 3 && std::find(s->failed.begin(), s->failed.end(), k) != s->failed.end())
         return SILU_ERR_TIMEOUT;
     return SILU_OK;
 }
@@ -959,10 +1002,19 @@ int silu_server_times(silu_server *s, int64_t ticket, int64_t *submitted_ns, int
 {
     if (!s || !submitted_ns || !done_ns) return SILU_ERR_ARG;
     reap(s);
-    auto it = s->times.find(ticket);
-    if (it == s->times.end()) return SILU_ERR_ARG;
-    *submitted_ns = it->second.first;
-    *done_ns = it->second.second;
+    auto it = s->recs.find(ticket);
+    if (it == s->recs.end()) return SILU_ERR_ARG;
+    *submitted_ns = it->second.submitted_ns;
+    *done_ns = it->second.done_ns;
+    return SILU_OK;
+}
+
+int silu_server_footprint(const silu_server *s, int64_t *records, int64_t *result_slots, int64_t *unreported)
+{
+    if (!s || !records || !result_slots || !unreported) return SILU_ERR_ARG;
+    *records = (int64_t)s->recs.size();
+    *result_slots = s->nresults;
+    *unreported = (int64_t)s->done_queue.size();
     return SILU_OK;
 }
 
@@ -975,7 +1027,7 @@ int silu_server_wait(silu_server *s, int64_t ticket)
         if (st) return st;
         if (state == 3) return SILU_OK;
         if (state == 2) { // its last launch is enqueued: wait for that step's event
-            const int64_t k = s->finish_step[ticket];
+            const int64_t k = s->recs.at(ticket).finish_step;
             hipError_t e = hipSuccess;
             if (s->mode == 1) {
                 e = hipEventSynchronize(s->ev[k % RING]);

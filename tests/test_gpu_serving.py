@@ -607,3 +607,47 @@ def test_solve_request_on_a_streamed_matrix(orc, B, ctx):
     np.testing.assert_array_equal(host(x), x_ref)
     assert rel == pytest.approx(hist[-1], rel=1e-12)
     server.close()
+
+
+def test_per_ticket_state_stays_bounded(B, ctx, pool):
+    """A long-running request loop keeps bounded per-ticket state: after more
+    than 65,536 finished requests the oldest records are dropped (poll and wait
+    report those tickets done, times refuses them), the latest are kept, and
+    the pinned slots for solve-request results are reused rather than grown."""
+    say("serving: bounded per-ticket state")
+    p = pool[0]
+    n = p["A"].n
+    server = B.Server(ctx, arena_bytes=64 << 20, max_active=1024)
+    mid = server.register(p["Ad"], p["F"])
+    b = dev(W.rhs(n, 1))
+    xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(1024)]
+    first = last = None
+    total = 0
+    while total < 70000:
+        tickets = [server.submit(mid, b, xs[k], 1, 2, 1) for k in range(1024)]
+        first = tickets[0] if first is None else first
+        last = tickets[-1]
+        server.wait(last)  # admitted in order, same length: the last one done means all are
+        total += len(tickets)
+    records, slots, unreported = server.footprint()
+    say(f"  {total} requests: records {records}, result slots {slots}, unreported {unreported}")
+    assert records <= 65536 and unreported <= 65536
+    assert server.poll(first) == server.DONE
+    server.wait(first)
+    with pytest.raises(B.SiluError):
+        server.times(first)
+    t_sub, t_done = server.times(last)
+    assert t_done is not None and t_done >= t_sub
+    # solve requests in waves: the pinned result slots do not grow with their number
+    seen = []
+    for wave in range(4):
+        tickets = [server.submit_solve(mid, b, xs[k], 1e-300, 2, 2, 2) for k in range(1024)]
+        server.wait(tickets[-1])
+        for t in tickets:
+            server.wait(t)
+        k, rel = server.solve_result(tickets[-1])
+        assert k == 3 and rel > 0.0  # never below 1e-300: max_outer + 1
+        seen.append(server.footprint()[1])
+    say(f"  pinned result slots after each wave of 1,024 solve requests: {seen}")
+    assert seen[-1] == seen[1] and seen[-1] <= 16 * 1024
+    server.close()
