@@ -487,3 +487,33 @@ def test_ragged_sizes_variable_rows(orc, B, ctx, n, kernel):
         x = dev(x0)
         ctx.ilu_smooth(c.Ad, c.F, dev(b), x, 2, 3, 4, mixed=mixed, kernel=kernel)
         np.testing.assert_array_equal(host(x), want)
+
+
+@pytest.mark.parametrize("name", ["aniso11_ilut", "perm9"])
+def test_run_twice_deterministic(orc, B, ctx, cases, name):
+    """Every entry point gives the same bits when called twice on the same
+    inputs (no atomics or arrival-order reductions anywhere on the path): the
+    smoother under every kernel variant (including vector-CSR, whose shuffle
+    reductions differ from the oracle's order but not from run to run), FP64
+    and FP32-inner, the direct form, the polynomial Gauss-Seidel smoother and
+    FGMRES."""
+    say("run twice", name)
+    c = cases[name]
+    b, x0 = dev(W.rhs(c.A.n, 7)), dev(W.rhs(c.A.n, 8))
+
+    def twice(fn):
+        outs = []
+        for _ in range(2):
+            x = x0.clone()
+            fn(x)
+            outs.append(host(x))
+        np.testing.assert_array_equal(outs[0], outs[1])
+
+    for kernel in KERNELS:
+        for mixed in (False, True):
+            twice(lambda x: ctx.ilu_smooth(c.Ad, c.F, b, x, 2, 3, 4, mixed=mixed, kernel=kernel))
+    twice(lambda x: ctx.ilu_smooth(c.Ad, c.F, b, x, 2, 1, 1, direct=True))
+    G = ctx.gs_split(c.Ad, fp32=True)
+    for mixed in (False, True):
+        twice(lambda x: ctx.gs_smooth(c.Ad, G, b, x, 2, 3, mixed=mixed))
+    twice(lambda x: ctx.fgmres(c.Ad, c.F, b, x, restart=10, max_iters=40, tol=1e-10))
