@@ -18,7 +18,7 @@ fixed-point sweeps against the host ILU(0), one outer step with 1..8 inner
 iterations on row-scaled and on unscaled factors (time and residual), a
 streaming-copy bandwidth
 calibration, the roofline of the dominant kernel from per-launch HIP events,
-the CPU oracle timed on a bounded sample of the same operator, and the serving
+the CPU oracle timed on the same operator (one thread and all host threads), and the serving
 stream (1,280 requests on 64 resident matrices, continuous batching vs one at
 a time).
 
@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="aniso200", choices=sorted(WORKLOADS))
     ap.add_argument("--N", type=int, default=None, help="override grid side (testing only)")
-    ap.add_argument("--kernel", default=None, choices=[None, "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
+    ap.add_argument("--kernel", default=None, choices=[None, "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -362,6 +362,14 @@ def main():
     copy_gbps = 2 * cb / (ms_copy * 1e-3) / 1e9
     del src, dst
     log(f"stream copy {copy_gbps:.0f} GB/s")
+    # read-dominant stream shaped like the sweeps' traffic (8 bytes written per 192 read)
+    rb = 43690 * 49152  # just under 2 GiB
+    src = torch.empty(rb // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    rout = torch.empty(rb // 24 // 8, dtype=torch.float64, device="cuda")
+    ms_read = time_steps(torch, lambda: ctx.stream_read(src, rout), 20, 3)
+    read_gbps = (rb + rb // 24) / (ms_read * 1e-3) / 1e9
+    del src, rout
+    log(f"stream read {read_gbps:.0f} GB/s")
 
     def timed(fn, label):
         """Warm up, time the steps (no instrumentation), then run them again with
@@ -675,6 +683,7 @@ def main():
         "layout_GBps": layout_app / (ms * 1e-3) / 1e9,
         "layout_bytes_per_app": layout_app,
         "copy_GBps": copy_gbps,
+        "read_GBps": read_gbps,
         "zero_guess_ms": ms_zero,
         "zero_guess_identical": zero_same,
         "reorder": reorder,
@@ -708,7 +717,10 @@ def main():
                      "layout_bytes_per_launch": dv["layout_bytes"] / dv["launches"],
                      "layout_achieved": ach_layout, "layout_frac": ach_layout / HBM_PEAK_GBPS,
                      "layout_frac_of_copy": ach_layout / copy_gbps,
-                     "traffic_achieved": (traffic / avg_s / 1e9) if traffic else None},
+                     "layout_frac_of_read_ceiling": ach_layout / read_gbps,
+                     "traffic_achieved": (traffic / avg_s / 1e9) if traffic else None,
+                     "traffic_frac": (traffic / avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
+                     "traffic_frac_of_read_ceiling": (traffic / avg_s / 1e9 / read_gbps) if traffic else None},
         "cpu_baseline": cpu,
         "serving": serving,
     }

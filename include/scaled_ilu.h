@@ -71,6 +71,7 @@ extern "C" {
                                   /* is b itself (skips one pass over A when m_L >= 2)       */
 #define SILU_GRAPH 0x20000        /* ilu_smooth: replay the call's sweeps from a hipGraph    */
 #define SILU_REORDER 0x40000      /* ilu_smooth: sweep locality-relabeled copies             */
+#define SILU_SLICED_LOOP 0x80000  /* sliced sweeps: two groups of slots in flight at a time   */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -502,6 +503,14 @@ int silu_stats_reset(silu_ctx *ctx);
  * bandwidth and to calibrate traffic counters.  bytes must be a multiple of
  * 16 and both pointers 16-byte aligned.  Asynchronous. */
 int silu_stream_copy(silu_ctx *ctx, const void *src, void *dst, size_t bytes);
+
+/* Read-dominant calibration stream shaped like a sweep's traffic (8 bytes
+ * written per 192 read, about 96 % reads): reads src[0..bytes) with 16-byte
+ * non-temporal loads and writes bytes / 24 bytes of check words to out.  The
+ * achievable bandwidth for the sweeps' mix of traffic.  bytes a positive
+ * multiple of 49,152; src 16-byte and out 8-byte aligned.  Asynchronous.
+ * Errors: ARG. */
+int silu_stream_read(silu_ctx *ctx, const void *src, size_t bytes, void *out);
 
 /* ---- serving: continuous batching on resident matrices ---------------- */
 

@@ -33,11 +33,12 @@ SILU_DIRECT, SILU_MIXED, SILU_CHECK_FINITE, SILU_VALIDATE, SILU_NO_SCALING = 0x1
 SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x400
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
 SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH, SILU_REORDER = 0x8000, 0x10000, 0x20000, 0x40000
+SILU_SLICED_LOOP = 0x80000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
 # "win": the LDS window wherever it fits; "stream16": offsets at most; "stream32": col_idx always
-KERNELS = {None: 0, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
+KERNELS = {None: 0, "sliced_loop": SILU_SLICED_LOOP, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
            "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR, "win": SILU_KERNEL_STREAM | SILU_WINDOW,
            "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW, "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1
@@ -117,6 +118,7 @@ _sig = {
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "silu_stats_reset": (C.c_int, [_P]),
     "silu_stream_copy": (C.c_int, [_P, _P, _P, C.c_size_t]),
+    "silu_stream_read": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "silu_factor_iluk": (C.c_int, [C.POINTER(silu_host_csr), C.c_int, C.POINTER(silu_host_csr),
                                    C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
     "silu_factor_ilut": (C.c_int, [C.POINTER(silu_host_csr), C.c_double, C.c_int, C.POINTER(silu_host_csr),
@@ -554,6 +556,15 @@ class Context:
         nb = src.numel() * src.element_size()
         self._check(_lib.silu_stream_copy(self._h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nb),
                     "silu_stream_copy")
+
+    def stream_read(self, src: torch.Tensor, out: torch.Tensor):
+        """Read-dominant calibration stream: reads all of src (a multiple of 49,152 bytes),
+        writes src's bytes / 24 to out."""
+        nb = src.numel() * src.element_size()
+        if out.numel() * out.element_size() < nb // 24:
+            raise ValueError("stream_read: out holds fewer than bytes / 24 bytes")
+        self._check(_lib.silu_stream_read(self._h, C.c_void_p(src.data_ptr()), nb, C.c_void_p(out.data_ptr())),
+                    "silu_stream_read")
 
 
 def _release_cb(ctx_ref, key):

@@ -461,9 +461,11 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
         return hip_fail(c, e);
     }
     int64_t slots = 0;
+    int gmax = 0;
     for (int t = 0; t < nslice; t++) {
         sptr[(size_t)t] = (int32_t)std::min<int64_t>(slots, INT32_MAX);
         slots += (int64_t)(sk[(size_t)t] & 0x7fffffff) * 64;
+        gmax = std::max(gmax, (sk[(size_t)t] & 0x7fffffff) >> 2);
         if (sk[(size_t)t] < 0) S.masked_rows += 64;
     }
     // padding beyond 4x the entries (a few very long rows) is not worth the copy
@@ -565,6 +567,7 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     S.v.ndiag = (int)dtab.size();
     S.v.shift = lo;
     S.v.slots = slots;
+    S.v.gmax = gmax;
     S.ok = true;
     return store();
 }
@@ -2116,6 +2119,16 @@ int silu_stream_copy(silu_ctx *c, const void *src, void *dst, size_t bytes)
     return timed_launch(c, 2.0 * (double)bytes, [&](const char **nm) {
         *nm = "stream_copy";
         return launch_copy(src, dst, bytes, c->stream);
+    });
+}
+
+int silu_stream_read(silu_ctx *c, const void *src, size_t bytes, void *out)
+{
+    if (!c || !src || !out || bytes == 0 || bytes % 49152 || ((uintptr_t)src & 15) || ((uintptr_t)out & 7))
+        return SILU_ERR_ARG;
+    return timed_launch(c, (double)bytes + (double)(bytes / 24), [&](const char **nm) {
+        *nm = "stream_read";
+        return launch_read(src, bytes, out, c->stream);
     });
 }
 

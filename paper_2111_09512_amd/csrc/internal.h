@@ -48,6 +48,7 @@ struct SlicedView {
     int ndiag = 0;
     int shift = 0;                 // code 2
     int64_t slots = 0;
+    int gmax = 0;                  // most groups of four slots in one slice
 };
 
 // Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
@@ -122,6 +123,7 @@ struct SweepGeom {
     bool prefer_win = false;          // STREAM: window even where 16-bit offsets fit
     SlicedView sl;                    // SLICED: the sliced copy (attached by the caller)
     int slice_code_min = 1;           // SLICED: narrowest column code allowed (1, 2 or 4 bytes)
+    bool slice_prefetch = true;       // SLICED: a slice's loads all issued up front where it fits
     const uint16_t *slot16 = nullptr; // STREAM, windowed: LDS slot of each entry's iterate value
     const int32_t *wo = nullptr;      // STREAM, windowed: block-relative offset of each slot [lw]
     int lw = 0;
@@ -280,5 +282,7 @@ hipError_t launch_init_flags(int32_t *flags, int count, int32_t value, hipStream
 hipError_t launch_finite_check(int n, const double *x, int32_t *flags, hipStream_t s);
 hipError_t launch_scale_copy(int n, const double *rhs, const double *dinv, double *out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+// Read-dominant calibration stream: reads `bytes` (a multiple of 49,152), writes bytes / 24 to out.
+hipError_t launch_read(const void *src, size_t bytes, void *out, hipStream_t s);
 
 }  // namespace silu

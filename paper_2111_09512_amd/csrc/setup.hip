@@ -570,6 +570,36 @@ hipError_t launch_compress16(int n, const int32_t *rp, const int32_t *col, int r
     return hipGetLastError();
 }
 
+// Read-dominant stream, shaped like a sweep's traffic (about 96 % reads): each
+// tile of 256 lanes reads READ_VECS 16-byte vectors per lane (all loads issued
+// before they are combined, non-temporal) and writes one 8-byte word per lane,
+// 8 bytes written per 192 read.
+constexpr int READ_VECS = 12;
+__global__ void __launch_bounds__(256) k_read16(const u32x4 *__restrict__ src, unsigned long long *__restrict__ out,
+                                                size_t ntiles)
+{
+    for (size_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const size_t base = t * 256 * READ_VECS + threadIdx.x;
+        u32x4 v[READ_VECS];
+#pragma unroll
+        for (int k = 0; k < READ_VECS; ++k) v[k] = __builtin_nontemporal_load(&src[base + (size_t)k * 256]);
+        u32x4 acc = v[0];
+#pragma unroll
+        for (int k = 1; k < READ_VECS; ++k) acc ^= v[k];
+        const unsigned long long w = ((unsigned long long)(acc.x ^ acc.z) << 32) | (acc.y ^ acc.w);
+        __builtin_nontemporal_store(w, &out[t * 256 + threadIdx.x]);
+    }
+}
+
+hipError_t launch_read(const void *src, size_t bytes, void *out, hipStream_t s)
+{
+    const size_t ntiles = bytes / (256 * READ_VECS * 16);
+    if (ntiles == 0) return hipSuccess;
+    const int grid = (int)std::min<size_t>(ntiles, 256 * 16);
+    hipLaunchKernelGGL(k_read16, dim3(grid), dim3(256), 0, s, (const u32x4 *)src, (unsigned long long *)out, ntiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n16 = bytes / 16;

@@ -363,6 +363,111 @@ __device__ __forceinline__ double sliced_wave(const SweepArgs &a, const SlicedVi
     return live ? (double)t : 0.0;
 }
 
+// The same slice with every load of the slice in flight at once (diagonal-
+// table codes, slices of at most GM groups without masked rows): the values
+// and codes of all groups, then all gathers, then the row sum in ascending
+// column order as above.  The loop form above keeps two groups in flight and
+// waits for a group's codes before its gathers, so each wave makes several
+// dependent round trips to memory per slice; here it makes two.  The body is
+// specialised on the slice's exact group count so that it has no branches
+// between the loads (the waits for each group's codes and gathers are then
+// counted exactly instead of draining every load in flight).  The slice
+// header (a wave-uniform index) is read through the scalar cache.
+template <class T, int GG>
+__device__ __forceinline__ typename T::AT slice_sum_pf(const SlicedView &s, int p0, int lane, int row,
+                                                       const typename T::XT *__restrict__ xin, const int32_t *dtab,
+                                                       typename T::AT sum)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using AT = typename T::AT;
+    VT v[GG][4];
+    unsigned c[GG];
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+        if (sizeof(VT) == 8) {
+            const f64x2 *pv = (const f64x2 *)s.val + (p0 >> 1) + 128 * q + lane;
+            const f64x2 lo2 = __builtin_nontemporal_load(pv), hi2 = __builtin_nontemporal_load(pv + 64);
+            v[q][0] = (VT)lo2.x;
+            v[q][1] = (VT)lo2.y;
+            v[q][2] = (VT)hi2.x;
+            v[q][3] = (VT)hi2.y;
+        } else {
+            const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)s.val + (p0 >> 2) + 64 * q + lane);
+            v[q][0] = (VT)v4.x;
+            v[q][1] = (VT)v4.y;
+            v[q][2] = (VT)v4.z;
+            v[q][3] = (VT)v4.w;
+        }
+        c[q] = __builtin_nontemporal_load((const unsigned *)s.codes + (p0 >> 2) + 64 * q + lane);
+    }
+    XT xv[GG][4];
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xv[q][r] = xin[row + dtab[(c[q] >> (8 * r)) & 0xffu]];
+    }
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum = sum + (AT)v[q][r] * (AT)xv[q][r];
+    }
+    return sum;
+}
+
+template <class T, int GG>
+__device__ __forceinline__ typename T::AT slice_sum_pf_g(int G, const SlicedView &s, int p0, int lane, int row,
+                                                         const typename T::XT *__restrict__ xin, const int32_t *dtab,
+                                                         typename T::AT sum)
+{
+    if (G == GG) return slice_sum_pf<T, GG>(s, p0, lane, row, xin, dtab, sum);
+    if constexpr (GG > 1) return slice_sum_pf_g<T, GG - 1>(G, s, p0, lane, row, xin, dtab, sum);
+    return sum;
+}
+
+template <class T, int GM>
+__device__ __forceinline__ double sliced_wave_pf(const SweepArgs &a, const SlicedView &s, int wave,
+                                                 const int32_t *dtab)
+{
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    wave = __builtin_amdgcn_readfirstlane(wave);
+    if (wave >= s.nslice) return 0.0;
+    const int kf = s.sk[wave];
+    const int G = kf >> 2;
+    if (kf < 0 || G > GM || G < 1) return sliced_wave<T, 1, 2>(a, s, wave, dtab);
+    // an unmasked slice: all 64 rows exist and hold entries
+    const int lane = (int)threadIdx.x & 63;
+    const int row = wave * 64 + lane;
+    const int p0 = s.sptr[wave];
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    RT rhs_v = (RT)0;
+    double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
+    if (a.epi != EPI_SPMV) rhs_v = ((const RT *)a.rhs)[row];
+    if (a.epi == EPI_UPDATE) aux = a.x[row];
+    if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
+    if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+    if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
+    if (a.dshift) dsh = a.dshift[row];
+    AT sum = (AT)0;
+    if (a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[row]);
+    sum = slice_sum_pf_g<T, GM>(G, s, p0, lane, row, xin, dtab, sum);
+    const AT t = a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum;
+    epilogue_pre<T>(a, row, t, aux, aux2, cf);
+    return (double)t;
+}
+
+template <class T, int WPB, int GM>
+__global__ void __launch_bounds__(64 * WPB) k_sweep_sliced_pf(SweepArgs a, SlicedView s)
+{
+    __shared__ int32_t dtab[256];
+    for (int t = (int)threadIdx.x; t < s.ndiag; t += 64 * WPB) dtab[t] = s.dtab[t];
+    __syncthreads();
+    const int wave = xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * WPB + ((int)threadIdx.x >> 6);
+    sliced_wave_pf<T, GM>(a, s, wave, dtab);
+}
+
 template <class T, int CODE, int WPB, int UNR>
 __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
 {
@@ -764,6 +869,19 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         constexpr int WPB = 4, UNR = 2;
         if (g.sl.nslice <= 0) return hipErrorInvalidValue;
         const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
+        if (g.slice_prefetch && g.sl.code == 1 && g.sl.gmax >= 1 && g.sl.gmax <= 8) {
+            switch (g.sl.gmax) {
+            case 1: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 1>), grid, block, 0, s, a, g.sl); break;
+            case 2: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 2>), grid, block, 0, s, a, g.sl); break;
+            case 3: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 3>), grid, block, 0, s, a, g.sl); break;
+            case 4: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 4>), grid, block, 0, s, a, g.sl); break;
+            case 5: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 5>), grid, block, 0, s, a, g.sl); break;
+            case 6: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 6>), grid, block, 0, s, a, g.sl); break;
+            case 7: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 7>), grid, block, 0, s, a, g.sl); break;
+            default: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 8>), grid, block, 0, s, a, g.sl); break;
+            }
+            return hipGetLastError();
+        }
         switch (g.sl.code) {
         case 1: hipLaunchKernelGGL((k_sweep_sliced<T, 1, WPB, UNR>), grid, block, 0, s, a, g.sl); break;
         case 2: hipLaunchKernelGGL((k_sweep_sliced<T, 2, WPB, UNR>), grid, block, 0, s, a, g.sl); break;
@@ -885,6 +1003,7 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
         g.allow_win = !(flags & 0x1000) && !(flags & 0x2000);
         g.prefer_win = false;
         g.slice_code_min = (flags & 0x1000) ? 4 : ((flags & 0x8000) ? 2 : 1); // SILU_INDEX32, SILU_CODE16
+        g.slice_prefetch = !(flags & 0x80000);                                // SILU_SLICED_LOOP
         return g;
     }
     // SILU_KERNEL_STREAM: CSR-stream; short rows fill a

@@ -27,7 +27,7 @@ def ctx(B):
     return B.Context()
 
 
-KERNELS = [None, "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
+KERNELS = [None, "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
 
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
@@ -517,3 +517,27 @@ def test_run_twice_deterministic(orc, B, ctx, cases, name):
     for mixed in (False, True):
         twice(lambda x: ctx.gs_smooth(c.Ad, G, b, x, 2, 3, mixed=mixed))
     twice(lambda x: ctx.fgmres(c.Ad, c.F, b, x, restart=10, max_iters=40, tol=1e-10))
+
+
+def test_calibration_streams(B, ctx):
+    """The bandwidth calibration kernels move the bytes they claim: the copy
+    reproduces its source, the read stream's check words are the XOR of the
+    16-byte vectors each lane read (two tiles and a grid-stride remainder)."""
+    import torch
+
+    say("calibration streams")
+    rng = np.random.default_rng(11)
+    nbytes = 3 * 49152
+    words = rng.integers(0, 2**32, nbytes // 4, dtype=np.uint64).astype(np.uint32)
+    src = torch.from_numpy(words.view(np.int32).copy()).cuda()
+    dst = torch.zeros_like(src)
+    ctx.stream_copy(src, dst)
+    np.testing.assert_array_equal(host(dst), words.view(np.int32))
+    out = torch.zeros(nbytes // 24 // 8, dtype=torch.int64, device="cuda")
+    ctx.stream_read(src, out)
+    v = words.reshape(3, 12, 256, 4)  # tile, vector k, lane, 32-bit word
+    acc = np.bitwise_xor.reduce(v, axis=1).astype(np.uint64)  # [tile, lane, 4]
+    want = ((acc[..., 0] ^ acc[..., 2]) << np.uint64(32)) | (acc[..., 1] ^ acc[..., 3])
+    np.testing.assert_array_equal(host(out).view(np.uint64), want.reshape(-1))
+    with pytest.raises(B.SiluError):
+        ctx.stream_read(src[:1000], out)
