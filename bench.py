@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="aniso200", choices=sorted(WORKLOADS))
     ap.add_argument("--N", type=int, default=None, help="override grid side (testing only)")
-    ap.add_argument("--kernel", default=None, choices=[None, "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
+    ap.add_argument("--kernel", default=None, choices=[None, "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -465,8 +465,31 @@ def main():
                                               "GBps": v["bytes"] / v["ms"] / 1e6} for k, v in st_r.items()}}
             if not mixed:
                 reorder["fp64"]["identical_to_plain"] = bool(torch.equal(x, x64))
+        # the same with b and x kept in the copies' order across calls (SILU_RELABELED):
+        # moved in once and out once, outside the timed applications
+        b_rel = ctx.reorder_vectors(Ad, F, bvec)
+        x_rel = torch.zeros_like(x)
+        ws_rel = ctx.workspace(n, B.SILU_REORDER | B.SILU_RELABELED)
+        for label, mixed in (("fp64", False), ("mixed", True)):
+            def app_rel():
+                x_rel.zero_()
+                ctx.ilu_smooth(Ad, F, b_rel, x_rel, outer, mL, mU, mixed=mixed, kernel=kern, ws=ws_rel, reorder=True,
+                               relabeled=True)
+
+            ms_r, bytes_r, st_r = timed(app_rel, f"relabeled vectors {label}")
+            lb_r = st_r.pop("_layout_bytes_per_app")
+            reorder[f"{label}_relabeled_vectors"] = {
+                "ms": ms_r, "apps_per_s": 1e3 / ms_r, "GBps": bytes_r / (ms_r * 1e-3) / 1e9,
+                "layout_GBps": lb_r / (ms_r * 1e-3) / 1e9,
+                "kernels": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                                "GBps": v["bytes"] / v["ms"] / 1e6} for k, v in st_r.items()}}
+            if not mixed:
+                back = ctx.reorder_vectors(Ad, F, x_rel, to_relabeled=False)
+                reorder["fp64_relabeled_vectors"]["identical_to_plain"] = bool(torch.equal(back, x64))
         log(f"reorder: set-up {setup_s:.1f} s, FP64 {reorder['fp64']['ms']:.3f} ms, mixed {reorder['mixed']['ms']:.3f} ms, "
-            f"identical {reorder['fp64']['identical_to_plain']}")
+            f"identical {reorder['fp64']['identical_to_plain']}; vectors kept relabeled: FP64 "
+            f"{reorder['fp64_relabeled_vectors']['ms']:.3f} ms, mixed {reorder['mixed_relabeled_vectors']['ms']:.3f} ms, "
+            f"identical {reorder['fp64_relabeled_vectors']['identical_to_plain']}")
 
     # ---- mixed form ----
     ms_mixed = bytes_mixed = mixed_err = None

@@ -72,6 +72,10 @@ extern "C" {
 #define SILU_GRAPH 0x20000        /* ilu_smooth: replay the call's sweeps from a hipGraph    */
 #define SILU_REORDER 0x40000      /* ilu_smooth: sweep locality-relabeled copies             */
 #define SILU_SLICED_LOOP 0x80000  /* sliced sweeps: two groups of slots in flight at a time   */
+#define SILU_CODE8 0x100000       /* sliced sweeps: a 1-byte diagonal code per slot instead of */
+                                  /* the per-row pattern table                                */
+#define SILU_RELABELED 0x200000   /* ilu_smooth with SILU_REORDER: b and x are already in the  */
+                                  /* relabeled order (silu_reorder_vectors); no permutations  */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -272,6 +276,18 @@ int ilu_smooth(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const do
 /* Same with separate inner iteration counts for the L and the U factor. */
 int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
                 int outer_sweeps, int m_L, int m_U, int flags, void *ws, size_t ws_bytes);
+
+/* Moves a vector into the order of the SILU_REORDER copies of (A, F)
+ * (to_relabeled = 1: dst[k] = src[order[k]]) or back (0: dst[order[k]] =
+ * src[k]); the copies are built first if they are not cached (synchronous
+ * then, as for ilu_smooth with SILU_REORDER).  A caller that smooths the same
+ * vectors many times moves b and x in once, calls ilu_smooth with SILU_REORDER
+ * | SILU_RELABELED (which then permutes nothing and needs only the four-vector
+ * workspace of the plain call), and moves x back once; the result is the
+ * plain call's bit for bit.  src, dst: device FP64 [n], distinct.
+ * Asynchronous.  Errors: ARG, SHAPE, HIP. */
+int silu_reorder_vectors(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *src, double *dst,
+                         int to_relabeled);
 
 /* The relabeling of SILU_REORDER, on HOST arrays: reverse Cuthill-McKee on
  * the graph of strong couplings, row i coupled to j != i when |a_ij| >= theta
@@ -641,11 +657,13 @@ int silu_server_last_hip_error(const silu_server *server);
 #define SILU_SERVE_STEPWISE 0
 #define SILU_SERVE_PERSISTENT 1
 int silu_server_set_mode(silu_server *server, int mode, int max_workgroups);
-/* Polls a persistent launch's bounded wait makes before it gives up (each
- * poll follows a sleep of about 0.1 us; 0 restores the default 262144).  For
- * tests of the failure path: a limit of 1 makes most waits expire, and the
- * launch still drains and reports SILU_ERR_TIMEOUT through poll. */
-int silu_server_set_wait_limit(silu_server *server, int polls);
+/* Wall-clock time in microseconds a persistent launch's bounded wait may
+ * take before it gives up (measured on the device's constant-rate clock, so
+ * the bound holds however long each poll takes; 0 restores the default
+ * 200,000).  For tests of the failure path: a limit of 1 makes most waits
+ * expire, and the launch still drains and reports SILU_ERR_TIMEOUT through
+ * poll. */
+int silu_server_set_wait_limit(silu_server *server, int microseconds);
 
 #ifdef __cplusplus
 }

@@ -34,11 +34,13 @@ SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_KERNEL_BLOCKED = 0x100, 0x200, 0x40
 SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000, 0x4000
 SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH, SILU_REORDER = 0x8000, 0x10000, 0x20000, 0x40000
 SILU_SLICED_LOOP = 0x80000
+SILU_CODE8 = 0x100000
+SILU_RELABELED = 0x200000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
 # "win": the LDS window wherever it fits; "stream16": offsets at most; "stream32": col_idx always
-KERNELS = {None: 0, "sliced_loop": SILU_SLICED_LOOP, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
+KERNELS = {None: 0, "sliced8": SILU_CODE8, "sliced_loop": SILU_CODE8 | SILU_SLICED_LOOP, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
            "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR, "win": SILU_KERNEL_STREAM | SILU_WINDOW,
            "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW, "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1
@@ -119,6 +121,7 @@ _sig = {
     "silu_stats_reset": (C.c_int, [_P]),
     "silu_stream_copy": (C.c_int, [_P, _P, _P, C.c_size_t]),
     "silu_stream_read": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "silu_reorder_vectors": (C.c_int, [_P, _P, _P, _P, _P, C.c_int]),
     "silu_factor_iluk": (C.c_int, [C.POINTER(silu_host_csr), C.c_int, C.POINTER(silu_host_csr),
                                    C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
     "silu_factor_ilut": (C.c_int, [C.POINTER(silu_host_csr), C.c_double, C.c_int, C.POINTER(silu_host_csr),
@@ -476,17 +479,18 @@ class Context:
                    m_U: int | None = None, direct: bool = False, mixed: bool = False, check_finite: bool = False,
                    validate: bool = False, kernel: str | None = None, ws: torch.Tensor | None = None,
                    graph: bool = True, zero_guess: bool = False, record: bool = False,
-                   reorder: bool = False) -> torch.Tensor:
+                   reorder: bool = False, relabeled: bool = False) -> torch.Tensor:
         """x <- x + M^{-1}(b - A x), `outer_sweeps` times, in place on x (returned).
         zero_guess: x holds zeros on entry (the first residual is b).
         record: replay the call's sweep sequence from a hipGraph recorded on the
         first call with the same tensors and counts (SILU_GRAPH).
-        reorder: sweep locality-relabeled copies (SILU_REORDER; same results)."""
+        reorder: sweep locality-relabeled copies (SILU_REORDER; same results).
+        relabeled: with reorder, b and x are already in the copies' order (reorder_vectors)."""
         m_U = m_L if m_U is None else m_U
         flags = ((SILU_DIRECT if direct else 0) | (SILU_MIXED if mixed else 0) | (SILU_ZERO_GUESS if zero_guess else 0) |
                  (SILU_CHECK_FINITE if check_finite else 0) | (SILU_VALIDATE if validate else 0) |
                  (0 if graph else SILU_NO_GRAPH) | (SILU_GRAPH if record else 0) |
-                 (SILU_REORDER if reorder else 0) | KERNELS[kernel])
+                 (SILU_REORDER if reorder else 0) | (SILU_RELABELED if relabeled else 0) | KERNELS[kernel])
         _vec(b, A.n, "b")
         _vec(x, A.n, "x")
         ws = self.workspace(A.n, flags) if ws is None else ws
@@ -496,6 +500,18 @@ class Context:
                                      C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags,
                                      C.c_void_p(ws.data_ptr()), ws.numel()), "ilu_smooth")
         return x
+
+    def reorder_vectors(self, A: Csr, F: Factors, src: torch.Tensor, to_relabeled: bool = True,
+                        out: torch.Tensor | None = None) -> torch.Tensor:
+        """src moved into the order of the SILU_REORDER copies of (A, F), or back."""
+        _vec(src, A.n, "src")
+        out = torch.empty_like(src) if out is None else out
+        self._track(A, F.Ls, F.Us, values=((), (F.Ls_val32,), (F.Us_val32,)))
+        Ac, Fc = A.c(), F.c()
+        self._check(_lib.silu_reorder_vectors(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(src.data_ptr()),
+                                              C.c_void_p(out.data_ptr()), 1 if to_relabeled else 0),
+                    "silu_reorder_vectors")
+        return out
 
     def trisolve_direct(self, T: Csr, uplo: int, diag: int, rhs: torch.Tensor, out: torch.Tensor | None = None,
                         validate: bool = False, graph: bool = True) -> torch.Tensor:
@@ -693,9 +709,9 @@ class Server:
         per admitted batch running every sweep of its requests)."""
         self._check(_lib.silu_server_set_mode(self._h, mode, max_workgroups), "silu_server_set_mode")
 
-    def set_wait_limit(self, polls: int):
-        """Polls before a persistent launch's wait gives up (0: default)."""
-        self._check(_lib.silu_server_set_wait_limit(self._h, polls), "silu_server_set_wait_limit")
+    def set_wait_limit(self, microseconds: int):
+        """Wall-clock bound of one wait inside a persistent launch, in microseconds (0: default)."""
+        self._check(_lib.silu_server_set_wait_limit(self._h, microseconds), "silu_server_set_wait_limit")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -13,7 +13,7 @@ HIPCC = os.path.join(ROCM, "bin", "hipcc")
 CLANGXX = os.path.join(ROCM, "llvm", "bin", "clang++")
 
 HIP_SOURCES = ["sweep.hip", "setup.hip", "krylov.hip", "fixedpoint.hip", "reorder.hip", "api.hip", "serve.hip"]
-CXX_SOURCES = ["factor.cpp", "order.cpp"]
+CXX_SOURCES = ["factor.cpp", "order.cpp", "plan.cpp"]
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # no packed-FP32 instructions anywhere in device code

@@ -13,6 +13,7 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <new>
 #include <string>
 #include <tuple>
@@ -59,7 +60,8 @@ using CompKey = std::tuple<const void *, const void *, int64_t, int64_t, int>;
 // code width allowed.
 struct Sliced {
     SlicedView v;
-    int32_t *sptr = nullptr, *sk = nullptr, *dtab = nullptr;
+    int32_t *sptr = nullptr, *sk = nullptr, *dtab = nullptr, *ptab = nullptr;
+    uint8_t *pid = nullptr;
     void *val = nullptr, *codes = nullptr;
     int64_t masked_rows = 0;
     bool ok = false;
@@ -105,6 +107,8 @@ void free_sliced(Sliced &S)
     (void)hipFree(S.dtab);
     (void)hipFree(S.val);
     (void)hipFree(S.codes);
+    (void)hipFree(S.ptab);
+    (void)hipFree(S.pid);
     S = Sliced();
 }
 
@@ -203,7 +207,8 @@ template <class F>
 int timed_launch(silu_ctx *c, double bytes, double layout, F &&fn)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    const bool timing = c->timing;
+    if (timing) {
         HIPCHK(c, get_event(c, &e0));
         HIPCHK(c, get_event(c, &e1));
         HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -215,7 +220,7 @@ int timed_launch(silu_ctx *c, double bytes, double layout, F &&fn)
         c->rec_bytes += bytes;
         c->rec_layout += layout;
     }
-    if (c->timing) {
+    if (timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->pending.push_back({kernel_id(c, name), e0, e1, bytes, layout});
     }
@@ -440,9 +445,57 @@ int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, int win_policy, Comp
     return SILU_OK;
 }
 
+// Row patterns of N: the distinct sequences of offsets col - row (a row's
+// pattern includes its length).  Fills pid[r] (rows past n: 0) and the table
+// of offsets, kp per pattern, each pattern's last offset repeated into its
+// padded slots (an empty row: offset 0).  False when there are more than 256
+// patterns or the table would exceed PAT_MAX_ENTRIES offsets.
+bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<int32_t> &col, int kp,
+                  std::vector<uint8_t> &pid, std::vector<int32_t> &ptab, int *npat)
+{
+    std::unordered_map<uint64_t, std::vector<int>> by_hash;
+    std::vector<int64_t> first_row; // a row holding each pattern
+    pid.assign((size_t)((n + 63) / 64 * 64), 0);
+    for (int64_t r = 0; r < n; r++) {
+        const int32_t a = rp[(size_t)r], b = rp[(size_t)r + 1];
+        uint64_t h = 1469598103934665603ull ^ (uint64_t)(b - a);
+        for (int32_t e = a; e < b; e++) h = (h ^ (uint64_t)(uint32_t)(col[(size_t)e] - (int32_t)r)) * 1099511628211ull;
+        auto &cands = by_hash[h];
+        int found = -1;
+        for (int p : cands) {
+            const int64_t q = first_row[(size_t)p];
+            const int32_t qa = rp[(size_t)q], qb = rp[(size_t)q + 1];
+            if (qb - qa != b - a) continue;
+            bool same = true;
+            for (int32_t k = 0; k < b - a && same; k++)
+                same = col[(size_t)(qa + k)] - (int32_t)q == col[(size_t)(a + k)] - (int32_t)r;
+            if (same) {
+                found = p;
+                break;
+            }
+        }
+        if (found < 0) {
+            found = (int)first_row.size();
+            if (found >= 256 || (int64_t)(found + 1) * kp > PAT_MAX_ENTRIES) return false;
+            first_row.push_back(r);
+            cands.push_back(found);
+        }
+        pid[(size_t)r] = (uint8_t)found;
+    }
+    *npat = (int)first_row.size();
+    ptab.assign((size_t)*npat * (size_t)kp, 0);
+    for (int p = 0; p < *npat; p++) {
+        const int64_t q = first_row[(size_t)p];
+        const int32_t qa = rp[(size_t)q], len = rp[(size_t)q + 1] - qa;
+        for (int k = 0; k < kp; k++)
+            ptab[(size_t)p * kp + k] = len == 0 ? 0 : col[(size_t)(qa + std::min(k, len - 1))] - (int32_t)q;
+    }
+    return true;
+}
+
 // Build (once) the sliced-ELL copy of N with values `val` of `vbytes` bytes.
-// code_min: 1 allows the diagonal table, 2 starts at 16-bit offsets, 4 uses
-// columns.  *out->ok is false when the matrix has no entries or the copy
+// code_min: 0 allows the row-pattern table, 1 the diagonal table, 2 starts at
+// 16-bit offsets, 4 uses columns.  *out->ok is false when the matrix has no entries or the copy
 // would not fit 32-bit slot indices (the caller then streams the CSR).
 int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced &S)
 {
@@ -473,12 +526,28 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
         free_sliced(S);
         return store();
     }
-    // column codes: the diagonal table when at most 256 distinct col - row
-    // occur, else 16-bit slice-relative offsets when they fit, else columns
+    // column codes: none when the rows follow at most 256 patterns (a table
+    // of offsets per pattern and one byte per row), else the diagonal table
+    // when at most 256 distinct col - row occur, else 16-bit slice-relative
+    // offsets when they fit, else columns
     int code = 4, lo = 0;
-    std::vector<int32_t> dtab, dmap;
+    std::vector<int32_t> dtab, dmap, ptab;
+    std::vector<uint8_t> pid;
+    int npat = 0;
     int32_t range[2];
-    if (code_min <= 1) {
+    if (code_min <= 0 && gmax >= 1 && gmax <= 8) { // the pattern kernels take up to 8 groups
+        std::vector<int32_t> hrp((size_t)n + 1), hcol((size_t)N->nnz);
+        e = hipMemcpyAsync(hrp.data(), N->row_ptr, hrp.size() * 4, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hcol.data(), N->col_idx, hcol.size() * 4, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            free_sliced(S);
+            return hip_fail(c, e);
+        }
+        if (row_patterns(n, hrp, hcol, 4 * gmax, pid, ptab, &npat)) code = 8;
+    }
+    if (code == 4 && code_min <= 1) {
         HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
         HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
         HIPCHK(c, launch_offset_range(n, N->row_ptr, N->col_idx, 1, c->d_flags, c->stream));
@@ -539,7 +608,14 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     e = hipMalloc(&S.sptr, (size_t)nslice * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(S.sptr, sptr.data(), (size_t)nslice * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMalloc(&S.val, (size_t)slots * (size_t)vbytes);
-    if (e == hipSuccess) e = hipMalloc(&S.codes, (size_t)slots * (size_t)code);
+    if (e == hipSuccess && code != 8) e = hipMalloc(&S.codes, (size_t)slots * (size_t)code);
+    if (e == hipSuccess && code == 8) {
+        e = hipMalloc(&S.ptab, ptab.size() * 4);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMalloc(&S.pid, pid.size());
+        if (e == hipSuccess) e = hipMemcpyAsync(S.pid, pid.data(), pid.size(), hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess && code == 1) {
         e = hipMalloc(&S.dtab, dtab.size() * 4);
         if (e == hipSuccess)
@@ -568,6 +644,10 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     S.v.shift = lo;
     S.v.slots = slots;
     S.v.gmax = gmax;
+    S.v.pid = S.pid;
+    S.v.ptab = S.ptab;
+    S.v.npat = npat;
+    S.v.kp = code == 8 ? 4 * gmax : 0;
     S.ok = true;
     return store();
 }
@@ -604,8 +684,10 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
             g.sl = S->v;
             const double xb = (p == Prec::MIX_L || p == Prec::MIX_U) ? 4.0 : 8.0;
             const double rb = p == Prec::MIX_U ? 4.0 : 8.0;
-            sliced_bytes = (double)S->v.slots * (vbytes + S->v.code) + 8.0 * S->v.nslice +
-                           8.0 * (double)S->masked_rows + (double)N->n_rows * (xb + rb) + 4.0 * S->v.ndiag;
+            const int cb = S->v.code == 8 ? 0 : S->v.code; // row patterns: one byte per row instead
+            sliced_bytes = (double)S->v.slots * (vbytes + cb) + 8.0 * S->v.nslice +
+                           8.0 * (double)S->masked_rows + (double)N->n_rows * (xb + rb) + 4.0 * S->v.ndiag +
+                           (S->v.code == 8 ? (double)N->n_rows + 4.0 * S->v.npat * S->v.kp : 0.0);
         } else {
             g.kind = SweepKernel::STREAM; // no entries, too large for the sliced copy, or no structure
         }
@@ -1035,7 +1117,7 @@ const char *silu_status_string(int s)
 int silu_workspace_size(silu_ctx *c, int64_t n, int flags, size_t *bytes)
 {
     if (!c || !bytes || n < 0) return SILU_ERR_ARG;
-    *bytes = ((flags & SILU_REORDER) ? 6 : 4) * ws_vec_bytes(n);
+    *bytes = ((flags & SILU_REORDER) && !(flags & SILU_RELABELED) ? 6 : 4) * ws_vec_bytes(n);
     return SILU_OK;
 }
 
@@ -1163,11 +1245,18 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         if ((st = validate(c, &F->Ls, -1))) return st;
         if ((st = validate(c, &F->Us, 1))) return st;
     }
+    if ((flags & SILU_RELABELED) && !(flags & SILU_REORDER)) return SILU_ERR_ARG;
     if (flags & SILU_REORDER) {
         // the same steps on the relabeled copies: b and x in, x out
         if (direct) return SILU_ERR_UNSUPPORTED;
         Reorder *R = nullptr;
         if ((st = get_reorder(c, A, F, &R))) return st;
+        if (flags & SILU_RELABELED) { // b and x are already in the relabeled order
+            const silu_factors F2 = relabeled_factors(F, R);
+            const int inner = flags & ~(SILU_REORDER | SILU_RELABELED | SILU_CHECK_FINITE | SILU_VALIDATE);
+            if ((st = smooth_plain(c, &R->A2, &F2, b, x, outer_sweeps, m_L, m_U, inner, ws, ws_bytes))) return st;
+            return (flags & SILU_CHECK_FINITE) ? check_finite(c, n, x) : SILU_OK;
+        }
         Ws w{(char *)ws, ws_vec_bytes(n)};
         double *b2 = (double *)w.slot(4), *x2 = (double *)w.slot(5);
         const double vb = 20.0 * (double)n; // index, read, write
@@ -2119,6 +2208,26 @@ int silu_stream_copy(silu_ctx *c, const void *src, void *dst, size_t bytes)
     return timed_launch(c, 2.0 * (double)bytes, [&](const char **nm) {
         *nm = "stream_copy";
         return launch_copy(src, dst, bytes, c->stream);
+    });
+}
+
+int silu_reorder_vectors(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *src, double *dst,
+                         int to_relabeled)
+{
+    if (!c || !A || !F || !src || !dst || src == dst || (to_relabeled != 0 && to_relabeled != 1)) return SILU_ERR_ARG;
+    int st = check_square(A, SILU_F64);
+    if (st) return st;
+    if ((st = check_square(&F->Ls, SILU_F64))) return st;
+    if ((st = check_square(&F->Us, SILU_F64))) return st;
+    const int64_t n = A->n_rows;
+    if (F->Ls.n_rows != n || F->Us.n_rows != n) return SILU_ERR_SHAPE;
+    if (!F->dinv || (!F->scaled && !F->d) || (F->scaled == 2 && !F->dc)) return SILU_ERR_ARG;
+    Reorder *R = nullptr;
+    if ((st = get_reorder(c, A, F, &R))) return st;
+    return timed_launch(c, 20.0 * (double)n, [&](const char **nm) {
+        *nm = to_relabeled ? "reorder_in" : "reorder_out";
+        return to_relabeled ? launch_permute_in((int)n, R->pos, src, nullptr, dst, nullptr, c->stream)
+                            : launch_scatter((int)n, R->order, src, dst, c->stream);
     });
 }
 

@@ -49,7 +49,15 @@ struct SlicedView {
     int shift = 0;                 // code 2
     int64_t slots = 0;
     int gmax = 0;                  // most groups of four slots in one slice
+    // code 8 (row patterns): no per-slot code; row r's slots gather at
+    // r + ptab[pid[r] * kp + k] (the row's offsets col - r in ascending order,
+    // the last one repeated into its padded slots)
+    const uint8_t *pid = nullptr;  // [nslice * 64] pattern of each row
+    const int32_t *ptab = nullptr; // [npat * kp]
+    int npat = 0, kp = 0;
 };
+// Row-pattern tables are kept to at most this many offsets (16 KB of LDS).
+constexpr int PAT_MAX_ENTRIES = 4096;
 
 // Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
 // and RB_CAP entries per workgroup (a longer row gets a workgroup alone).
@@ -240,9 +248,9 @@ struct PersistPlan {
     int32_t *done;        // [nops]
     const SweepArgs *ops; // [nops]
     int nops;
-    int spin_limit;       // polls before a wait gives up (>= 1)
+    long long wait_ticks; // wall-clock ticks (wall_clock64) a wait may take before it gives up (>= 1)
 };
-constexpr int PERSIST_SPIN_LIMIT = 1 << 18;
+constexpr int PERSIST_WAIT_US = 200000; // default bound of one wait, in microseconds
 hipError_t launch_sweep_persist(const PersistPlan &p, int grid, hipStream_t s);
 
 struct LevelArgs {

@@ -34,6 +34,7 @@
 
 #include "../../include/scaled_ilu.h"
 #include "internal.h"
+#include "plan.h"
 
 using namespace silu;
 
@@ -179,7 +180,8 @@ struct silu_server {
     // persistent mode
     int mode = 0;
     int max_wg = DEFAULT_MAX_WG;
-    int spin_limit = PERSIST_SPIN_LIMIT;
+    int wait_us = PERSIST_WAIT_US;  // bound of one wait inside a persistent launch
+    long long clock_khz = 0;        // the device's wall_clock64 rate
     hipStream_t ps[PSTREAMS] = {};
     hipEvent_t ev_in = nullptr;
     char *h_plan[RING] = {};
@@ -465,18 +467,16 @@ size_t align64(size_t v) { return (v + 63) & ~(size_t)63; }
 // counters.
 int launch_persistent(silu_server *s, std::vector<Request> &batch)
 {
-    std::stable_sort(batch.begin(), batch.end(), [s](const Request &a, const Request &b) {
-        return s->mats[(size_t)a.mid].A.n_rows * a.total < s->mats[(size_t)b.mid].A.n_rows * b.total;
-    });
-    int64_t nops = 0, tiles = 0, grid = 0;
-    for (const Request &q : batch) {
-        const int64_t t = (s->mats[(size_t)q.mid].A.n_rows + SERVE_RPB - 1) / SERVE_RPB;
-        nops += q.total;
-        tiles += t * q.total;
-        grid += 2 * t; // one op's tiles at work, the next op's waiting
+    std::vector<int64_t> rows(batch.size());
+    std::vector<int> nop(batch.size()), order;
+    for (size_t r = 0; r < batch.size(); r++) {
+        rows[r] = s->mats[(size_t)batch[r].mid].A.n_rows;
+        nop[r] = batch[r].total;
     }
-    if (nops > (1 << 24) || tiles > INT32_MAX - (1 << 20)) return SILU_ERR_UNSUPPORTED;
-    grid = std::min<int64_t>(grid, s->max_wg);
+    std::vector<int32_t> pfirst, pdep;
+    int64_t grid = 0;
+    if (!persist_plan(rows, nop, SERVE_RPB, s->max_wg, order, pfirst, pdep, &grid)) return SILU_ERR_UNSUPPORTED;
+    const int64_t nops = (int64_t)pdep.size(), tiles = pfirst.back();
     const size_t n_int = 4 + (size_t)(nops + 1) + 2 * (size_t)nops;
     const size_t ops_off = align64(n_int * sizeof(int32_t));
     const size_t bytes = ops_off + (size_t)nops * sizeof(SweepArgs);
@@ -502,20 +502,18 @@ int launch_persistent(silu_server *s, std::vector<Request> &batch)
     ctl[1] = 0;
     ctl[2] = (int32_t)nops;
     ctl[3] = (int32_t)tiles;
-    int64_t i = 0, t0 = 0;
-    for (const Request &q : batch) {
-        const int64_t t = (s->mats[(size_t)q.mid].A.n_rows + SERVE_RPB - 1) / SERVE_RPB;
-        Request r = q;
+    int64_t i = 0;
+    for (int r : order) {
+        Request q = batch[(size_t)r];
         for (int j = 0; j < q.total; j++, i++) {
-            r.op = j;
-            ops[i] = op_of(s, r);
-            first[i] = (int32_t)t0;
-            dep[i] = j == 0 ? -1 : (int32_t)(i - 1);
+            q.op = j;
+            ops[i] = op_of(s, q);
+            first[i] = pfirst[(size_t)i];
+            dep[i] = pdep[(size_t)i];
             done[i] = 0;
-            t0 += t;
         }
     }
-    first[nops] = (int32_t)tiles;
+    first[nops] = pfirst[(size_t)nops];
     hipStream_t ps = s->ps[s->steps % PSTREAMS];
     char *d = s->d_plan[slot];
     PersistPlan p;
@@ -525,7 +523,7 @@ int launch_persistent(silu_server *s, std::vector<Request> &batch)
     p.done = (int32_t *)p.dep + nops;
     p.ops = (const SweepArgs *)(d + ops_off);
     p.nops = (int)nops;
-    p.spin_limit = s->spin_limit;
+    p.wait_ticks = std::max<long long>(1, (long long)s->wait_us * s->clock_khz / 1000);
     e = hipEventRecord(s->ev_in, s->stream); // b and x are produced on the caller's stream
     if (e == hipSuccess) e = hipStreamWaitEvent(ps, s->ev_in, 0);
     if (e == hipSuccess) e = hipMemcpyAsync(d, s->h_plan[slot], bytes, hipMemcpyHostToDevice, ps);
@@ -574,6 +572,11 @@ int create_persistent(silu_server *s)
         if (!s->ps[i] && (e = hipStreamCreateWithFlags(&s->ps[i], hipStreamNonBlocking)) != hipSuccess)
             return fail(s, e);
     if (!s->ev_in && (e = hipEventCreateWithFlags(&s->ev_in, hipEventDisableTiming)) != hipSuccess) return fail(s, e);
+    int dev = 0, khz = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return fail(s, e);
+    if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess) return fail(s, e);
+    if (khz <= 0) return SILU_ERR_UNSUPPORTED;
+    s->clock_khz = khz;
     for (int i = 0; i < RING; i++) {
         if (!s->h_ctl[i]) {
             if ((e = hipHostMalloc((void **)&s->h_ctl[i], 4 * sizeof(int32_t))) != hipSuccess) return fail(s, e);
@@ -1044,10 +1047,10 @@ int silu_server_wait(silu_server *s, int64_t ticket)
     }
 }
 
-int silu_server_set_wait_limit(silu_server *s, int polls)
+int silu_server_set_wait_limit(silu_server *s, int microseconds)
 {
-    if (!s || polls < 0) return SILU_ERR_ARG;
-    s->spin_limit = polls ? polls : PERSIST_SPIN_LIMIT;
+    if (!s || microseconds < 0) return SILU_ERR_ARG;
+    s->wait_us = microseconds ? microseconds : PERSIST_WAIT_US;
     return SILU_OK;
 }
 

@@ -400,7 +400,8 @@ __device__ __forceinline__ int64_t value_slot(int64_t base, int k, int lane, int
 // repeats the row's last column with value 0 (an empty row: its own column),
 // so an unmasked sweep reads only columns the row reads anyway.  Codes: 1 =
 // u8 index into the diagonal table (dmap[col - row - dlo]), 2 = u16 offset
-// col - 64 s - shift, 4 = the int32 column.
+// col - 64 s - shift, 4 = the int32 column, 8 = none (the row's pattern
+// table entry gives its columns).
 template <typename VT, int CODE>
 __global__ void __launch_bounds__(256) k_fill_sliced(int n, int nslice, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col, const VT *__restrict__ val,
@@ -419,6 +420,7 @@ __global__ void __launch_bounds__(256) k_fill_sliced(int n, int nslice, const in
         const int c = k < len ? col[p0 + k] : last;
         sval[value_slot(base, k, lane, (int)sizeof(VT))] = k < len ? val[p0 + k] : (VT)0;
         const int64_t pc = base + 256 * (k >> 2) + 4 * lane + (k & 3);
+        if (CODE == 8) continue; // row patterns: no per-slot code
         if (CODE == 1) ((uint8_t *)scode)[pc] = (uint8_t)dmap[c - min(r, n - 1) - lo];
         else if (CODE == 2) ((uint16_t *)scode)[pc] = (uint16_t)(c - s * 64 - lo);
         else ((int32_t *)scode)[pc] = c;
@@ -627,11 +629,13 @@ hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_
     hipLaunchKernelGGL((k_fill_sliced<VT, C>), g, b, 0, s, n, nslice, rp, col, (const VT *)val, sptr, sk, dmap, lo,     \
                        (VT *)sval, scode)
     if (val_bytes == 8) {
-        if (code == 1) SILU_FILL(double, 1);
+        if (code == 8) SILU_FILL(double, 8);
+        else if (code == 1) SILU_FILL(double, 1);
         else if (code == 2) SILU_FILL(double, 2);
         else SILU_FILL(double, 4);
     } else {
-        if (code == 1) SILU_FILL(float, 1);
+        if (code == 8) SILU_FILL(float, 8);
+        else if (code == 1) SILU_FILL(float, 1);
         else if (code == 2) SILU_FILL(float, 2);
         else SILU_FILL(float, 4);
     }

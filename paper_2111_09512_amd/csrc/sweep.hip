@@ -468,6 +468,148 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced_pf(SweepArgs a, Slice
     sliced_wave_pf<T, GM>(a, s, wave, dtab);
 }
 
+// Row-pattern slices (code 8): no per-slot code at all.  Row r's slot k gathers
+// at r + pt[k], pt being the row's pattern in the table that the workgroup
+// keeps in LDS (the row's offsets col - r in ascending order, its last offset
+// repeated into the padded slots), found through one byte per row.  A group's
+// four offsets are one 16-byte LDS read.  Unmasked slices of at most GM groups
+// take the prefetched body (every value load in flight, then every gather);
+// masked slices (an empty row, rows past the end) the loop below with per-row
+// lengths.  The sums and padding are those of the coded layouts, so results
+// are the same bit for bit.
+template <class T, int GG>
+__device__ __forceinline__ typename T::AT slice_sum_pat(const SlicedView &s, int p0, int lane, int row,
+                                                        const typename T::XT *__restrict__ xin, const int32_t *pt,
+                                                        typename T::AT sum)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using AT = typename T::AT;
+    VT v[GG][4];
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+        if (sizeof(VT) == 8) {
+            const f64x2 *pv = (const f64x2 *)s.val + (p0 >> 1) + 128 * q + lane;
+            const f64x2 lo2 = __builtin_nontemporal_load(pv), hi2 = __builtin_nontemporal_load(pv + 64);
+            v[q][0] = (VT)lo2.x;
+            v[q][1] = (VT)lo2.y;
+            v[q][2] = (VT)hi2.x;
+            v[q][3] = (VT)hi2.y;
+        } else {
+            const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)s.val + (p0 >> 2) + 64 * q + lane);
+            v[q][0] = (VT)v4.x;
+            v[q][1] = (VT)v4.y;
+            v[q][2] = (VT)v4.z;
+            v[q][3] = (VT)v4.w;
+        }
+    }
+    XT xv[GG][4];
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+        const i32x4 o = *(const i32x4 *)(pt + 4 * q);
+        xv[q][0] = xin[row + o.x];
+        xv[q][1] = xin[row + o.y];
+        xv[q][2] = xin[row + o.z];
+        xv[q][3] = xin[row + o.w];
+    }
+#pragma unroll
+    for (int q = 0; q < GG; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sum = sum + (AT)v[q][r] * (AT)xv[q][r];
+    }
+    return sum;
+}
+
+template <class T, int GG>
+__device__ __forceinline__ typename T::AT slice_sum_pat_g(int G, const SlicedView &s, int p0, int lane, int row,
+                                                          const typename T::XT *__restrict__ xin, const int32_t *pt,
+                                                          typename T::AT sum)
+{
+    if (G == GG) return slice_sum_pat<T, GG>(s, p0, lane, row, xin, pt, sum);
+    if constexpr (GG > 1) return slice_sum_pat_g<T, GG - 1>(G, s, p0, lane, row, xin, pt, sum);
+    return sum;
+}
+
+template <class T, int GM>
+__device__ __forceinline__ double sliced_wave_pat(const SweepArgs &a, const SlicedView &s, int wave,
+                                                  const int32_t *ptab)
+{
+    using VT = typename T::VT;
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    wave = __builtin_amdgcn_readfirstlane(wave);
+    if (wave >= s.nslice) return 0.0;
+    const int kf = s.sk[wave];
+    const int p0 = s.sptr[wave];
+    const int G = (kf & 0x7fffffff) >> 2;
+    const int lane = (int)threadIdx.x & 63;
+    const int row = wave * 64 + lane;
+    const bool live = row < a.n;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    const int32_t *pt = ptab + (int)s.pid[row] * s.kp;
+    RT rhs_v = (RT)0;
+    double aux = 0.0, aux2 = 0.0, dsh = 1.0, cf = 1.0;
+    if (live) {
+        if (a.epi != EPI_SPMV) rhs_v = ((const RT *)a.rhs)[row];
+        if (a.epi == EPI_UPDATE) aux = a.x[row];
+        if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
+        if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+        if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
+        if (a.dshift) dsh = a.dshift[row];
+    }
+    AT sum = (AT)0;
+    if (live && a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[row]);
+    if (kf >= 0 && G <= GM && G >= 1) {
+        sum = slice_sum_pat_g<T, GM>(G, s, p0, lane, row, xin, pt, sum);
+    } else {
+        const int len = kf >= 0 ? 4 * G : (live ? a.rp[row + 1] - a.rp[row] : 0);
+        const int safe = min(row, a.n - 1);
+        for (int q = 0; q < G; ++q) {
+            VT v[4];
+            if (sizeof(VT) == 8) {
+                const f64x2 *pv = (const f64x2 *)s.val + (p0 >> 1) + 128 * q + lane;
+                const f64x2 lo2 = __builtin_nontemporal_load(pv), hi2 = __builtin_nontemporal_load(pv + 64);
+                v[0] = (VT)lo2.x;
+                v[1] = (VT)lo2.y;
+                v[2] = (VT)hi2.x;
+                v[3] = (VT)hi2.y;
+            } else {
+                const f32x4 v4 = __builtin_nontemporal_load((const f32x4 *)s.val + (p0 >> 2) + 64 * q + lane);
+                v[0] = (VT)v4.x;
+                v[1] = (VT)v4.y;
+                v[2] = (VT)v4.z;
+                v[3] = (VT)v4.w;
+            }
+            const i32x4 o = *(const i32x4 *)(pt + 4 * q);
+            const int j[4] = {row + o.x, row + o.y, row + o.z, row + o.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool on = 4 * q + r < len;
+                const AT t = sum + (AT)v[r] * (AT)xin[on ? j[r] : safe];
+                sum = on ? t : sum;
+            }
+        }
+    }
+    const AT t = a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum;
+    if (live) epilogue_pre<T>(a, row, t, aux, aux2, cf);
+    return live ? (double)t : 0.0;
+}
+
+// Each workgroup copies the pattern table to LDS once and then runs SPW
+// rounds of WPB consecutive slices.
+template <class T, int WPB, int GM, int SPW>
+__global__ void __launch_bounds__(64 * WPB) k_sweep_sliced_pat(SweepArgs a, SlicedView s)
+{
+    extern __shared__ int32_t lds_pat[];
+    const int npk = s.npat * s.kp;
+    for (int t = (int)threadIdx.x; t < npk; t += 64 * WPB) lds_pat[t] = s.ptab[t];
+    __syncthreads();
+    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    for (int it = 0; it < SPW; ++it)
+        sliced_wave_pat<T, GM>(a, s, (b * SPW + it) * WPB + ((int)threadIdx.x >> 6), lds_pat);
+}
+
 template <class T, int CODE, int WPB, int UNR>
 __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
 {
@@ -656,10 +798,11 @@ hipError_t go_batch_args_sized(const BatchArgs &b, hipStream_t s)
 // with a dependency it waits until done[dep] counts every tile of that op.
 // The wait cannot deadlock: the tiles it waits for have smaller numbers, so
 // workgroups that are already running took them, and the smallest unfinished
-// tile never waits.  Each wait is bounded (p.spin_limit polls, each after a
-// short sleep): on expiry the op's index + 1 goes to ctl[1], the tile is
-// skipped and still counted, so every workgroup drains in bounded time and
-// the host reports the failure.
+// tile never waits.  Each wait is bounded in wall-clock time (p.wait_ticks of
+// the constant-rate clock wall_clock64 reads, however long each poll takes):
+// on expiry the op's index + 1 goes to ctl[1], the tile is skipped and still
+// counted, so every workgroup drains in bounded time and the host reports the
+// failure.
 // Memory order: every XCD has its own L2; the counters are updated and
 // polled at system scope so that their coherence does not rest on any one
 // L2.  A finished tile's stores reach memory through each thread's fence (L2
@@ -688,10 +831,10 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_persist(PersistPlan p)
                 const int d = p.dep[op];
                 if (d >= 0) {
                     const int need = p.first[d + 1] - p.first[d];
-                    int polls = 0;
+                    const long long t0 = wall_clock64();
                     while (__hip_atomic_load(&p.done[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < need) {
                         __builtin_amdgcn_s_sleep(4);
-                        if (++polls >= p.spin_limit) {
+                        if (wall_clock64() - t0 >= p.wait_ticks) {
                             int zero = 0;
                             __hip_atomic_compare_exchange_strong(&p.ctl[1], &zero, op + 1, __ATOMIC_RELAXED,
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -869,6 +1012,25 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         constexpr int WPB = 4, UNR = 2;
         if (g.sl.nslice <= 0) return hipErrorInvalidValue;
         const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
+        if (g.sl.code == 8) {
+            constexpr int SPW = 4;
+            if (g.sl.npat < 1 || g.sl.kp < 4 || (g.sl.kp & 3) || g.sl.npat * g.sl.kp > PAT_MAX_ENTRIES ||
+                g.sl.gmax > 8 || g.sl.kp != 4 * g.sl.gmax)
+                return hipErrorInvalidValue;
+            const dim3 pgrid((g.sl.nslice + WPB * SPW - 1) / (WPB * SPW));
+            const size_t lds = (size_t)g.sl.npat * g.sl.kp * sizeof(int32_t);
+            switch (g.sl.gmax) {
+            case 1: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 1, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 2: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 2, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 3: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 3, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 4: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 4, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 5: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 5, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 6: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 6, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            case 7: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 7, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            default: hipLaunchKernelGGL((k_sweep_sliced_pat<T, WPB, 8, SPW>), pgrid, block, lds, s, a, g.sl); break;
+            }
+            return hipGetLastError();
+        }
         if (g.slice_prefetch && g.sl.code == 1 && g.sl.gmax >= 1 && g.sl.gmax <= 8) {
             switch (g.sl.gmax) {
             case 1: hipLaunchKernelGGL((k_sweep_sliced_pf<T, WPB, 1>), grid, block, 0, s, a, g.sl); break;
@@ -1002,7 +1164,8 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
         g.allow16 = !(flags & 0x1000);
         g.allow_win = !(flags & 0x1000) && !(flags & 0x2000);
         g.prefer_win = false;
-        g.slice_code_min = (flags & 0x1000) ? 4 : ((flags & 0x8000) ? 2 : 1); // SILU_INDEX32, SILU_CODE16
+        // SILU_INDEX32, SILU_CODE16, SILU_CODE8; by default the row-pattern table where it fits
+        g.slice_code_min = (flags & 0x1000) ? 4 : ((flags & 0x8000) ? 2 : ((flags & 0x100000) ? 1 : 0));
         g.slice_prefetch = !(flags & 0x80000);                                // SILU_SLICED_LOOP
         return g;
     }

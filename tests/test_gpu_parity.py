@@ -27,7 +27,7 @@ def ctx(B):
     return B.Context()
 
 
-KERNELS = [None, "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
+KERNELS = [None, "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
 
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),

@@ -125,3 +125,33 @@ def test_values_changed_in_place(orc, B, ctx):
     x = dev(np.zeros(A.n))
     ctx.ilu_smooth(Ad, F, dev(b), x, 1, 3, 3, reorder=True)
     np.testing.assert_array_equal(host(x), orc.smooth(A2, Ls, Us, dinv, b, np.zeros(A.n), 1, 3, 3))
+
+
+@pytest.mark.parametrize("name", ["perm9", "perm17", "aniso11_ilut"])
+def test_relabeled_vectors_equal_plain(orc, B, ctx, cases, name):
+    """b and x moved into the copies' order once (silu_reorder_vectors), several
+    smoother calls with SILU_REORDER | SILU_RELABELED (no permutations inside),
+    x moved back once: the same bits as the same calls in the given order, FP64
+    and FP32-inner, from a zero guess too; and moving a vector in and out gives
+    it back."""
+    say("relabeled vectors", name)
+    c = cases[name]
+    n = c.A.n
+    b, x0 = dev(W.rhs(n, 3)), dev(W.rhs(n, 4))
+    np.testing.assert_array_equal(host(ctx.reorder_vectors(c.Ad, c.F, ctx.reorder_vectors(c.Ad, c.F, x0),
+                                                           to_relabeled=False)), host(x0))
+    for mixed in (False, True):
+        for zero in (False, True):
+            start = torch.zeros_like(x0) if zero else x0.clone()
+            x = start.clone()
+            for _ in range(3):
+                ctx.ilu_smooth(c.Ad, c.F, b, x, 1, 3, 3, mixed=mixed, zero_guess=zero and _ == 0)
+            b2 = ctx.reorder_vectors(c.Ad, c.F, b)
+            x2 = ctx.reorder_vectors(c.Ad, c.F, start)
+            ws = ctx.workspace(n, B.SILU_REORDER | B.SILU_RELABELED)
+            for _ in range(3):
+                ctx.ilu_smooth(c.Ad, c.F, b2, x2, 1, 3, 3, mixed=mixed, zero_guess=zero and _ == 0, reorder=True,
+                               relabeled=True, ws=ws)
+            np.testing.assert_array_equal(host(ctx.reorder_vectors(c.Ad, c.F, x2, to_relabeled=False)), host(x))
+    with pytest.raises(B.SiluError):  # relabeled vectors without the relabeled copies
+        ctx.ilu_smooth(c.Ad, c.F, b, x0.clone(), 1, 3, 3, relabeled=True)
