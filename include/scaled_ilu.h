@@ -289,6 +289,29 @@ int ilu_smooth2(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const d
 int silu_reorder_vectors(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *src, double *dst,
                          int to_relabeled);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * iterative ilu_smooth2 with its four work vectors in a scratch array the
+ * library holds on each device (64 MiB, made with the code object and kept
+ * until the process ends), so no workspace argument and no allocation: no
+ * hipMalloc, no layout built.  Sweeps read the sliced or 16-bit layouts an
+ * earlier ilu_smooth call with the same matrices and flags cached in the
+ * context, else the caller's CSR arrays directly (same results bit for bit);
+ * per-kernel timing is not recorded.  n at most 2,097,152 rows (four FP64
+ * n-vectors, 256-byte rounded, in 64 MiB), else SILU_ERR_NOMEM.  flags: only
+ * SILU_MIXED, SILU_ZERO_GUESS, SILU_CHECK_FINITE and the kernel-choice flags
+ * (SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_INDEX32, SILU_NO_WINDOW,
+ * SILU_CODE16, SILU_CODE8, SILU_SLICED_LOOP), else SILU_ERR_ARG.  Every call
+ * on one device shares that device's scratch array, which keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other
+ * contexts, other threads) race and must be ordered by the caller.
+ * Asynchronous.  Errors: as ilu_smooth2, and HIP if the scratch array's
+ * address could not be found when the context was created.
+ */
+int ilu_smooth_noalloc(silu_ctx *ctx, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                       int outer_sweeps, int m_L, int m_U, int flags);
+
 /* The relabeling of SILU_REORDER, on HOST arrays: reverse Cuthill-McKee on
  * the graph of strong couplings, row i coupled to j != i when |a_ij| >= theta
  * * max_{k != i} |a_ik| (the strength of connection of algebraic multigrid,

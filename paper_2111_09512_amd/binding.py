@@ -122,6 +122,7 @@ _sig = {
     "silu_stream_copy": (C.c_int, [_P, _P, _P, C.c_size_t]),
     "silu_stream_read": (C.c_int, [_P, _P, C.c_size_t, _P]),
     "silu_reorder_vectors": (C.c_int, [_P, _P, _P, _P, _P, C.c_int]),
+    "ilu_smooth_noalloc": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int, C.c_int, C.c_int]),
     "silu_factor_iluk": (C.c_int, [C.POINTER(silu_host_csr), C.c_int, C.POINTER(silu_host_csr),
                                    C.POINTER(silu_host_csr), C.POINTER(C.c_int64)]),
     "silu_factor_ilut": (C.c_int, [C.POINTER(silu_host_csr), C.c_double, C.c_int, C.POINTER(silu_host_csr),
@@ -499,6 +500,23 @@ class Context:
         self._check(_lib.ilu_smooth2(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags,
                                      C.c_void_p(ws.data_ptr()), ws.numel()), "ilu_smooth")
+        return x
+
+    def ilu_smooth_noalloc(self, A: Csr, F: Factors, b: torch.Tensor, x: torch.Tensor, outer_sweeps: int, m_L: int,
+                           m_U: int | None = None, mixed: bool = False, zero_guess: bool = False,
+                           check_finite: bool = False, kernel: str | None = None) -> torch.Tensor:
+        """ilu_smooth with its work vectors in the library's per-device scratch array
+        (no workspace, no allocation), in place on x."""
+        m_U = m_L if m_U is None else m_U
+        flags = ((SILU_MIXED if mixed else 0) | (SILU_ZERO_GUESS if zero_guess else 0) |
+                 (SILU_CHECK_FINITE if check_finite else 0) | KERNELS[kernel])
+        _vec(b, A.n, "b")
+        _vec(x, A.n, "x")
+        self._track(A, F.Ls, F.Us, values=((), (F.Ls_val32,), (F.Us_val32,)))
+        Ac, Fc = A.c(), F.c()
+        self._check(_lib.ilu_smooth_noalloc(self._h, C.byref(Ac), C.byref(Fc), C.c_void_p(b.data_ptr()),
+                                            C.c_void_p(x.data_ptr()), outer_sweeps, m_L, m_U, flags),
+                    "ilu_smooth_noalloc")
         return x
 
     def reorder_vectors(self, A: Csr, F: Factors, src: torch.Tensor, to_relabeled: bool = True,

@@ -13,6 +13,7 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <new>
 #include <string>
@@ -142,6 +143,8 @@ struct SmoothGraph {
 
 struct silu_ctx {
     int device = 0;
+    void *scratch = nullptr; // this device's copy of the no-allocation scratch array (device address)
+    bool no_build = false;   // inside ilu_smooth_noalloc: build no layout, record no timing
     hipStream_t stream = nullptr;
     int64_t bad_row = -1;
     hipError_t last_hip = hipSuccess;
@@ -207,7 +210,7 @@ template <class F>
 int timed_launch(silu_ctx *c, double bytes, double layout, F &&fn)
 {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timing = c->timing;
+    const bool timing = c->timing && !c->no_build;
     if (timing) {
         HIPCHK(c, get_event(c, &e0));
         HIPCHK(c, get_event(c, &e1));
@@ -324,6 +327,7 @@ int get_partition(silu_ctx *c, const silu_csr *M, int cap, int rmax, Partition *
         *out = &it->second;
         return SILU_OK;
     }
+    if (c->no_build) return SILU_ERR_UNSUPPORTED; // the partition is made on the host and allocated
     const int64_t n = M->n_rows;
     std::vector<int32_t> rp((size_t)n + 1);
     HIPCHK(c, hipMemcpyAsync(rp.data(), M->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, c->stream));
@@ -367,6 +371,11 @@ int get_compressed(silu_ctx *c, const silu_csr *M, int rpb, int win_policy, Comp
 {
     CompKey key{M->row_ptr, M->col_idx, M->n_rows, M->nnz, rpb};
     auto it = c->comp.find(key);
+    if (c->no_build) { // what is cached, as it is; else plain 32-bit columns
+        static Compressed none;
+        *out = it != c->comp.end() ? &it->second : &none;
+        return SILU_OK;
+    }
     Compressed *C = nullptr;
     int32_t range[2] = {INT32_MAX, INT32_MIN};
     if (it != c->comp.end()) {
@@ -658,6 +667,11 @@ int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int 
     auto it = c->sliced.find(key);
     if (it != c->sliced.end()) {
         *out = &it->second;
+        return SILU_OK;
+    }
+    if (c->no_build) { // not cached: the caller streams the CSR arrays instead
+        static Sliced none;
+        *out = &none;
         return SILU_OK;
     }
     Sliced S;
@@ -1044,6 +1058,35 @@ void free_owned_sliced(void *owner)
 
 } // namespace silu
 
+// Scratch memory of ilu_smooth_noalloc: one array per device, made with the
+// code object (nothing is allocated for it at run time) and held until the
+// process ends.  Its device address differs per device and is looked up once
+// per device, with that device current, when the first context on it is
+// created; host code uses only that address, never the array's own name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[MAX_DEVICES] = {};
+
+// The scratch array's address on the current device (resolved once), or null.
+void *scratch_address(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch[device] = p;
+        else (void)hipGetLastError(); // the no-allocation entry point then reports HIP
+    }
+    return g_scratch[device];
+}
+
+} // namespace
+
 extern "C" {
 
 int silu_create(silu_ctx **ctx, void *hip_stream)
@@ -1059,6 +1102,7 @@ int silu_create(silu_ctx **ctx, void *hip_stream)
         delete c;
         return SILU_ERR_HIP;
     }
+    c->scratch = scratch_address(c->device);
     *ctx = c;
     return SILU_OK;
 }
@@ -1429,6 +1473,24 @@ int ilu_smooth(silu_ctx *c, const silu_csr *A, const silu_factors *F, const doub
                int inner_iters, int flags, void *ws, size_t ws_bytes)
 {
     return ilu_smooth2(c, A, F, b, x, outer_sweeps, inner_iters, inner_iters, flags, ws, ws_bytes);
+}
+
+int ilu_smooth_noalloc(silu_ctx *c, const silu_csr *A, const silu_factors *F, const double *b, double *x,
+                       int outer_sweeps, int m_L, int m_U, int flags)
+{
+    constexpr int allowed = SILU_MIXED | SILU_ZERO_GUESS | SILU_CHECK_FINITE | SILU_KERNEL_STREAM |
+                            SILU_KERNEL_VECTOR | SILU_INDEX32 | SILU_NO_WINDOW | SILU_CODE16 | SILU_CODE8 |
+                            SILU_SLICED_LOOP;
+    if (!c || !A || (flags & ~allowed)) return SILU_ERR_ARG;
+    if (A->n_rows < 0 || A->n_rows >= INT32_MAX) return SILU_ERR_ARG;
+    size_t need = 0;
+    silu_workspace_size(c, A->n_rows, flags, &need);
+    if (need > NOALLOC_SCRATCH_BYTES) return SILU_ERR_NOMEM;
+    if (!c->scratch) return SILU_ERR_HIP;
+    c->no_build = true;
+    const int st = smooth_plain(c, A, F, b, x, outer_sweeps, m_L, m_U, flags, c->scratch, NOALLOC_SCRATCH_BYTES);
+    c->no_build = false;
+    return st;
 }
 
 // ---- polynomial Gauss-Seidel smoother --------------------------------------
