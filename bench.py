@@ -197,6 +197,52 @@ def bench_serving(torch, B, ctx, arena_mb):
     with gc_paused():
         lat_m, span_m, steps_m = S.run_batched(server, mids, reqs, mixed=True)
     mixed_err = max(float(torch.linalg.norm(reqs[i].x - xb[i]) / torch.linalg.norm(xb[i])) for i in range(len(reqs)))
+    # saturation: all 1,280 requests submitted at t = 0 (no arrival process): batched through the
+    # server against the same smoother calls issued back to back with ilu_smooth (no host sync
+    # between them); the algorithmic bytes of the whole stream come from the library's per-kernel
+    # accounting of the back-to-back run, the same sweeps the server launches
+    for r in reqs:
+        r.x.zero_()
+    with gc_paused():
+        lat_s, span_s, steps_s = S.run_batched(server, mids, reqs, realtime=False)
+    same_s = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
+    wsb = ctx.workspace(max(m[2] for m in mats))
+
+    def back_to_back():
+        for r in reqs:
+            Ad_, F_, _ = mats[r.mid]
+            ctx.ilu_smooth(Ad_, F_, r.b, r.x, r.outer, r.m_L, r.m_U, ws=wsb)
+
+    for r in reqs:
+        r.x.zero_()
+    ctx.stats_reset()
+    ctx.set_timing(True)
+    back_to_back()
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    stream_bytes = sum(v["bytes"] for v in ctx.stats().values())
+    for r in reqs:
+        r.x.zero_()
+    with gc_paused():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        back_to_back()
+        torch.cuda.synchronize()
+        span_b2b = time.perf_counter() - t0
+    same_b2b = all(bool(torch.equal(xb[i], reqs[i].x)) for i in range(len(reqs)))
+    saturation = {
+        "requests": len(reqs), "bytes_algorithmic": stream_bytes,
+        "batched": {"apps_per_s": len(reqs) / span_s, "makespan_s": span_s, "steps": steps_s,
+                    "GBps": stream_bytes / span_s / 1e9, "frac_of_peak": stream_bytes / span_s / 1e9 / HBM_PEAK_GBPS,
+                    **S.percentiles(lat_s)},
+        "back_to_back_ilu_smooth": {"apps_per_s": len(reqs) / span_b2b, "makespan_s": span_b2b,
+                                    "GBps": stream_bytes / span_b2b / 1e9,
+                                    "frac_of_peak": stream_bytes / span_b2b / 1e9 / HBM_PEAK_GBPS},
+        "results_identical": bool(same_s and same_b2b)}
+    log(f"serving at saturation: batched {saturation['batched']['apps_per_s']:.0f} apps/s "
+        f"({saturation['batched']['GBps']:.0f} GB/s algorithmic, {steps_s} steps), back to back "
+        f"{saturation['back_to_back_ilu_smooth']['apps_per_s']:.0f} apps/s "
+        f"({saturation['back_to_back_ilu_smooth']['GBps']:.0f} GB/s); identical {saturation['results_identical']}")
     server.close()
     # two lanes: matrices up to 64^3 rows batched on the context's stream, larger
     # ones on a second stream of their own, each lane half of the arena
@@ -228,7 +274,7 @@ def bench_serving(torch, B, ctx, arena_mb):
            "batched_two_lanes": {"apps_per_s": len(reqs) / span_l, "makespan_s": span_l, "steps": steps_l,
                                  "small_lane_max_rows": 64 ** 3, **S.percentiles(lat_l)},
            "one_at_a_time": {"apps_per_s": len(reqs) / span_1, "makespan_s": span_1, **S.percentiles(lat_1)},
-           "results_identical": bool(same and same_l)}
+           "results_identical": bool(same and same_l), "saturation": saturation}
     log(f"serving: batched p50 {res['batched']['p50_ms']:.2f} ms p99 {res['batched']['p99_ms']:.2f} ms "
         f"{res['batched']['apps_per_s']:.0f} apps/s; two lanes p50 {res['batched_two_lanes']['p50_ms']:.2f} ms "
         f"p99 {res['batched_two_lanes']['p99_ms']:.2f} ms; one-at-a-time p50 {res['one_at_a_time']['p50_ms']:.2f} ms "
@@ -677,7 +723,8 @@ def main():
         del orc_in
 
     rec = measured_traffic(args.workload)
-    traffic = rec["traffic_bytes_per_launch"] if rec and rec.get("kernel") == dname else None
+    tk = (rec or {}).get("kernels", {})
+    traffic = tk[dname]["traffic_bytes_per_launch"] if dname in tk else None
 
     # ---- serving stream (continuous batching on 64 resident matrices) ----
     serving = None
@@ -732,7 +779,14 @@ def main():
                         "GBps": v["bytes"] / v["ms"] / 1e6, "layout_GBps": v["layout_bytes"] / v["ms"] / 1e6}
                     for k, v in st.items()},
         "kernels_mixed": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
-                              "GBps": v["bytes"] / v["ms"] / 1e6, "layout_GBps": v["layout_bytes"] / v["ms"] / 1e6}
+                              "GBps": v["bytes"] / v["ms"] / 1e6, "layout_GBps": v["layout_bytes"] / v["ms"] / 1e6,
+                              # HBM bytes the counters measured per launch (null without a record for
+                              # the current kernel sources), and the bandwidth and fraction of peak they give
+                              "traffic": tk[k]["traffic_bytes_per_launch"] if k in tk else None,
+                              "traffic_GBps": (tk[k]["traffic_bytes_per_launch"] * v["launches"] / v["ms"] / 1e6)
+                              if k in tk else None,
+                              "traffic_frac": (tk[k]["traffic_bytes_per_launch"] * v["launches"] / v["ms"] / 1e6
+                                               / HBM_PEAK_GBPS) if k in tk else None}
                           for k, v in st_mixed.items()},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,

@@ -689,6 +689,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
           const double *dcol = nullptr)
 {
     double sliced_bytes = -1.0;
+    bool fell_back = false; // the default sliced layout did not apply
     if (g.kind == SweepKernel::SLICED) {
         const int vbytes = (p == Prec::F64 || p == Prec::MIX_RES) ? 8 : 4;
         Sliced *S = nullptr;
@@ -704,6 +705,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
                            (S->v.code == 8 ? (double)N->n_rows + 4.0 * S->v.npat * S->v.kp : 0.0);
         } else {
             g.kind = SweepKernel::STREAM; // no entries, too large for the sliced copy, or no structure
+            fell_back = true;
         }
     }
     if (g.kind == SweepKernel::STREAM && g.allow16 && N->nnz > 0) {
@@ -718,6 +720,13 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
         } else if (C->ok) {
             g.off16 = C->d;
             g.shift = C->shift;
+        } else if (fell_back && !c->no_build) {
+            // no structure and no narrow column code: 32-bit columns either way; the row-block
+            // partition (1,024 entries per workgroup, every load issued at once) streams
+            // such matrices faster than CSR-stream (the relabeled random operator: 1.35 ms
+            // against 1.41 ms per FP32-inner application)
+            g.kind = SweepKernel::BLOCKED;
+            g.cap = 1024;
         }
     }
     if (g.kind == SweepKernel::BLOCKED) {
