@@ -780,13 +780,15 @@ def main():
                     for k, v in st.items()},
         "kernels_mixed": {k: {"launches": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
                               "GBps": v["bytes"] / v["ms"] / 1e6, "layout_GBps": v["layout_bytes"] / v["ms"] / 1e6,
-                              # HBM bytes the counters measured per launch (null without a record for
-                              # the current kernel sources), and the bandwidth and fraction of peak they give
-                              "traffic": tk[k]["traffic_bytes_per_launch"] if k in tk else None,
+                              # HBM bytes the counters measured per launch of the FP32-inner kernels (null
+                              # without a record for the current kernel sources; the FP64 residual of this
+                              # form is a different launch mix from the FP64 record's), and the bandwidth
+                              # and fraction of peak they give
+                              "traffic": tk[k]["traffic_bytes_per_launch"] if k in tk and "_mix" in k else None,
                               "traffic_GBps": (tk[k]["traffic_bytes_per_launch"] * v["launches"] / v["ms"] / 1e6)
-                              if k in tk else None,
+                              if k in tk and "_mix" in k else None,
                               "traffic_frac": (tk[k]["traffic_bytes_per_launch"] * v["launches"] / v["ms"] / 1e6
-                                               / HBM_PEAK_GBPS) if k in tk else None}
+                                               / HBM_PEAK_GBPS) if k in tk and "_mix" in k else None}
                           for k, v in st_mixed.items()},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,

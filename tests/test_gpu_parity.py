@@ -541,3 +541,41 @@ def test_calibration_streams(B, ctx):
     np.testing.assert_array_equal(host(out).view(np.uint64), want.reshape(-1))
     with pytest.raises(B.SiluError):
         ctx.stream_read(src[:1000], out)
+
+
+def _patterned_lower(n, npat, rowlen, seed):
+    """Strictly lower matrix whose rows follow `npat` offset patterns (each
+    `rowlen` distinct offsets in [1, 4 rowlen]), assigned to rows at random; a
+    row whose offsets would leave the matrix keeps only the ones that fit (a
+    boundary pattern of its own)."""
+    rng = np.random.default_rng(seed)
+    pats = [np.sort(rng.choice(np.arange(1, 4 * rowlen + 1), size=rowlen, replace=False))[::-1] for _ in range(npat)]
+    which = rng.integers(0, npat, size=n)
+    rows, cols = [], []
+    for i in range(n):
+        c = i - pats[which[i]]
+        c = c[c >= 0]
+        rows.append(np.full(c.size, i))
+        cols.append(c)
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    D = np.zeros((n, n))
+    D[rows, cols] = -rng.random(rows.size) / (2.0 * rowlen)
+    return W.CSR.from_dense(D)
+
+
+@pytest.mark.parametrize("npat,rowlen", [(1, 5), (120, 8), (240, 12), (300, 6), (60, 32), (40, 33)])
+def test_row_pattern_tables(orc, B, ctx, npat, rowlen):
+    """Row-pattern sliced copies at their limits: one pattern, up to 256 (counting
+    the boundary rows' own), more than 256 (the 1-byte diagonal codes instead),
+    32 slots per row (eight groups, the most the pattern sweep takes) and 33 (the
+    coded layout instead); every layout choice gives the oracle's Richardson
+    iterates bit for bit."""
+    say("row patterns", npat, rowlen)
+    n = 1500
+    T = _patterned_lower(n, npat, rowlen, seed=npat * 100 + rowlen)
+    Td = B.Csr.from_host(T)
+    rhs = W.rhs(n, 9)
+    for m in (1, 3, 6):
+        for kernel in (None, "sliced8"):
+            np.testing.assert_array_equal(host(ctx.trisolve_iter(Td, dev(rhs), m, kernel=kernel)),
+                                          orc.richardson(T, rhs, m))
