@@ -799,7 +799,12 @@ def main():
                      "layout_frac_of_read_ceiling": ach_layout / read_gbps,
                      "traffic_achieved": (traffic / avg_s / 1e9) if traffic else None,
                      "traffic_frac": (traffic / avg_s / 1e9 / HBM_PEAK_GBPS) if traffic else None,
-                     "traffic_frac_of_read_ceiling": (traffic / avg_s / 1e9 / read_gbps) if traffic else None},
+                     "traffic_frac_of_read_ceiling": (traffic / avg_s / 1e9 / read_gbps) if traffic else None,
+                     # the >= 70 % of peak HBM bandwidth target, on algorithmic and on counter bytes
+                     "target_frac": 0.70,
+                     "meets_target_algorithmic": bool(ach / HBM_PEAK_GBPS >= 0.70),
+                     "meets_target_counters": (bool(traffic / avg_s / 1e9 / HBM_PEAK_GBPS >= 0.70)
+                                               if traffic else None)},
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -58,6 +58,8 @@ struct SlicedView {
 };
 // Row-pattern tables are kept to at most this many offsets (16 KB of LDS).
 constexpr int PAT_MAX_ENTRIES = 4096;
+// Row-pattern sweeps run four rounds of slices per workgroup from this many slices up.
+constexpr int PAT_ROUNDS_MIN_SLICES = 65536;
 
 // Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
 // and RB_CAP entries per workgroup (a longer row gets a workgroup alone).
