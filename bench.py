@@ -306,24 +306,38 @@ def bench_solve_requests(torch, B, ctx):
     bs = [torch.from_numpy(W.rhs(mats[k % 2][2], 500 + k)).cuda() for k in range(64)]
     xs = [torch.zeros_like(b) for b in bs]
     torch.cuda.synchronize()
-    with gc_paused():
-        t0 = time.perf_counter()
-        tickets = [server.submit_solve(mids[k % 2], bs[k], xs[k], 1e-6, 400, 3, 3) for k in range(64)]
-        done_at = {}
-        while len(done_at) < len(tickets):
-            server.step()
-            now = time.perf_counter() - t0
-            for t in server.completed():
-                done_at[t] = now
-    lat = np.array([done_at[t] for t in tickets])
+    def stream(steps_per_call):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        with gc_paused():
+            t0 = time.perf_counter()
+            tickets = [server.submit_solve(mids[k % 2], bs[k], xs[k], 1e-6, 400, 3, 3) for k in range(64)]
+            done_at = {}
+            while len(done_at) < len(tickets):
+                if steps_per_call > 1:
+                    server.run(steps_per_call)
+                else:
+                    server.step()
+                now = time.perf_counter() - t0
+                for t in server.completed():
+                    done_at[t] = now
+        return tickets, np.array([done_at[t] for t in tickets])
+
+    tickets, lat = stream(1)
     steps = np.array([server.solve_result(t)[0] for t in tickets])
     rel = np.array([server.solve_result(t)[1] for t in tickets])
+    # the same with 16 scheduling steps per call into the library (the host loop in C++)
+    tickets16, lat16 = stream(16)
+    same16 = [server.solve_result(t)[0] for t in tickets16] == list(steps)
     server.close()
     out = {"requests": 64, "tol": 1e-6, "max_outer": 400, "m": 3, "sides": [16, 24],
            "outer_steps_min": int(steps.min()), "outer_steps_max": int(steps.max()),
-           "all_converged": bool((steps <= 400).all() and (rel < 1e-6).all()), **S.percentiles(lat)}
+           "all_converged": bool((steps <= 400).all() and (rel < 1e-6).all()), **S.percentiles(lat),
+           "steps_per_call_16": {**S.percentiles(lat16), "same_step_counts": bool(same16)}}
     log(f"serving solve requests: 64 at once, outer steps {steps.min()}-{steps.max()}, all converged "
-        f"{out['all_converged']}, completion p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms")
+        f"{out['all_converged']}, completion p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms; 16 steps per "
+        f"call p50 {out['steps_per_call_16']['p50_ms']:.2f} ms p99 {out['steps_per_call_16']['p99_ms']:.2f} ms")
     return out
 
 
