@@ -171,11 +171,14 @@ struct silu_server {
     // and not yet seen complete, in order
     std::deque<std::pair<int64_t, int>> marks;
     int64_t nmarks = 0, last_mark_step = -1;
-    SweepArgs *h_ops[RING] = {};
-    int32_t *h_first[RING] = {};
-    SweepArgs *d_ops = nullptr;
-    int32_t *d_first = nullptr;
+    // op tables too long for the kernel arguments: each staged group's ops and
+    // first-block offsets packed into one pinned buffer per ring slot, copied
+    // to d_stage with one copy per step
+    char *h_stage[RING] = {};
+    char *d_stage = nullptr;
     int cap = 0; // op-table capacity
+    std::vector<SweepArgs> step_ops; // this step's ops and their precisions
+    std::vector<Prec> step_prec;
     hipError_t last = hipSuccess;
     // persistent mode
     int mode = 0;
@@ -380,31 +383,29 @@ SweepArgs op_of(const silu_server *s, const Request &q, Prec *prec = nullptr)
     return a;
 }
 
+// Bytes of one staging buffer for cap ops over at most 5 groups: each group's
+// ops, then its cap + 1 first-block offsets, the group rounded up to 16 bytes.
+size_t stage_bytes(int cap) { return (size_t)cap * (sizeof(SweepArgs) + sizeof(int32_t)) + 5 * 32; }
+
+size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
 int grow(silu_server *s, int need)
 {
     if (need <= s->cap) return SILU_OK;
-    // idle the ring before reallocating the staging and device tables
+    // idle the ring before reallocating the staging buffers and the device table
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return fail(s, e);
     int cap = std::max(need, std::max(64, 2 * s->cap));
     for (int i = 0; i < RING; i++) {
-        (void)hipHostFree(s->h_ops[i]);
-        (void)hipHostFree(s->h_first[i]);
-        s->h_ops[i] = nullptr;
-        s->h_first[i] = nullptr;
+        (void)hipHostFree(s->h_stage[i]);
+        s->h_stage[i] = nullptr;
     }
-    (void)hipFree(s->d_ops);
-    (void)hipFree(s->d_first);
-    s->d_ops = nullptr;
-    s->d_first = nullptr;
+    (void)hipFree(s->d_stage);
+    s->d_stage = nullptr;
     s->cap = 0;
-    for (int i = 0; i < RING; i++) {
-        if ((e = hipHostMalloc((void **)&s->h_ops[i], sizeof(SweepArgs) * (size_t)cap)) != hipSuccess) return fail(s, e);
-        if ((e = hipHostMalloc((void **)&s->h_first[i], sizeof(int32_t) * (size_t)(cap + 1))) != hipSuccess)
-            return fail(s, e);
-    }
-    if ((e = hipMalloc(&s->d_ops, sizeof(SweepArgs) * (size_t)cap)) != hipSuccess) return fail(s, e);
-    if ((e = hipMalloc(&s->d_first, sizeof(int32_t) * (size_t)(cap + 1))) != hipSuccess) return fail(s, e);
+    for (int i = 0; i < RING; i++)
+        if ((e = hipHostMalloc((void **)&s->h_stage[i], stage_bytes(cap))) != hipSuccess) return fail(s, e);
+    if ((e = hipMalloc(&s->d_stage, stage_bytes(cap))) != hipSuccess) return fail(s, e);
     s->cap = cap;
     return SILU_OK;
 }
@@ -632,11 +633,9 @@ int silu_server_destroy(silu_server *s)
     destroy_persistent(s);
     for (int i = 0; i < RING; i++) {
         if (s->ev[i]) (void)hipEventDestroy(s->ev[i]);
-        (void)hipHostFree(s->h_ops[i]);
-        (void)hipHostFree(s->h_first[i]);
+        (void)hipHostFree(s->h_stage[i]);
     }
-    (void)hipFree(s->d_ops);
-    (void)hipFree(s->d_first);
+    (void)hipFree(s->d_stage);
     for (Matrix &M : s->mats) free_matrix_copies(M);
     for (SolveCtl *blk : s->result_blocks) (void)hipHostFree(blk);
     (void)hipHostFree(s->hflags);
@@ -846,8 +845,10 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         const int nops = (int)s->active.size();
         // the step's ops, one launch per precision present (the ops of different
         // requests are independent, so their launch order does not matter)
-        std::vector<SweepArgs> ops((size_t)nops);
-        std::vector<Prec> prec((size_t)nops);
+        std::vector<SweepArgs> &ops = s->step_ops;
+        std::vector<Prec> &prec = s->step_prec;
+        ops.resize((size_t)nops);
+        prec.resize((size_t)nops);
         for (int i = 0; i < nops; i++) ops[(size_t)i] = op_of(s, s->active[(size_t)i], &prec[(size_t)i]);
         static const Prec kinds[5] = {Prec::F64, Prec::MIX_RES, Prec::MIX_L1, Prec::MIX_L, Prec::MIX_U};
         int count[5] = {0, 0, 0, 0, 0};
@@ -863,7 +864,13 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         bool finishing = false;
         for (const Request &q : s->active) finishing |= q.op + 1 == q.total;
         hipError_t e = hipSuccess;
-        int off_ops = 0, off_first = 0; // packing of the staged groups
+        struct Staged {
+            Prec kind;
+            size_t ops_off, first_off;
+            int k, total;
+        } sg[5];
+        int nsg = 0;
+        size_t used = 0; // bytes of this step's staging buffer filled
         for (int g = 0; g < 5 && e == hipSuccess; g++) {
             if (!count[g]) continue;
             if (count[g] <= BATCH_ARG_OPS) { // the op table travels in the kernel arguments
@@ -878,9 +885,10 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
                 ba.first[k] = total;
                 ba.nops = k;
                 e = launch_sweep_batch_args(kinds[g], ba, s->stream);
-            } else { // through this step's staging buffers, copied to the device tables
-                SweepArgs *h_ops = s->h_ops[slot] + off_ops;
-                int32_t *h_first = s->h_first[slot] + off_first;
+            } else { // packed into this step's staging buffer, launched after its one copy
+                const size_t first_off = used + sizeof(SweepArgs) * (size_t)count[g];
+                SweepArgs *h_ops = (SweepArgs *)(s->h_stage[slot] + used);
+                int32_t *h_first = (int32_t *)(s->h_stage[slot] + first_off);
                 int k = 0, total = 0;
                 for (int i = 0; i < nops; i++) {
                     if (prec[(size_t)i] != kinds[g]) continue;
@@ -889,17 +897,15 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
                     total += (ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
                 }
                 h_first[k] = total;
-                e = hipMemcpyAsync(s->d_ops + off_ops, h_ops, sizeof(SweepArgs) * (size_t)k, hipMemcpyHostToDevice,
-                                   s->stream);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(s->d_first + off_first, h_first, sizeof(int32_t) * (size_t)(k + 1),
-                                       hipMemcpyHostToDevice, s->stream);
-                if (e == hipSuccess)
-                    e = launch_sweep_batch(kinds[g], s->d_ops + off_ops, s->d_first + off_first, k, total, s->stream);
-                off_ops += k;
-                off_first += k + 1;
+                sg[nsg++] = {kinds[g], used, first_off, k, total};
+                used = align16(first_off + sizeof(int32_t) * (size_t)(k + 1));
             }
         }
+        if (e == hipSuccess && nsg)
+            e = hipMemcpyAsync(s->d_stage, s->h_stage[slot], used, hipMemcpyHostToDevice, s->stream);
+        for (int i = 0; i < nsg && e == hipSuccess; i++)
+            e = launch_sweep_batch(sg[i].kind, (const SweepArgs *)(s->d_stage + sg[i].ops_off),
+                                   (const int32_t *)(s->d_stage + sg[i].first_off), sg[i].k, sg[i].total, s->stream);
         if (e != hipSuccess) return fail(s, e);
         // close the convergence checks of solve requests made in this launch
         SolveCheckArgs ca;
