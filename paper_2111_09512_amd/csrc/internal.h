@@ -56,10 +56,9 @@ struct SlicedView {
     const int32_t *ptab = nullptr; // [npat * kp]
     int npat = 0, kp = 0;
 };
-// Row-pattern tables are kept to at most this many offsets (16 KB of LDS).
+// Row-pattern tables are kept to at most this many offsets (16 KB, small
+// enough to stay in the caches while a sweep reads it).
 constexpr int PAT_MAX_ENTRIES = 4096;
-// Row-pattern sweeps run four rounds of slices per workgroup from this many slices up.
-constexpr int PAT_ROUNDS_MIN_SLICES = 65536;
 
 // Row-block partition of the blocked CSR-stream kernel: at most RB_RMAX rows
 // and RB_CAP entries per workgroup (a longer row gets a workgroup alone).
