@@ -297,6 +297,7 @@ double epi_bytes(Prec p, int64_t n, int epi, bool dshift)
     switch (epi) {
     case EPI_STORE:
     case EPI_SPMV: b = n * ob; break;
+    case EPI_STORE_SPLIT: b = n * (ob + 4.0); break;
     case EPI_SCALE: b = n * (8.0 + ob); break;
     case EPI_UPDATE: b = n * 16.0; break;
     default: b = n * 24.0; break;
@@ -686,7 +687,7 @@ int get_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int 
 
 int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, const void *xin,
           const void *rhs, int epi, void *out, const double *dinv, double *x, const double *dshift,
-          const double *dcol = nullptr)
+          const double *dcol = nullptr, float *out32 = nullptr)
 {
     double sliced_bytes = -1.0;
     bool fell_back = false; // the default sliced layout did not apply
@@ -748,6 +749,7 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
     a.dinv = dinv;
     a.x = x;
     a.dshift = dshift;
+    if (epi == EPI_STORE_SPLIT) a.out32 = out32; // shares its place with x, which this epilogue does not use
     const bool upd = epi == EPI_UPDATE || epi == EPI_SCALE_UPDATE;
     a.dcol = upd ? dcol : nullptr;
     double bytes = sweep_bytes(p, N->n_rows, N->nnz, epi, dshift != nullptr, 4.0);
@@ -1364,10 +1366,16 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         }
         // residual r = b - A x (fused with D^{-1} when m_L = 1); with a zero
         // guess the first one is b itself (b - A 0 = b exactly)
-        const void *rr = r;
+        // the FP32-inner form also stores y_1 = (float) r beside r, for its first L sweep to
+        // gather (in tmp[1], which that sweep does not write)
+        const void *rr = r, *y1 = nullptr;
         if (m_L >= 2 && it == 0 && (flags & SILU_ZERO_GUESS)) {
             rr = b;
             st = SILU_OK;
+        } else if (m_L >= 2 && mixed) {
+            y1 = tmp[1];
+            st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE_SPLIT, r, nullptr, nullptr, nullptr, nullptr,
+                       (float *)tmp[1]);
         } else if (m_L >= 2) {
             st = sweep(c, Prec::F64, gA, A, A->val, x, b, EPI_STORE, r, nullptr, nullptr, nullptr);
         } else if (scaled) {
@@ -1386,13 +1394,15 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
             continue;
         }
         // L sweeps: y_1 = r, y_k = r - Ls y_{k-1}
-        const void *cur = rr;
+        const void *cur = y1 ? y1 : rr;
         for (int k = 2; k <= m_L; k++) {
             const bool last = k == m_L;
             void *out = last ? s : tmp[k & 1];
             int epi = last ? (m_U >= 2 ? to_s : to_x) : EPI_STORE;
-            // in the mixed form y_1 = (float) r is never stored: the first sweep gathers r and rounds it
-            const Prec p = (mixed && k == 2) ? Prec::MIX_L1 : pL;
+            // in the mixed form the first sweep gathers y_1 = (float) r as the residual stored it,
+            // or, where no residual was computed (a declared zero guess: r = b), gathers b and
+            // rounds it (the same values either way)
+            const Prec p = (mixed && k == 2 && !y1) ? Prec::MIX_L1 : pL;
             st = sweep(c, p, gL, &F->Ls, Lval, cur, rr, epi, (epi == EPI_SCALE || epi == EPI_STORE) ? out : nullptr,
                        F->dinv, x, nullptr, dcol);
             if (st) return st;

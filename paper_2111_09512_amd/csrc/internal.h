@@ -17,7 +17,8 @@ enum Epi : int {
     EPI_SCALE = 1,        // out_i = dinv_i * t_i                  (s = D^{-1} y)
     EPI_UPDATE = 2,       // x_i = x_i + c_i * t_i                 (x += z)
     EPI_SCALE_UPDATE = 3, // x_i = x_i + c_i * (OT)(dinv_i * t_i)  (x += D^{-1} y when m_U = 1)
-    EPI_SPMV = 4          // out_i = sum_j N_ij xin_j  (no rhs; the product A z of the Krylov solver)
+    EPI_SPMV = 4,         // out_i = sum_j N_ij xin_j  (no rhs; the product A z of the Krylov solver)
+    EPI_STORE_SPLIT = 5   // out_i = t_i and out32_i = (float) t_i  (r and the FP32-inner form's y_1)
 };
 // c_i is the column factor d_c,i of the row/column scaling (SweepArgs::dcol),
 // or 1 (an exact multiplication) when dcol is null.
@@ -75,7 +76,10 @@ struct SweepArgs {
     int epi;
     void *out;            // EPI_STORE / EPI_SCALE destination
     const double *dinv;   // EPI_SCALE / EPI_SCALE_UPDATE
-    double *x;            // EPI_UPDATE / EPI_SCALE_UPDATE
+    union {
+        double *x;    // EPI_UPDATE / EPI_SCALE_UPDATE
+        float *out32; // EPI_STORE_SPLIT: the FP32 copy of out
+    };
     const double *dshift; // unscaled variant: adds (d_i - 1) * xin_i to the row sum (FP64 only)
     const double *dcol = nullptr; // EPI_UPDATE / EPI_SCALE_UPDATE: column factors c_i, or null (c_i = 1)
     const SlicedView *sv = nullptr; // batched sweeps: the op's sliced copy (device), or null: CSR-stream

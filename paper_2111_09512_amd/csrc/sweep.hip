@@ -95,6 +95,10 @@ __device__ __forceinline__ void epilogue(const SweepArgs &a, int row, typename T
     case EPI_SPMV:
         ((OT *)a.out)[row] = (OT)v;
         break;
+    case EPI_STORE_SPLIT:
+        ((OT *)a.out)[row] = (OT)v;
+        a.out32[row] = (float)v;
+        break;
     case EPI_SCALE:
         ((OT *)a.out)[row] = (OT)(a.dinv[row] * (double)v);
         break;
@@ -121,6 +125,10 @@ __device__ __forceinline__ void epilogue_pre(const SweepArgs &a, int row, typena
     case EPI_STORE:
     case EPI_SPMV:
         ((OT *)a.out)[row] = (OT)v;
+        break;
+    case EPI_STORE_SPLIT:
+        ((OT *)a.out)[row] = (OT)v;
+        a.out32[row] = (float)v;
         break;
     case EPI_SCALE:
         ((OT *)a.out)[row] = (OT)(aux * (double)v);
