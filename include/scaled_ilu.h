@@ -628,7 +628,12 @@ int silu_server_solve_result(silu_server *server, int64_t ticket, int *outer_ste
 int silu_server_step(silu_server *server, int *n_active, int *n_queued);
 /* Up to max_steps steps in one call (each one admits and launches as above),
  * stopping early when no request is active: a host loop that calls this
- * keeps the GPU fed with fewer round trips. */
+ * keeps the GPU fed with fewer round trips.  While no request waits for
+ * admission, no stop flag is pending and every active request has k or more
+ * ops left, up to 8 steps are enqueued together (their op tables copied to
+ * the device at once): the same launches, so the same results, with less host
+ * work per step; a solve request the device stops meanwhile skips its sweeps
+ * and is retired by the next single step. */
 int silu_server_run(silu_server *server, int max_steps, int *n_active, int *n_queued);
 /* state: 0 queued, 1 running, 2 last sweep enqueued, 3 done (result in x).
  * Returns SILU_ERR_TIMEOUT (state 3) for a request whose persistent launch

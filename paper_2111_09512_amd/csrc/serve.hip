@@ -130,6 +130,27 @@ struct Record {
     double relres = 0.0;
 };
 
+// One step's launches, planned for the active requests advanced by t ops:
+// their ops grouped by precision (one launch per precision present; the ops of
+// different requests are independent, so the launch order does not matter).
+// Groups of at most BATCH_ARG_OPS ops carry their table in the kernel
+// arguments; longer ones are packed into a staging buffer, copied to the
+// device before the step's launches.
+struct StagedGroup {
+    Prec kind;
+    size_t ops_off, first_off; // in the staging buffer
+    int k, total;
+};
+struct StepPlan {
+    int t = 0;
+    std::vector<SweepArgs> ops;
+    std::vector<Prec> prec;
+    int count[5] = {0, 0, 0, 0, 0};
+    StagedGroup sg[5];
+    int nsg = 0;
+};
+const Prec KINDS[5] = {Prec::F64, Prec::MIX_RES, Prec::MIX_L1, Prec::MIX_L, Prec::MIX_U};
+
 int64_t now_ns()
 {
     return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -177,8 +198,8 @@ struct silu_server {
     char *h_stage[RING] = {};
     char *d_stage = nullptr;
     int cap = 0; // op-table capacity
-    std::vector<SweepArgs> step_ops; // this step's ops and their precisions
-    std::vector<Prec> step_prec;
+    StepPlan step_plan;                // reused: the plan of a single step
+    std::vector<StepPlan> burst_plans; // and those of a burst
     hipError_t last = hipSuccess;
     // persistent mode
     int mode = 0;
@@ -770,6 +791,174 @@ int silu_server_solve_result(silu_server *s, int64_t ticket, int *outer_steps, d
     return SILU_OK;
 }
 
+void plan_step(const silu_server *s, int t, StepPlan &p)
+{
+    const int nops = (int)s->active.size();
+    p.t = t;
+    p.nsg = 0;
+    p.ops.resize((size_t)nops);
+    p.prec.resize((size_t)nops);
+    for (int i = 0; i < nops; i++) {
+        Request q = s->active[(size_t)i];
+        q.op += t;
+        p.ops[(size_t)i] = op_of(s, q, &p.prec[(size_t)i]);
+    }
+    for (int g = 0; g < 5; g++) p.count[g] = 0;
+    for (int i = 0; i < nops; i++)
+        for (int g = 0; g < 5; g++) p.count[g] += p.prec[(size_t)i] == KINDS[g];
+}
+
+bool plan_staged(const StepPlan &p)
+{
+    for (int g = 0; g < 5; g++)
+        if (p.count[g] > BATCH_ARG_OPS) return true;
+    return false;
+}
+
+// The plan's staged groups packed into buf from *used on.
+void pack_step(StepPlan &p, char *buf, size_t *used)
+{
+    const int nops = (int)p.ops.size();
+    for (int g = 0; g < 5; g++) {
+        if (p.count[g] <= BATCH_ARG_OPS) continue;
+        const size_t first_off = *used + sizeof(SweepArgs) * (size_t)p.count[g];
+        SweepArgs *h_ops = (SweepArgs *)(buf + *used);
+        int32_t *h_first = (int32_t *)(buf + first_off);
+        int k = 0, total = 0;
+        for (int i = 0; i < nops; i++) {
+            if (p.prec[(size_t)i] != KINDS[g]) continue;
+            h_ops[k] = p.ops[(size_t)i];
+            h_first[k++] = total;
+            total += (p.ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
+        }
+        h_first[k] = total;
+        p.sg[p.nsg++] = {KINDS[g], *used, first_off, k, total};
+        *used = align16(first_off + sizeof(int32_t) * (size_t)(k + 1));
+    }
+}
+
+// The plan's launches (staged groups reading d_stage, already copied), then
+// the closing launch of the convergence checks its ops make.
+hipError_t launch_step(silu_server *s, const StepPlan &p, const char *d_stage)
+{
+    const int nops = (int)p.ops.size();
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < 5 && e == hipSuccess; g++) {
+        if (!p.count[g] || p.count[g] > BATCH_ARG_OPS) continue;
+        BatchArgs ba;
+        int k = 0, total = 0;
+        for (int i = 0; i < nops; i++) {
+            if (p.prec[(size_t)i] != KINDS[g]) continue;
+            ba.op[k] = p.ops[(size_t)i];
+            ba.first[k++] = total;
+            total += (p.ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
+        }
+        ba.first[k] = total;
+        ba.nops = k;
+        e = launch_sweep_batch_args(KINDS[g], ba, s->stream);
+    }
+    for (int i = 0; i < p.nsg && e == hipSuccess; i++)
+        e = launch_sweep_batch(p.sg[i].kind, (const SweepArgs *)(d_stage + p.sg[i].ops_off),
+                               (const int32_t *)(d_stage + p.sg[i].first_off), p.sg[i].k, p.sg[i].total, s->stream);
+    SolveCheckArgs ca;
+    ca.count = 0;
+    for (const Request &q0 : s->active) {
+        if (e != hipSuccess) break;
+        const int op = q0.op + p.t;
+        if (q0.tol <= 0.0 || op % (1 + (q0.mL - 1) + (q0.mU - 1)) != 0) continue;
+        const int64_t n = s->mats[(size_t)q0.mid].A.n_rows;
+        char *cb = s->arena + q0.ws.off + 4 * vec_bytes(n);
+        ca.c[ca.count++] = {(SolveCtl *)cb, (const double *)(cb + sizeof(SolveCtl)),
+                            (int)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS), op == 0 ? 1 : 0, q0.tol,
+                            q0.flag >= 0 ? s->d_hflags + q0.flag : nullptr};
+        if (ca.count == SOLVE_CHECKS_PER_LAUNCH) {
+            e = launch_solve_check(ca, s->stream);
+            ca.count = 0;
+        }
+    }
+    if (e == hipSuccess && ca.count) e = launch_solve_check(ca, s->stream);
+    return e;
+}
+
+// The bookkeeping after the steps up to `last` were enqueued with every
+// active request advanced by `adv` ops: requests whose last op ran retire
+// (a finishing solve request's state goes to pinned host memory first), and
+// the last step records a mark when one is due (slot >= 0: already claimed
+// for a staging buffer).
+int finish_steps(silu_server *s, int adv, int slot)
+{
+    const int64_t last = s->steps - 1;
+    bool finishing = s->force_mark;
+    s->force_mark = false;
+    int st;
+    for (Request &q : s->active) {
+        if (q.op + adv != q.total) continue;
+        finishing = true;
+        if (q.tol > 0.0 && (st = save_result(s, q))) return st;
+    }
+    if (slot < 0 && (finishing || last - s->last_mark_step >= MARK_EVERY) && (st = claim_mark(s, &slot)))
+        return st;
+    if (slot >= 0 && (st = record_mark(s, slot, last))) return st;
+    size_t w = 0;
+    for (size_t i = 0; i < s->active.size(); i++) {
+        Request &q = s->active[i];
+        q.op += adv;
+        if (q.op == q.total) {
+            s->recs[q.ticket].finish_step = last;
+            s->to_release.push_back({last, q.ws});
+            s->to_report.push_back({last, q.ticket});
+        } else {
+            s->active[w++] = q;
+        }
+    }
+    s->active.resize(w);
+    return SILU_OK;
+}
+
+// Several steps enqueued together (silu_server_run): when nothing waits for
+// admission, no stop flag is pending and every active request has at least
+// k ops left, the next k steps are planned at once, their staged op tables
+// copied to the device with one copy, and their launches enqueued back to
+// back -- the launches of k single steps, with one copy and at most one mark
+// for all of them.  A request the device stops meanwhile skips its sweeps
+// there and is retired by the next single step.  *done: the steps enqueued
+// (0: none, the caller takes a single step).
+int burst(silu_server *s, int k_max, int *done)
+{
+    *done = 0;
+    if (s->mode != 0 || !s->queue.empty() || s->active.empty() || s->force_mark) return SILU_OK;
+    int k = std::min(k_max, MAX_AHEAD);
+    for (const Request &q : s->active) {
+        if (q.flag >= 0 && __atomic_load_n(&s->hflags[q.flag], __ATOMIC_ACQUIRE) != 0) return SILU_OK;
+        k = std::min(k, q.total - q.op);
+    }
+    if (k < 2) return SILU_OK;
+    int st;
+    if ((st = throttle(s))) return st;
+    std::vector<StepPlan> &plans = s->burst_plans;
+    if ((int)plans.size() < k) plans.resize((size_t)k);
+    bool staged = false;
+    for (int t = 0; t < k; t++) {
+        plan_step(s, t, plans[(size_t)t]);
+        staged |= plan_staged(plans[(size_t)t]);
+    }
+    int slot = -1;
+    if (staged) {
+        if ((st = grow(s, k * ((int)s->active.size() + 5)))) return st;
+        if ((st = claim_mark(s, &slot))) return st; // its staging buffer is free
+    }
+    size_t used = 0;
+    for (int t = 0; t < k && staged; t++) pack_step(plans[(size_t)t], s->h_stage[slot], &used);
+    hipError_t e = hipSuccess;
+    if (used) e = hipMemcpyAsync(s->d_stage, s->h_stage[slot], used, hipMemcpyHostToDevice, s->stream);
+    for (int t = 0; t < k && e == hipSuccess; t++) e = launch_step(s, plans[(size_t)t], s->d_stage);
+    if (e != hipSuccess) return fail(s, e);
+    s->steps += k;
+    if ((st = finish_steps(s, k, slot))) return st;
+    *done = k;
+    return SILU_OK;
+}
+
 int silu_server_step(silu_server *s, int *n_active, int *n_queued)
 {
     if (!s) return SILU_ERR_ARG;
@@ -842,109 +1031,22 @@ int silu_server_step(silu_server *s, int *n_active, int *n_queued)
         s->queue.pop_front();
     }
     if (!s->active.empty()) {
-        const int nops = (int)s->active.size();
-        // the step's ops, one launch per precision present (the ops of different
-        // requests are independent, so their launch order does not matter)
-        std::vector<SweepArgs> &ops = s->step_ops;
-        std::vector<Prec> &prec = s->step_prec;
-        ops.resize((size_t)nops);
-        prec.resize((size_t)nops);
-        for (int i = 0; i < nops; i++) ops[(size_t)i] = op_of(s, s->active[(size_t)i], &prec[(size_t)i]);
-        static const Prec kinds[5] = {Prec::F64, Prec::MIX_RES, Prec::MIX_L1, Prec::MIX_L, Prec::MIX_U};
-        int count[5] = {0, 0, 0, 0, 0};
-        for (int i = 0; i < nops; i++)
-            for (int g = 0; g < 5; g++) count[g] += prec[(size_t)i] == kinds[g];
-        bool staged = false;
-        for (int g = 0; g < 5; g++) staged |= count[g] > BATCH_ARG_OPS;
-        int st = staged ? grow(s, nops + 5) : SILU_OK;
+        StepPlan &p = s->step_plan;
+        plan_step(s, 0, p);
+        const bool staged = plan_staged(p);
+        int st = staged ? grow(s, (int)s->active.size() + 5) : SILU_OK;
         if (st) return st;
         if ((st = throttle(s))) return st;
         int slot = -1;
-        if (staged && (st = claim_mark(s, &slot))) return st; // its staging buffers are free
-        bool finishing = false;
-        for (const Request &q : s->active) finishing |= q.op + 1 == q.total;
+        if (staged && (st = claim_mark(s, &slot))) return st; // its staging buffer is free
+        size_t used = 0;
+        if (staged) pack_step(p, s->h_stage[slot], &used);
         hipError_t e = hipSuccess;
-        struct Staged {
-            Prec kind;
-            size_t ops_off, first_off;
-            int k, total;
-        } sg[5];
-        int nsg = 0;
-        size_t used = 0; // bytes of this step's staging buffer filled
-        for (int g = 0; g < 5 && e == hipSuccess; g++) {
-            if (!count[g]) continue;
-            if (count[g] <= BATCH_ARG_OPS) { // the op table travels in the kernel arguments
-                BatchArgs ba;
-                int k = 0, total = 0;
-                for (int i = 0; i < nops; i++) {
-                    if (prec[(size_t)i] != kinds[g]) continue;
-                    ba.op[k] = ops[(size_t)i];
-                    ba.first[k++] = total;
-                    total += (ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
-                }
-                ba.first[k] = total;
-                ba.nops = k;
-                e = launch_sweep_batch_args(kinds[g], ba, s->stream);
-            } else { // packed into this step's staging buffer, launched after its one copy
-                const size_t first_off = used + sizeof(SweepArgs) * (size_t)count[g];
-                SweepArgs *h_ops = (SweepArgs *)(s->h_stage[slot] + used);
-                int32_t *h_first = (int32_t *)(s->h_stage[slot] + first_off);
-                int k = 0, total = 0;
-                for (int i = 0; i < nops; i++) {
-                    if (prec[(size_t)i] != kinds[g]) continue;
-                    h_ops[k] = ops[(size_t)i];
-                    h_first[k++] = total;
-                    total += (ops[(size_t)i].n + SERVE_RPB - 1) / SERVE_RPB;
-                }
-                h_first[k] = total;
-                sg[nsg++] = {kinds[g], used, first_off, k, total};
-                used = align16(first_off + sizeof(int32_t) * (size_t)(k + 1));
-            }
-        }
-        if (e == hipSuccess && nsg)
-            e = hipMemcpyAsync(s->d_stage, s->h_stage[slot], used, hipMemcpyHostToDevice, s->stream);
-        for (int i = 0; i < nsg && e == hipSuccess; i++)
-            e = launch_sweep_batch(sg[i].kind, (const SweepArgs *)(s->d_stage + sg[i].ops_off),
-                                   (const int32_t *)(s->d_stage + sg[i].first_off), sg[i].k, sg[i].total, s->stream);
+        if (used) e = hipMemcpyAsync(s->d_stage, s->h_stage[slot], used, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = launch_step(s, p, s->d_stage);
         if (e != hipSuccess) return fail(s, e);
-        // close the convergence checks of solve requests made in this launch
-        SolveCheckArgs ca;
-        ca.count = 0;
-        for (const Request &q : s->active) {
-            if (q.tol <= 0.0 || q.op % (1 + (q.mL - 1) + (q.mU - 1)) != 0) continue;
-            const int64_t n = s->mats[(size_t)q.mid].A.n_rows;
-            char *cb = s->arena + q.ws.off + 4 * vec_bytes(n);
-            ca.c[ca.count++] = {(SolveCtl *)cb, (const double *)(cb + sizeof(SolveCtl)),
-                                (int)((n + SERVE_TILE_ROWS - 1) / SERVE_TILE_ROWS), q.op == 0 ? 1 : 0, q.tol,
-                                q.flag >= 0 ? s->d_hflags + q.flag : nullptr};
-            if (ca.count == SOLVE_CHECKS_PER_LAUNCH) {
-                if ((e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
-                ca.count = 0;
-            }
-        }
-        if (ca.count && (e = launch_solve_check(ca, s->stream)) != hipSuccess) return fail(s, e);
-        // a finishing solve request's state goes to pinned host memory before the mark
-        for (Request &q : s->active)
-            if (q.tol > 0.0 && q.op + 1 == q.total && (st = save_result(s, q))) return st;
-        const int64_t step = s->steps++;
-        finishing |= s->force_mark;
-        s->force_mark = false;
-        if (slot < 0 && (finishing || step - s->last_mark_step >= MARK_EVERY) && (st = claim_mark(s, &slot)))
-            return st;
-        if (slot >= 0 && (st = record_mark(s, slot, step))) return st;
-        size_t w = 0;
-        for (size_t i = 0; i < s->active.size(); i++) {
-            Request &q = s->active[i];
-            q.op++;
-            if (q.op == q.total) {
-                s->recs[q.ticket].finish_step = step;
-                s->to_release.push_back({step, q.ws});
-                s->to_report.push_back({step, q.ticket});
-            } else {
-                s->active[w++] = q;
-            }
-        }
-        s->active.resize(w);
+        s->steps++;
+        if ((st = finish_steps(s, 1, slot))) return st;
     } else if (s->force_mark) { // stopped solve requests and nothing to launch: an empty step ends them
         s->force_mark = false;
         const int64_t step = s->steps++;
@@ -962,9 +1064,18 @@ int silu_server_run(silu_server *s, int max_steps, int *n_active, int *n_queued)
 {
     if (!s || max_steps < 1) return SILU_ERR_ARG;
     int a = 0, q = 0;
-    for (int k = 0; k < max_steps; k++) {
-        const int st = silu_server_step(s, &a, &q);
+    for (int k = 0; k < max_steps;) {
+        int done = 0;
+        int st = burst(s, max_steps - k, &done);
         if (st) return st;
+        if (done) {
+            k += done;
+            a = (int)s->active.size();
+            q = (int)s->queue.size();
+        } else {
+            if ((st = silu_server_step(s, &a, &q))) return st;
+            k++;
+        }
         if (a == 0) break;
     }
     if (n_active) *n_active = a;

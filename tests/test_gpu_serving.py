@@ -63,11 +63,17 @@ def _alone(ctx, pool, r):
     return host(x)
 
 
-def _drain(server, tickets, max_steps=100000):
+def _drain(server, tickets, max_steps=100000, per_call=1):
+    """Step the server until every ticket is done; per_call > 1: that many
+    scheduling steps per call (silu_server_run, which enqueues several steps
+    at once while nothing waits for admission)."""
     left = set(tickets)
     steps = 0
     while left:
-        server.step()
+        if per_call > 1:
+            server.run(per_call)
+        else:
+            server.step()
         steps += 1
         for t in list(left):
             if server.poll(t) == server.DONE:
@@ -417,13 +423,15 @@ def _tol_with_margin(hist_fn, tol):
     raise AssertionError("no tolerance with a margin")
 
 
-def test_solve_requests_match_the_oracle(orc, B, ctx, pool):
+@pytest.mark.parametrize("per_call", [1, 16], ids=["step", "run16"])
+def test_solve_requests_match_the_oracle(orc, B, ctx, pool, per_call):
     """Solve requests (iterate until eq. relres < tol) in the same steps as
     smoother requests: the outer-step count and x equal the oracle's
     smooth_until bit for bit, the reported relative residual to rounding;
     including x0 already converged (0 steps), max_outer = 0, a request that
     never converges (max_outer + 1) and m_L = 1 (the residual fused with
-    D^{-1})."""
+    D^{-1}); driven one step per call and 16 per call (several steps
+    enqueued at once)."""
     say("serving: solve requests")
     server = B.Server(ctx, arena_bytes=64 << 20, max_active=64)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
@@ -456,7 +464,7 @@ def test_solve_requests_match_the_oracle(orc, B, ctx, pool):
         n = pool[c["mid"]]["A"].n
         server.submit(mids[c["mid"]], dev(W.rhs(n, 900 + k)), torch.zeros(n, dtype=torch.float64, device="cuda"),
                       2, 3, 3)
-    _drain(server, tickets)
+    _drain(server, tickets, per_call=per_call)
     seen = set()
     for k, c in enumerate(cases):
         k_ref, x_ref, hist = c["ref"]
@@ -505,10 +513,12 @@ def test_solve_request_finishes_when_converged(orc, B, ctx, pool):
     server.close()
 
 
-def test_more_than_64_requests_in_one_step(B, ctx, pool):
+@pytest.mark.parametrize("per_call", [1, 8], ids=["step", "run8"])
+def test_more_than_64_requests_in_one_step(B, ctx, pool, per_call):
     """Over 64 requests active at once (the launch finds a workgroup's op by
     bisection there, by one ballot per wave up to 64): each result equals the
-    request alone."""
+    request alone; with 8 steps per call their staged op tables of several
+    steps share one copy."""
     say("serving: > 64 active requests")
     server = B.Server(ctx, arena_bytes=256 << 20, max_active=160)
     mids = [server.register(p["Ad"], p["F"]) for p in pool]
@@ -525,13 +535,14 @@ def test_more_than_64_requests_in_one_step(B, ctx, pool):
         tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"]))
     a, q = server.step()
     assert a > 64 and q == 0
-    _drain(server, tickets)
+    _drain(server, tickets, per_call=per_call)
     for i, r in enumerate(reqs):
         np.testing.assert_array_equal(host(xs[i]), _alone(ctx, pool, r))
     server.close()
 
 
-def test_fp32_inner_requests_equal_the_single_call(orc, B, ctx):
+@pytest.mark.parametrize("per_call", [1, 16], ids=["step", "run16"])
+def test_fp32_inner_requests_equal_the_single_call(orc, B, ctx, per_call):
     """FP32-inner requests (L and U~ sweeps on FP32 factor values) mixed in the
     same steps with FP64 ones, on sliced and streamed matrices: each equals
     ilu_smooth(mixed=True) alone bit for bit (the FP64 ones ilu_smooth), and
@@ -563,7 +574,7 @@ def test_fp32_inner_requests_equal_the_single_call(orc, B, ctx):
         x = dev(r["x0"])
         xs.append(x)
         tickets.append(server.submit(mids[r["mid"]], dev(r["b"]), x, r["outer"], r["mL"], r["mU"], mixed=r["mixed"]))
-    _drain(server, tickets)
+    _drain(server, tickets, per_call=per_call)
     for i, r in enumerate(reqs):
         p = pool[r["mid"]]
         xa = dev(r["x0"])
