@@ -76,6 +76,8 @@ extern "C" {
                                   /* the per-row pattern table                                */
 #define SILU_RELABELED 0x200000   /* ilu_smooth with SILU_REORDER: b and x are already in the  */
                                   /* relabeled order (silu_reorder_vectors); no permutations  */
+#define SILU_ROWPAT 0x400000      /* sliced sweeps: the per-row pattern table even where every  */
+                                  /* row lies on a few diagonals (no diagonal slices)          */
 
 #define SILU_LOWER 0
 #define SILU_UPPER 1
@@ -302,7 +304,7 @@ int silu_reorder_vectors(silu_ctx *ctx, const silu_csr *A, const silu_factors *F
  * n-vectors, 256-byte rounded, in 64 MiB), else SILU_ERR_NOMEM.  flags: only
  * SILU_MIXED, SILU_ZERO_GUESS, SILU_CHECK_FINITE and the kernel-choice flags
  * (SILU_KERNEL_STREAM, SILU_KERNEL_VECTOR, SILU_INDEX32, SILU_NO_WINDOW,
- * SILU_CODE16, SILU_CODE8, SILU_SLICED_LOOP), else SILU_ERR_ARG.  Every call
+ * SILU_CODE16, SILU_CODE8, SILU_ROWPAT, SILU_SLICED_LOOP), else SILU_ERR_ARG.  Every call
  * on one device shares that device's scratch array, which keeps the last
  * call's contents: calls that overlap on one GPU (other streams, other
  * contexts, other threads) race and must be ordered by the caller.

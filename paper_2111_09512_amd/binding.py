@@ -35,12 +35,13 @@ SILU_NO_GRAPH, SILU_INDEX32, SILU_NO_WINDOW, SILU_WINDOW = 0x800, 0x1000, 0x2000
 SILU_CODE16, SILU_ZERO_GUESS, SILU_GRAPH, SILU_REORDER = 0x8000, 0x10000, 0x20000, 0x40000
 SILU_SLICED_LOOP = 0x80000
 SILU_CODE8 = 0x100000
+SILU_ROWPAT = 0x400000
 SILU_RELABELED = 0x200000
 # None: sliced copies (1-byte diagonal codes where they fit, else 2, else 4);
 # "sliced16": no diagonal table; "sliced32": 4-byte columns;
 # "stream": CSR-stream, 16-bit offsets where they fit, else the LDS window, else col_idx;
 # "win": the LDS window wherever it fits; "stream16": offsets at most; "stream32": col_idx always
-KERNELS = {None: 0, "sliced8": SILU_CODE8, "sliced_loop": SILU_CODE8 | SILU_SLICED_LOOP, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
+KERNELS = {None: 0, "rowpat": SILU_ROWPAT, "sliced8": SILU_CODE8, "sliced_loop": SILU_CODE8 | SILU_SLICED_LOOP, "sliced16": SILU_CODE16, "sliced32": SILU_INDEX32, "blocked": SILU_KERNEL_BLOCKED,
            "stream": SILU_KERNEL_STREAM, "vector": SILU_KERNEL_VECTOR, "win": SILU_KERNEL_STREAM | SILU_WINDOW,
            "stream16": SILU_KERNEL_STREAM | SILU_NO_WINDOW, "stream32": SILU_KERNEL_STREAM | SILU_INDEX32}
 SILU_LOWER, SILU_UPPER = 0, 1

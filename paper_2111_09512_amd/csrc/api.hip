@@ -503,16 +503,84 @@ bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<i
     return true;
 }
 
+// Diagonal slices of N (code 16) when every row lies on at most DIAG_MAX
+// diagonals col - row and their slots (one per diagonal for every row, in
+// 128-row slices) exceed the entries by at most 1/16: *built is then true.
+int build_diag(silu_ctx *c, const silu_csr *N, const double *val, Sliced &S, bool *built)
+{
+    *built = false;
+    const int n = (int)N->n_rows;
+    if (n < 2 || N->nnz <= 0) return SILU_OK;
+    int32_t range[2];
+    HIPCHK(c, launch_init_flags(c->d_flags, 1, INT32_MAX, c->stream));
+    HIPCHK(c, launch_init_flags(c->d_flags + 1, 1, INT32_MIN, c->stream));
+    HIPCHK(c, launch_offset_range(n, N->row_ptr, N->col_idx, 1, c->d_flags, c->stream));
+    HIPCHK(c, hipMemcpyAsync(range, c->d_flags, sizeof(range), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t dlo = range[0], span = (int64_t)range[1] - range[0] + 1;
+    if (span < 1 || span > (int64_t)1 << 24) return SILU_OK;
+    uint8_t *d_used = nullptr;
+    const int64_t span8 = (span + 7) / 8;
+    HIPCHK(c, hipMalloc(&d_used, (size_t)span8 * 8));
+    hipError_t e = launch_fill((int)span8, (double *)d_used, 0.0, nullptr, 0.0, c->stream);
+    if (e == hipSuccess) e = launch_mark_offsets(n, N->row_ptr, N->col_idx, 1, (int)dlo, d_used, c->stream);
+    std::vector<uint8_t> used((size_t)span);
+    if (e == hipSuccess) e = hipMemcpyAsync(used.data(), d_used, (size_t)span, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(d_used);
+    if (e != hipSuccess) return hip_fail(c, e);
+    std::vector<int32_t> dtab, dmap((size_t)span, 0);
+    for (int64_t t = 0; t < span && (int)dtab.size() <= DIAG_MAX; t++) {
+        if (!used[(size_t)t]) continue;
+        dmap[(size_t)t] = (int32_t)dtab.size();
+        dtab.push_back((int32_t)(t + dlo));
+    }
+    const int u = (int)dtab.size();
+    const int nslice = (n + 127) / 128;
+    const int64_t slots = (int64_t)nslice * u * 128;
+    if (u > DIAG_MAX || slots > N->nnz + N->nnz / 16 + 128 * (int64_t)u || slots > INT32_MAX) return SILU_OK;
+    int32_t *d_dmap = nullptr;
+    e = hipMalloc(&S.val, (size_t)slots * 8);
+    if (e == hipSuccess) e = hipMalloc(&S.dtab, (size_t)u * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.dtab, dtab.data(), (size_t)u * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMalloc(&d_dmap, dmap.size() * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_dmap, dmap.data(), dmap.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = launch_fill_diag(n, nslice, u, N->row_ptr, N->col_idx, val, d_dmap, (int)dlo, (double *)S.val, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream); // the host tables go out of scope
+    (void)hipFree(d_dmap);
+    if (e != hipSuccess) {
+        free_sliced(S);
+        return hip_fail(c, e);
+    }
+    S.v = SlicedView();
+    S.v.nslice = nslice;
+    S.v.code = 16;
+    S.v.val = S.val;
+    S.v.dtab = S.dtab;
+    S.v.ndiag = u;
+    S.v.slots = slots;
+    S.ok = true;
+    *built = true;
+    return SILU_OK;
+}
+
 // Build (once) the sliced-ELL copy of N with values `val` of `vbytes` bytes.
-// code_min: 0 allows the row-pattern table, 1 the diagonal table, 2 starts at
-// 16-bit offsets, 4 uses columns.  *out->ok is false when the matrix has no entries or the copy
-// would not fit 32-bit slot indices (the caller then streams the CSR).
+// code_min: -1 allows diagonal slices (FP64 values), 0 the row-pattern table,
+// 1 the diagonal table, 2 starts at 16-bit offsets, 4 uses columns.  *out->ok
+// is false when the matrix has no entries or the copy would not fit 32-bit
+// slot indices (the caller then streams the CSR).
 int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, int code_min, Sliced &S)
 {
     const int n = (int)N->n_rows;
     const int nslice = (n + 63) / 64;
     auto store = [&]() { return SILU_OK; }; // S.ok stays false unless the copy was built
     if (N->nnz <= 0 || n <= 0) return store();
+    if (code_min < 0 && vbytes == 8) {
+        bool built = false;
+        const int st = build_diag(c, N, (const double *)val, S, &built);
+        if (st || built) return st;
+    }
     // per-slice K and mask bit, then slot offsets
     HIPCHK(c, hipMalloc(&S.sk, (size_t)nslice * 4));
     hipError_t e = launch_slice_meta(n, nslice, N->row_ptr, S.sk, c->stream);
@@ -691,6 +759,8 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
 {
     double sliced_bytes = -1.0;
     bool fell_back = false; // the default sliced layout did not apply
+    // diagonal slices hold FP64 values and add no unscaled-variant diagonal term
+    if (g.slice_code_min < 0 && (dshift || !(p == Prec::F64 || p == Prec::MIX_RES))) g.slice_code_min = 0;
     if (g.kind == SweepKernel::SLICED) {
         const int vbytes = (p == Prec::F64 || p == Prec::MIX_RES) ? 8 : 4;
         Sliced *S = nullptr;
@@ -700,8 +770,9 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
             g.sl = S->v;
             const double xb = (p == Prec::MIX_L || p == Prec::MIX_U) ? 4.0 : 8.0;
             const double rb = p == Prec::MIX_U ? 4.0 : 8.0;
-            const int cb = S->v.code == 8 ? 0 : S->v.code; // row patterns: one byte per row instead
-            sliced_bytes = (double)S->v.slots * (vbytes + cb) + 8.0 * S->v.nslice +
+            // row patterns: one byte per row instead of codes; diagonal slices: neither, no slice table
+            const int cb = (S->v.code == 8 || S->v.code == 16) ? 0 : S->v.code;
+            sliced_bytes = (double)S->v.slots * (vbytes + cb) + (S->v.code == 16 ? 0.0 : 8.0 * S->v.nslice) +
                            8.0 * (double)S->masked_rows + (double)N->n_rows * (xb + rb) + 4.0 * S->v.ndiag +
                            (S->v.code == 8 ? (double)N->n_rows + 4.0 * S->v.npat * S->v.kp : 0.0);
         } else {
@@ -1375,7 +1446,7 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         bool split = false;
         if (mixed && m_L >= 2 && gL.kind == SweepKernel::SLICED) {
             Sliced *SL = nullptr;
-            if ((st = get_sliced(c, &F->Ls, Lval, 4, gL.slice_code_min, &SL))) return st;
+            if ((st = get_sliced(c, &F->Ls, Lval, 4, std::max(gL.slice_code_min, 0), &SL))) return st;
             split = SL->ok;
         }
         const void *rr = r, *y1 = nullptr;
@@ -1509,7 +1580,7 @@ int ilu_smooth_noalloc(silu_ctx *c, const silu_csr *A, const silu_factors *F, co
 {
     constexpr int allowed = SILU_MIXED | SILU_ZERO_GUESS | SILU_CHECK_FINITE | SILU_KERNEL_STREAM |
                             SILU_KERNEL_VECTOR | SILU_INDEX32 | SILU_NO_WINDOW | SILU_CODE16 | SILU_CODE8 |
-                            SILU_SLICED_LOOP;
+                            SILU_ROWPAT | SILU_SLICED_LOOP;
     if (!c || !A || (flags & ~allowed)) return SILU_ERR_ARG;
     if (A->n_rows < 0 || A->n_rows >= INT32_MAX) return SILU_ERR_ARG;
     size_t need = 0;

@@ -37,7 +37,8 @@ enum class SweepKernel : int { STREAM = 0, VECTOR = 1, BLOCKED = 2, SLICED = 3 }
 // Sliced-ELL copy of a CSR matrix (64-row slices, one wavefront per slice;
 // built once per matrix on the device and cached).  code: bytes per column
 // code -- 1 (index into the table of distinct diagonals col - row), 2
-// (slice-relative offset col - 64 s - shift) or 4 (the column).
+// (slice-relative offset col - 64 s - shift) or 4 (the column); 8: row
+// patterns (below); 16: diagonal slices (below).
 struct SlicedView {
     int nslice = 0;
     int code = 4;
@@ -56,7 +57,20 @@ struct SlicedView {
     const uint8_t *pid = nullptr;  // [nslice * 64] pattern of each row
     const int32_t *ptab = nullptr; // [npat * kp]
     int npat = 0, kp = 0;
+    // code 16 (diagonal slices, FP64 values only): every row of the matrix lies
+    // on the ndiag <= DIAG_MAX diagonals dtab[] (ascending); nslice slices of
+    // 128 rows, slot k of row r holding its entry on diagonal dtab[k] (0 where
+    // it has none) at val[diag_slot(r, k, ndiag)]
 };
+// Diagonal slices: at most this many diagonals, and at most 1/16 more slots
+// than entries.
+constexpr int DIAG_MAX = 32;
+// The value slot of row r (slice r / 128) on the k-th of u diagonals: the
+// slice's slots are diagonal-major, each diagonal's 128 rows consecutive.
+__host__ __device__ inline int64_t diag_slot(int r, int k, int u)
+{
+    return ((int64_t)(r >> 7) * u + k) * 128 + (r & 127);
+}
 // Row-pattern tables are kept to at most this many offsets (16 KB, small
 // enough to stay in the caches while a sweep reads it).
 constexpr int PAT_MAX_ENTRIES = 4096;
@@ -166,6 +180,10 @@ hipError_t launch_gs_fill(int n, const int32_t *rp, const int32_t *col, const do
                           hipStream_t s);
 // Sliced-ELL set-up: per-slice K and mask bit; fill values and codes.
 hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, hipStream_t s);
+// Diagonal slices (code 16): zero the copy, then place every entry at its
+// row's slot on diagonal dmap[col - row - lo].
+hipError_t launch_fill_diag(int n, int nslice, int u, const int32_t *rp, const int32_t *col, const double *val,
+                            const int32_t *dmap, int lo, double *sval, hipStream_t s);
 hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,
                               const int32_t *sptr, const int32_t *sk, int code, const int32_t *dmap, int lo,
                               void *sval, void *scode, hipStream_t s);

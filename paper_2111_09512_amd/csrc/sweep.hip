@@ -634,6 +634,146 @@ hipError_t go_pat(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Diagonal slices (code 16): every row lies on the same few diagonals (a
+// stencil operator and its ILU(0)/ILU(1) factors), so slot k of every row
+// holds its entry on diagonal d_k (0 where the row has none) and the rows of
+// a slice share their slots' column offsets: no per-slot code, no per-row
+// pattern, and neighbouring rows gather neighbouring iterate values.  Each
+// lane owns two consecutive rows of a 128-row slice: one 16-byte load brings
+// both rows' values of a slot, one 16-byte load both rows' iterate values on
+// that slot's diagonal -- half the iterate loads of one row per lane, whose
+// count (not their bytes) bounds the row-pattern sweeps.  Every value and
+// iterate load of the slice is issued before the first is waited for (the
+// kernel is compiled for two waves per SIMD where the U slots need the
+// registers), the rhs after them; so are the other epilogue operands, except
+// above 24 slots, where their registers would not fit beside the slots' and
+// they are loaded once the sums are done.  Each row's products are
+// summed in ascending diagonal (= column) order (no unscaled-variant
+// diagonal term: such sweeps take the row-pattern copy); a slot the row lacks adds
+// 0 * x = +-0 to a sum that started at +0.0 and so is never -0.0, which
+// leaves it unchanged: finite results are the row-sum of the oracle bit for
+// bit.  In the slices at either end of the matrix the iterate pair is loaded
+// at the column clamped into [0, n - 2]: a column outside the matrix only
+// occurs on a slot whose value is 0, and the clamped pair still gives the
+// other row of the lane its own value.
+// A row's epilogue operands (those of epilogue_pre), for rows that exist.
+__device__ __forceinline__ void diag_operands(const SweepArgs &a, int row, double &aux, double &aux2, double &cf)
+{
+    if (row >= a.n) return;
+    if (a.epi == EPI_UPDATE) aux = a.x[row];
+    if (a.epi == EPI_SCALE || a.epi == EPI_SCALE_UPDATE) aux = a.dinv[row];
+    if (a.epi == EPI_SCALE_UPDATE) aux2 = a.x[row];
+    if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
+}
+
+template <class T, int U>
+__device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView &s, int wave)
+{
+    using XT = typename T::XT;
+    using RT = typename T::RT;
+    using AT = typename T::AT;
+    static_assert(sizeof(typename T::VT) == 8 && sizeof(XT) == 8, "FP64 values and iterates");
+    const int n = a.n;
+    const int lane = (int)threadIdx.x & 63;
+    const int ra = wave * 128 + 2 * lane;
+    const XT *__restrict__ xin = (const XT *)a.xin;
+    int d[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) d[k] = __builtin_amdgcn_readfirstlane(s.dtab[k]);
+    f64x2 v[U], xv[U];
+    const int r0 = wave * 128;
+    if (r0 + d[0] >= 0 && r0 + 127 + d[U - 1] <= n - 1) { // every column inside the matrix
+        // buffer loads: the slice's values and its iterate window as two
+        // resources, the slot's offset in a scalar register, the lane's in one
+        // vector register shared by every load (no address registers per load)
+        const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)((const f64x2 *)s.val + (int64_t)wave * U * 64), (short)0, U * 1024, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(xin + (r0 + d[0])), (short)0, (128 + d[U - 1] - d[0]) * 8, 0x00020000);
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            v[k] = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rv, lane * 16, k * 1024, 2));
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            xv[k] = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rx, lane * 16, (d[k] - d[0]) * 8, 0));
+    } else { // a slice at either end of the matrix
+        const f64x2 *pv = (const f64x2 *)s.val + (int64_t)wave * U * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(pv + 64 * k);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int raw = ra + d[k];
+            const int idx = min(max(raw, 0), n - 2);
+            f64x2 t;
+            __builtin_memcpy(&t, xin + idx, 16);
+            xv[k].x = raw > n - 2 ? t.y : t.x;
+            xv[k].y = raw < 0 ? t.x : t.y;
+        }
+    }
+    RT rh0 = (RT)0, rh1 = (RT)0;
+    if (a.epi != EPI_SPMV) {
+        if (ra < n) rh0 = ((const RT *)a.rhs)[ra];
+        if (ra + 1 < n) rh1 = ((const RT *)a.rhs)[ra + 1];
+    }
+    double aux0 = 0.0, aux1 = 0.0, aux20 = 0.0, aux21 = 0.0, cf0 = 1.0, cf1 = 1.0;
+    if constexpr (U <= 24) {
+        diag_operands(a, ra, aux0, aux20, cf0);
+        diag_operands(a, ra + 1, aux1, aux21, cf1);
+    }
+    AT sa = (AT)0, sb = (AT)0;
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        sa = sa + (AT)v[k].x * (AT)xv[k].x;
+        sb = sb + (AT)v[k].y * (AT)xv[k].y;
+    }
+    if constexpr (U > 24) {
+        diag_operands(a, ra, aux0, aux20, cf0);
+        diag_operands(a, ra + 1, aux1, aux21, cf1);
+    }
+    if (ra < n) epilogue_pre<T>(a, ra, a.epi == EPI_SPMV ? sa : (AT)rh0 - sa, aux0, aux20, cf0);
+    if (ra + 1 < n) epilogue_pre<T>(a, ra + 1, a.epi == EPI_SPMV ? sb : (AT)rh1 - sb, aux1, aux21, cf1);
+}
+
+template <class T, int U>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sweep_diag_wide(SweepArgs a,
+                                                                                                      SlicedView s)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * 4 +
+                                                    ((int)threadIdx.x >> 6));
+    if (wave < s.nslice) diag_slice<T, U>(a, s, wave);
+}
+
+template <class T, int U>
+__global__ void __launch_bounds__(256) k_sweep_diag(SweepArgs a, SlicedView s)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * 4 +
+                                                    ((int)threadIdx.x >> 6));
+    if (wave < s.nslice) diag_slice<T, U>(a, s, wave);
+}
+
+// Launch of the diagonal-slice sweep, specialised on the number of diagonals
+// (13 to 28 take the two-waves-per-SIMD build, which keeps all the loads of a
+// slice in flight without spilling; with fewer the registers allow that at
+// any occupancy, with more only at one wave per SIMD).
+template <class T, int U>
+hipError_t go_diag_u(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
+{
+    const dim3 grid((g.sl.nslice + 3) / 4), block(256);
+    if (U > 12 && U <= 28)
+        hipLaunchKernelGGL((k_sweep_diag_wide<T, U>), grid, block, 0, s, a, g.sl);
+    else
+        hipLaunchKernelGGL((k_sweep_diag<T, U>), grid, block, 0, s, a, g.sl);
+    return hipGetLastError();
+}
+
+template <class T, int U = DIAG_MAX>
+hipError_t go_diag(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
+{
+    if (g.sl.ndiag == U) return go_diag_u<T, U>(g, a, s);
+    if constexpr (U > 1) return go_diag<T, U - 1>(g, a, s);
+    return hipErrorInvalidValue;
+}
+
 template <class T, int CODE, int WPB, int UNR>
 __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedView s)
 {
@@ -1036,6 +1176,15 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         constexpr int WPB = 4, UNR = 2;
         if (g.sl.nslice <= 0) return hipErrorInvalidValue;
         const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
+        if (g.sl.code == 16) {
+            if constexpr (sizeof(typename T::VT) == 8 && sizeof(typename T::XT) == 8) {
+                if (g.sl.ndiag < 1 || g.sl.ndiag > DIAG_MAX || a.n < 2 || (int64_t)g.sl.nslice * 128 < a.n ||
+                    a.dshift)
+                    return hipErrorInvalidValue;
+                return go_diag<T>(g, a, s);
+            }
+            return hipErrorInvalidValue; // FP64 values and iterates only
+        }
         if (g.sl.code == 8) {
             if (g.sl.npat < 1 || g.sl.kp < 4 || (g.sl.kp & 3) || g.sl.npat * g.sl.kp > PAT_MAX_ENTRIES ||
                 g.sl.gmax > 8 || g.sl.kp != 4 * g.sl.gmax)
@@ -1175,8 +1324,10 @@ SweepGeom pick_geom(int64_t n, int64_t nnz, int flags)
         g.allow16 = !(flags & 0x1000);
         g.allow_win = !(flags & 0x1000) && !(flags & 0x2000);
         g.prefer_win = false;
-        // SILU_INDEX32, SILU_CODE16, SILU_CODE8; by default the row-pattern table where it fits
-        g.slice_code_min = (flags & 0x1000) ? 4 : ((flags & 0x8000) ? 2 : ((flags & 0x100000) ? 1 : 0));
+        // SILU_INDEX32, SILU_CODE16, SILU_CODE8, SILU_ROWPAT; by default diagonal slices, else the
+        // row-pattern table where it fits
+        g.slice_code_min = (flags & 0x1000) ? 4
+                                            : ((flags & 0x8000) ? 2 : ((flags & 0x100000) ? 1 : ((flags & 0x400000) ? 0 : -1)));
         g.slice_prefetch = !(flags & 0x80000);                                // SILU_SLICED_LOOP
         return g;
     }

@@ -27,7 +27,10 @@ def ctx(B):
     return B.Context()
 
 
-KERNELS = [None, "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "blocked", "vector"]  # None: sliced copies (the default)
+# None: sliced copies (the default: diagonal slices where every row lies on a few
+# diagonals, else row patterns); "rowpat": row patterns even there
+KERNELS = [None, "rowpat", "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32",
+           "blocked", "vector"]
 
 SMALL = {
     "poisson17": (lambda: W.poisson7(17), "ilu0", {}),
@@ -579,3 +582,40 @@ def test_row_pattern_tables(orc, B, ctx, npat, rowlen):
         for kernel in (None, "sliced8"):
             np.testing.assert_array_equal(host(ctx.trisolve_iter(Td, dev(rhs), m, kernel=kernel)),
                                           orc.richardson(T, rhs, m))
+
+
+def _banded(n, diags, seed, drop=0.0):
+    """n x n matrix on the given diagonals (entries outside the matrix
+    dropped), each entry kept with probability 1 - drop, values of both signs."""
+    rng = np.random.default_rng(seed)
+    D = np.zeros((n, n))
+    for d in diags:
+        i = np.arange(max(0, -d), min(n, n - d))
+        keep = rng.random(i.size) >= drop
+        D[i[keep], i[keep] + d] = rng.uniform(-1.0, 1.0, int(keep.sum())) / len(diags)
+    return W.CSR.from_dense(D)
+
+
+@pytest.mark.parametrize("n", [2, 3, 127, 128, 129, 255, 300, 1000])
+@pytest.mark.parametrize("diags,drop", [((-130, -7, -1, 1, 2, 64, 129), 0.0), ((-3, -2, -1), 0.02),
+                                        (tuple(range(-30, 0)), 0.0), ((-1, 1), 0.5)])
+def test_diagonal_slices(orc, B, ctx, n, diags, drop):
+    """Matrices on a few diagonals take the diagonal-slice copy (two rows per
+    lane, 16-byte value and iterate loads, columns clamped at both ends of the
+    matrix, rows past n in the last 128-row slice): the product and Richardson
+    iterates equal the oracle's bit for bit, and those of the row-pattern copy
+    (SILU_ROWPAT) and of the CSR stream; with 30 diagonals (above the 24 whose
+    epilogue operands are loaded early), and with entries missing from a
+    diagonal (zeros in its slots; too many and the copy is not used)."""
+    say("diagonal slices", n, len(diags), drop)
+    L = _banded(n, diags, seed=n + len(diags))
+    Ld = B.Csr.from_host(L)
+    x = W.rhs(n, 3)
+    want = orc.spmv(L, x)
+    for kernel in (None, "rowpat", "stream"):
+        np.testing.assert_array_equal(host(ctx.spmv(Ld, dev(x), kernel=kernel)), want)
+    if all(d < 0 for d in diags):  # strictly lower: Richardson iterates on it
+        for m in (1, 2, 5):
+            ref = orc.richardson(L, x, m)
+            for kernel in (None, "rowpat"):
+                np.testing.assert_array_equal(host(ctx.trisolve_iter(Ld, dev(x), m, kernel=kernel)), ref)
