@@ -77,6 +77,13 @@ struct TMixU {
     using OT = float;
 };
 
+// Workgroups are dealt round-robin over the 8 XCDs; this remap gives each XCD
+// one contiguous slab of the grid's blocks, so neighbouring blocks share an
+// L2.  Kept where it measured faster (the row-block kernel on the relabeled
+// random operator: 1.54 against 1.63 ms per application, and the coded sliced
+// and vector kernels, not re-measured); the row-pattern, diagonal-slice,
+// CSR-stream and batched kernels take blocks in launch order, which measured
+// 2-10 % faster for them.
 __device__ __forceinline__ int xcd_slab_block(int b, int G)
 {
     const int q = G >> 3, r = G & 7, xcd = b & 7, k = b >> 3;
@@ -235,21 +242,20 @@ __device__ __forceinline__ double stream_rows(const SweepArgs &a, int blk, const
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_stream(SweepArgs a)
 {
-    stream_rows<T, BLOCK, RPB, CAP, IDX32>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), nullptr, 0, nullptr, 0);
+    stream_rows<T, BLOCK, RPB, CAP, IDX32>(a, (int)blockIdx.x, nullptr, 0, nullptr, 0);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_stream16(SweepArgs a, const uint16_t *__restrict__ off16, int shift)
 {
-    stream_rows<T, BLOCK, RPB, CAP, OFF16>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), off16, shift, nullptr,
-                                           0);
+    stream_rows<T, BLOCK, RPB, CAP, OFF16>(a, (int)blockIdx.x, off16, shift, nullptr, 0);
 }
 
 template <class T, int BLOCK, int RPB, int CAP>
 __global__ void __launch_bounds__(BLOCK) k_sweep_win(SweepArgs a, const uint16_t *__restrict__ code,
                                                      const int32_t *__restrict__ wo, int lw)
 {
-    stream_rows<T, BLOCK, RPB, CAP, WIN>(a, xcd_slab_block((int)blockIdx.x, (int)gridDim.x), code, 0, wo, lw);
+    stream_rows<T, BLOCK, RPB, CAP, WIN>(a, (int)blockIdx.x, code, 0, wo, lw);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,17 +605,17 @@ __device__ __forceinline__ double sliced_wave_pat(const SweepArgs &a, const Slic
     return live ? (double)t : 0.0;
 }
 
-// One slice per wave.  The pattern table is small (at most PAT_MAX_ENTRIES
-// offsets) and stays in the caches, so each lane reads its row's offsets from
-// it directly, one 16-byte load per group of four slots: no copy to LDS and no
+// One slice per wave, slices in launch order (the XCD slab remap measured 3 %
+// slower here).  The pattern table is small (at most PAT_MAX_ENTRIES offsets)
+// and stays in the caches, so each lane reads its row's offsets from it
+// directly, one 16-byte load per group of four slots: no copy to LDS and no
 // barrier ahead of the value loads.  (Measured on the n = 8M 27-point factors:
 // 295 us per sweep against 300 us with the table staged in LDS for four
 // rounds of slices per workgroup, and 34.8 against 35.6 us at n = 2M.)
 template <class T, int WPB, int GM>
 __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced_pat(SweepArgs a, SlicedView s)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * WPB +
-                                                    ((int)threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * WPB + ((int)threadIdx.x >> 6));
     if (wave >= s.nslice) return;
     const int lane = (int)threadIdx.x & 63;
     sliced_wave_pat<T, GM>(a, s, wave, s.sk[wave], s.sptr[wave], s.ptab + (int)s.pid[wave * 64 + lane] * s.kp);
@@ -711,9 +717,15 @@ __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView 
         }
     }
     RT rh0 = (RT)0, rh1 = (RT)0;
-    if (a.epi != EPI_SPMV) {
-        if (ra < n) rh0 = ((const RT *)a.rhs)[ra];
-        if (ra + 1 < n) rh1 = ((const RT *)a.rhs)[ra + 1];
+    if (a.epi != EPI_SPMV) { // the lane's two rows with one load
+        if (ra + 1 < n) {
+            f64x2 t2;
+            __builtin_memcpy(&t2, (const double *)a.rhs + ra, 16);
+            rh0 = t2.x;
+            rh1 = t2.y;
+        } else if (ra < n) {
+            rh0 = ((const RT *)a.rhs)[ra];
+        }
     }
     double aux0 = 0.0, aux1 = 0.0, aux20 = 0.0, aux21 = 0.0, cf0 = 1.0, cf1 = 1.0;
     if constexpr (U <= 24) {
@@ -730,24 +742,39 @@ __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView 
         diag_operands(a, ra, aux0, aux20, cf0);
         diag_operands(a, ra + 1, aux1, aux21, cf1);
     }
-    if (ra < n) epilogue_pre<T>(a, ra, a.epi == EPI_SPMV ? sa : (AT)rh0 - sa, aux0, aux20, cf0);
-    if (ra + 1 < n) epilogue_pre<T>(a, ra + 1, a.epi == EPI_SPMV ? sb : (AT)rh1 - sb, aux1, aux21, cf1);
+    using IT = typename T::IT;
+    const AT ta = a.epi == EPI_SPMV ? sa : (AT)rh0 - sa, tb = a.epi == EPI_SPMV ? sb : (AT)rh1 - sb;
+    if (ra + 1 < n && sizeof(typename T::OT) == 8 &&
+        (a.epi == EPI_STORE || a.epi == EPI_SPMV || a.epi == EPI_STORE_SPLIT)) {
+        // the stores of epilogue_pre for both rows, each one store
+        f64x2 o2;
+        o2.x = (double)(IT)ta;
+        o2.y = (double)(IT)tb;
+        __builtin_memcpy((double *)a.out + ra, &o2, 16);
+        if (a.epi == EPI_STORE_SPLIT) {
+            const float f2[2] = {(float)(IT)ta, (float)(IT)tb};
+            __builtin_memcpy(a.out32 + ra, f2, 8);
+        }
+    } else {
+        if (ra < n) epilogue_pre<T>(a, ra, ta, aux0, aux20, cf0);
+        if (ra + 1 < n) epilogue_pre<T>(a, ra + 1, tb, aux1, aux21, cf1);
+    }
 }
 
+// Slices in launch order (the XCD slab remap of the other sweeps measured 2 %
+// slower for this kernel).
 template <class T, int U>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_sweep_diag_wide(SweepArgs a,
                                                                                                       SlicedView s)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * 4 +
-                                                    ((int)threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
     if (wave < s.nslice) diag_slice<T, U>(a, s, wave);
 }
 
 template <class T, int U>
 __global__ void __launch_bounds__(256) k_sweep_diag(SweepArgs a, SlicedView s)
 {
-    const int wave = __builtin_amdgcn_readfirstlane(xcd_slab_block((int)blockIdx.x, (int)gridDim.x) * 4 +
-                                                    ((int)threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + ((int)threadIdx.x >> 6));
     if (wave < s.nslice) diag_slice<T, U>(a, s, wave);
 }
 
@@ -909,7 +936,7 @@ template <class T>
 __global__ void __launch_bounds__(256) k_sweep_batch(const SweepArgs *__restrict__ ops,
                                                      const int32_t *__restrict__ first, int nops)
 {
-    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int b = (int)blockIdx.x;
     const int i = find_op(first, nops, b);
     batch_tile<T>(ops[i], b - first[i]);
 }
@@ -927,7 +954,7 @@ struct BatchArgsN {
 template <class T, int CAP>
 __global__ void __launch_bounds__(256) k_sweep_batch_args(BatchArgsN<CAP> ba)
 {
-    const int b = xcd_slab_block((int)blockIdx.x, (int)gridDim.x);
+    const int b = (int)blockIdx.x;
     const int i = find_op(ba.first, ba.nops, b);
     batch_tile<T>(ba.op[i], b - ba.first[i]);
 }
