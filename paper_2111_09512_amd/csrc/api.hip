@@ -506,7 +506,7 @@ bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<i
 // Diagonal slices of N (code 16) when every row lies on at most DIAG_MAX
 // diagonals col - row and their slots (one per diagonal for every row, in
 // 128-row slices) exceed the entries by at most 1/16: *built is then true.
-int build_diag(silu_ctx *c, const silu_csr *N, const double *val, Sliced &S, bool *built)
+int build_diag(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, Sliced &S, bool *built)
 {
     *built = false;
     const int n = (int)N->n_rows;
@@ -540,13 +540,13 @@ int build_diag(silu_ctx *c, const silu_csr *N, const double *val, Sliced &S, boo
     const int64_t slots = (int64_t)nslice * u * 128;
     if (u > DIAG_MAX || slots > N->nnz + N->nnz / 16 + 128 * (int64_t)u || slots > INT32_MAX) return SILU_OK;
     int32_t *d_dmap = nullptr;
-    e = hipMalloc(&S.val, (size_t)slots * 8);
+    e = hipMalloc(&S.val, (size_t)slots * (size_t)vbytes);
     if (e == hipSuccess) e = hipMalloc(&S.dtab, (size_t)u * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(S.dtab, dtab.data(), (size_t)u * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMalloc(&d_dmap, dmap.size() * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(d_dmap, dmap.data(), dmap.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = launch_fill_diag(n, nslice, u, N->row_ptr, N->col_idx, val, d_dmap, (int)dlo, (double *)S.val, c->stream);
+        e = launch_fill_diag(n, nslice, u, N->row_ptr, N->col_idx, val, vbytes, d_dmap, (int)dlo, S.val, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream); // the host tables go out of scope
     (void)hipFree(d_dmap);
     if (e != hipSuccess) {
@@ -566,7 +566,7 @@ int build_diag(silu_ctx *c, const silu_csr *N, const double *val, Sliced &S, boo
 }
 
 // Build (once) the sliced-ELL copy of N with values `val` of `vbytes` bytes.
-// code_min: -1 allows diagonal slices (FP64 values), 0 the row-pattern table,
+// code_min: -1 allows diagonal slices, 0 the row-pattern table,
 // 1 the diagonal table, 2 starts at 16-bit offsets, 4 uses columns.  *out->ok
 // is false when the matrix has no entries or the copy would not fit 32-bit
 // slot indices (the caller then streams the CSR).
@@ -576,9 +576,9 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     const int nslice = (n + 63) / 64;
     auto store = [&]() { return SILU_OK; }; // S.ok stays false unless the copy was built
     if (N->nnz <= 0 || n <= 0) return store();
-    if (code_min < 0 && vbytes == 8) {
+    if (code_min < 0) {
         bool built = false;
-        const int st = build_diag(c, N, (const double *)val, S, &built);
+        const int st = build_diag(c, N, val, vbytes, S, &built);
         if (st || built) return st;
     }
     // per-slice K and mask bit, then slot offsets
@@ -759,8 +759,8 @@ int sweep(silu_ctx *c, Prec p, SweepGeom g, const silu_csr *N, const void *val, 
 {
     double sliced_bytes = -1.0;
     bool fell_back = false; // the default sliced layout did not apply
-    // diagonal slices hold FP64 values and add no unscaled-variant diagonal term
-    if (g.slice_code_min < 0 && (dshift || !(p == Prec::F64 || p == Prec::MIX_RES))) g.slice_code_min = 0;
+    // diagonal slices add no unscaled-variant diagonal term
+    if (g.slice_code_min < 0 && dshift) g.slice_code_min = 0;
     if (g.kind == SweepKernel::SLICED) {
         const int vbytes = (p == Prec::F64 || p == Prec::MIX_RES) ? 8 : 4;
         Sliced *S = nullptr;
@@ -1446,7 +1446,7 @@ static int smooth_plain(silu_ctx *c, const silu_csr *A, const silu_factors *F, c
         bool split = false;
         if (mixed && m_L >= 2 && gL.kind == SweepKernel::SLICED) {
             Sliced *SL = nullptr;
-            if ((st = get_sliced(c, &F->Ls, Lval, 4, std::max(gL.slice_code_min, 0), &SL))) return st;
+            if ((st = get_sliced(c, &F->Ls, Lval, 4, gL.slice_code_min, &SL))) return st;
             split = SL->ok;
         }
         const void *rr = r, *y1 = nullptr;

@@ -57,7 +57,7 @@ struct SlicedView {
     const uint8_t *pid = nullptr;  // [nslice * 64] pattern of each row
     const int32_t *ptab = nullptr; // [npat * kp]
     int npat = 0, kp = 0;
-    // code 16 (diagonal slices, FP64 values only): every row of the matrix lies
+    // code 16 (diagonal slices, FP64 or FP32 values): every row of the matrix lies
     // on the ndiag <= DIAG_MAX diagonals dtab[] (ascending); nslice slices of
     // 128 rows, slot k of row r holding its entry on diagonal dtab[k] (0 where
     // it has none) at val[diag_slot(r, k, ndiag)]
@@ -182,8 +182,8 @@ hipError_t launch_gs_fill(int n, const int32_t *rp, const int32_t *col, const do
 hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, hipStream_t s);
 // Diagonal slices (code 16): zero the copy, then place every entry at its
 // row's slot on diagonal dmap[col - row - lo].
-hipError_t launch_fill_diag(int n, int nslice, int u, const int32_t *rp, const int32_t *col, const double *val,
-                            const int32_t *dmap, int lo, double *sval, hipStream_t s);
+hipError_t launch_fill_diag(int n, int nslice, int u, const int32_t *rp, const int32_t *col, const void *val,
+                            int val_bytes, const int32_t *dmap, int lo, void *sval, hipStream_t s);
 hipError_t launch_fill_sliced(int n, int nslice, const int32_t *rp, const int32_t *col, const void *val, int val_bytes,
                               const int32_t *sptr, const int32_t *sk, int code, const int32_t *dmap, int lo,
                               void *sval, void *scode, hipStream_t s);

@@ -429,9 +429,10 @@ __global__ void __launch_bounds__(256) k_fill_sliced(int n, int nslice, const in
 
 // Diagonal slices: one thread per row places the row's entries (the copy
 // was zeroed first, so slots of diagonals the row lacks hold 0).
+template <typename VT>
 __global__ void __launch_bounds__(256) k_fill_diag(int n, int u, const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                   const int32_t *__restrict__ dmap, int lo, double *__restrict__ sval)
+                                                   const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                   const int32_t *__restrict__ dmap, int lo, VT *__restrict__ sval)
 {
     const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (r >= n) return;
@@ -633,15 +634,21 @@ hipError_t launch_slice_meta(int n, int nslice, const int32_t *rp, int32_t *sk, 
     return hipGetLastError();
 }
 
-hipError_t launch_fill_diag(int n, int nslice, int u, const int32_t *rp, const int32_t *col, const double *val,
-                            const int32_t *dmap, int lo, double *sval, hipStream_t s)
+hipError_t launch_fill_diag(int n, int nslice, int u, const int32_t *rp, const int32_t *col, const void *val,
+                            int val_bytes, const int32_t *dmap, int lo, void *sval, hipStream_t s)
 {
     if (nslice <= 0 || u <= 0) return hipSuccess;
     const int64_t slots = (int64_t)nslice * u * 128;
     if (slots > INT32_MAX) return hipErrorInvalidValue; // the caller keeps copies below 2^31 slots
-    const hipError_t e = launch_fill((int)slots, sval, 0.0, nullptr, 0.0, s);
+    // zeroed as doubles: slots is a multiple of 128, so FP32 copies are whole doubles too
+    const hipError_t e = launch_fill((int)(slots * val_bytes / 8), (double *)sval, 0.0, nullptr, 0.0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_diag, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, u, rp, col, val, dmap, lo, sval);
+    if (val_bytes == 8)
+        hipLaunchKernelGGL(k_fill_diag<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, u, rp, col,
+                           (const double *)val, dmap, lo, (double *)sval);
+    else
+        hipLaunchKernelGGL(k_fill_diag<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, u, rp, col,
+                           (const float *)val, dmap, lo, (float *)sval);
     return hipGetLastError();
 }
 

@@ -274,6 +274,7 @@ __global__ void __launch_bounds__(BLOCK) k_sweep_win(SweepArgs a, const uint16_t
 // ---------------------------------------------------------------------------
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
@@ -645,23 +646,24 @@ hipError_t go_pat(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 // holds its entry on diagonal d_k (0 where the row has none) and the rows of
 // a slice share their slots' column offsets: no per-slot code, no per-row
 // pattern, and neighbouring rows gather neighbouring iterate values.  Each
-// lane owns two consecutive rows of a 128-row slice: one 16-byte load brings
-// both rows' values of a slot, one 16-byte load both rows' iterate values on
-// that slot's diagonal -- half the iterate loads of one row per lane, whose
-// count (not their bytes) bounds the row-pattern sweeps.  Every value and
-// iterate load of the slice is issued before the first is waited for (the
-// kernel is compiled for two waves per SIMD where the U slots need the
-// registers), the rhs after them; so are the other epilogue operands, except
-// above 24 slots, where their registers would not fit beside the slots' and
-// they are loaded once the sums are done.  Each row's products are
-// summed in ascending diagonal (= column) order (no unscaled-variant
-// diagonal term: such sweeps take the row-pattern copy); a slot the row lacks adds
-// 0 * x = +-0 to a sum that started at +0.0 and so is never -0.0, which
-// leaves it unchanged: finite results are the row-sum of the oracle bit for
-// bit.  In the slices at either end of the matrix the iterate pair is loaded
-// at the column clamped into [0, n - 2]: a column outside the matrix only
-// occurs on a slot whose value is 0, and the clamped pair still gives the
-// other row of the lane its own value.
+// lane owns two consecutive rows of a 128-row slice: one load (16 bytes in
+// FP64, 8 in FP32) brings both rows' values of a slot, one load both rows'
+// iterate values on that slot's diagonal -- half the iterate loads of one row
+// per lane, whose count (not their bytes) bounds the row-pattern sweeps.
+// Every value and iterate load of the slice is issued before the first is
+// waited for (the FP64 kernel is compiled for two waves per SIMD where the U
+// slots need the registers), the rhs after them; so are the other epilogue
+// operands, except above 24 slots, where their registers would not fit
+// beside the slots' and they are loaded once the sums are done.  Each row's
+// products are summed in ascending diagonal (= column) order in the
+// precision's accumulator (no unscaled-variant diagonal term: such sweeps
+// take the row-pattern copy); a slot the row lacks adds 0 * x = +-0 to a sum
+// that started at +0 and so is never -0, which leaves it unchanged: finite
+// results are the row sums of the oracle (and of its FP32-inner emulation)
+// bit for bit.  In the slices at either end of the matrix the iterate pair
+// is loaded at the column clamped into [0, n - 2]: a column outside the
+// matrix only occurs on a slot whose value is 0, and the clamped pair still
+// gives the other row of the lane its own value.
 // A row's epilogue operands (those of epilogue_pre), for rows that exist.
 __device__ __forceinline__ void diag_operands(const SweepArgs &a, int row, double &aux, double &aux2, double &cf)
 {
@@ -672,13 +674,38 @@ __device__ __forceinline__ void diag_operands(const SweepArgs &a, int row, doubl
     if (a.dcol && (a.epi == EPI_UPDATE || a.epi == EPI_SCALE_UPDATE)) cf = a.dcol[row];
 }
 
+// Two consecutive elements (the lane's two rows) as one vector, and their
+// load from a buffer resource: 16 bytes for FP64, 8 for FP32.
+template <class E>
+struct Pair2 {
+    using type = f64x2;
+};
+template <>
+struct Pair2<float> {
+    using type = f32x2;
+};
+// AUX: the load's cache policy bits (2: non-temporal).
+template <class E, int AUX>
+__device__ __forceinline__ typename Pair2<E>::type buf_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff)
+{
+    if constexpr (sizeof(E) == 8)
+        return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+    else
+        return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+}
+
 template <class T, int U>
 __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView &s, int wave)
 {
+    using VT = typename T::VT;
     using XT = typename T::XT;
     using RT = typename T::RT;
     using AT = typename T::AT;
-    static_assert(sizeof(typename T::VT) == 8 && sizeof(XT) == 8, "FP64 values and iterates");
+    using IT = typename T::IT;
+    using OT = typename T::OT;
+    using VP = typename Pair2<VT>::type;
+    using XP = typename Pair2<XT>::type;
+    constexpr int vb = (int)sizeof(VT), xb = (int)sizeof(XT);
     const int n = a.n;
     const int lane = (int)threadIdx.x & 63;
     const int ra = wave * 128 + 2 * lane;
@@ -686,32 +713,31 @@ __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView 
     int d[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) d[k] = __builtin_amdgcn_readfirstlane(s.dtab[k]);
-    f64x2 v[U], xv[U];
+    VP v[U];
+    XP xv[U];
     const int r0 = wave * 128;
     if (r0 + d[0] >= 0 && r0 + 127 + d[U - 1] <= n - 1) { // every column inside the matrix
         // buffer loads: the slice's values and its iterate window as two
         // resources, the slot's offset in a scalar register, the lane's in one
         // vector register shared by every load (no address registers per load)
         const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)((const f64x2 *)s.val + (int64_t)wave * U * 64), (short)0, U * 1024, 0x00020000);
+            (void *)((const VT *)s.val + (int64_t)wave * U * 128), (short)0, U * 128 * vb, 0x00020000);
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(xin + (r0 + d[0])), (short)0, (128 + d[U - 1] - d[0]) * 8, 0x00020000);
+            (void *)(xin + (r0 + d[0])), (short)0, (128 + d[U - 1] - d[0]) * xb, 0x00020000);
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            v[k] = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rv, lane * 16, k * 1024, 2));
+        for (int k = 0; k < U; ++k) v[k] = buf_pair<VT, 2>(rv, lane * 2 * vb, k * 128 * vb);
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            xv[k] = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rx, lane * 16, (d[k] - d[0]) * 8, 0));
+        for (int k = 0; k < U; ++k) xv[k] = buf_pair<XT, 0>(rx, lane * 2 * xb, (d[k] - d[0]) * xb);
     } else { // a slice at either end of the matrix
-        const f64x2 *pv = (const f64x2 *)s.val + (int64_t)wave * U * 64 + lane;
+        const VP *pv = (const VP *)((const VT *)s.val + (int64_t)wave * U * 128) + lane;
 #pragma unroll
         for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(pv + 64 * k);
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int raw = ra + d[k];
             const int idx = min(max(raw, 0), n - 2);
-            f64x2 t;
-            __builtin_memcpy(&t, xin + idx, 16);
+            XP t;
+            __builtin_memcpy(&t, xin + idx, 2 * xb);
             xv[k].x = raw > n - 2 ? t.y : t.x;
             xv[k].y = raw < 0 ? t.x : t.y;
         }
@@ -719,10 +745,10 @@ __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView 
     RT rh0 = (RT)0, rh1 = (RT)0;
     if (a.epi != EPI_SPMV) { // the lane's two rows with one load
         if (ra + 1 < n) {
-            f64x2 t2;
-            __builtin_memcpy(&t2, (const double *)a.rhs + ra, 16);
-            rh0 = t2.x;
-            rh1 = t2.y;
+            RT t2[2];
+            __builtin_memcpy(t2, (const RT *)a.rhs + ra, 2 * sizeof(RT));
+            rh0 = t2[0];
+            rh1 = t2[1];
         } else if (ra < n) {
             rh0 = ((const RT *)a.rhs)[ra];
         }
@@ -742,15 +768,11 @@ __device__ __forceinline__ void diag_slice(const SweepArgs &a, const SlicedView 
         diag_operands(a, ra, aux0, aux20, cf0);
         diag_operands(a, ra + 1, aux1, aux21, cf1);
     }
-    using IT = typename T::IT;
     const AT ta = a.epi == EPI_SPMV ? sa : (AT)rh0 - sa, tb = a.epi == EPI_SPMV ? sb : (AT)rh1 - sb;
-    if (ra + 1 < n && sizeof(typename T::OT) == 8 &&
-        (a.epi == EPI_STORE || a.epi == EPI_SPMV || a.epi == EPI_STORE_SPLIT)) {
+    if (ra + 1 < n && (a.epi == EPI_STORE || a.epi == EPI_SPMV || a.epi == EPI_STORE_SPLIT)) {
         // the stores of epilogue_pre for both rows, each one store
-        f64x2 o2;
-        o2.x = (double)(IT)ta;
-        o2.y = (double)(IT)tb;
-        __builtin_memcpy((double *)a.out + ra, &o2, 16);
+        const OT o2[2] = {(OT)(IT)ta, (OT)(IT)tb};
+        __builtin_memcpy((OT *)a.out + ra, o2, 2 * sizeof(OT));
         if (a.epi == EPI_STORE_SPLIT) {
             const float f2[2] = {(float)(IT)ta, (float)(IT)tb};
             __builtin_memcpy(a.out32 + ra, f2, 8);
@@ -786,7 +808,7 @@ template <class T, int U>
 hipError_t go_diag_u(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 {
     const dim3 grid((g.sl.nslice + 3) / 4), block(256);
-    if (U > 12 && U <= 28)
+    if constexpr (sizeof(typename T::VT) + sizeof(typename T::XT) == 16 && U > 12 && U <= 28)
         hipLaunchKernelGGL((k_sweep_diag_wide<T, U>), grid, block, 0, s, a, g.sl);
     else
         hipLaunchKernelGGL((k_sweep_diag<T, U>), grid, block, 0, s, a, g.sl);
@@ -1204,13 +1226,9 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
         if (g.sl.nslice <= 0) return hipErrorInvalidValue;
         const dim3 grid((g.sl.nslice + WPB - 1) / WPB), block(64 * WPB);
         if (g.sl.code == 16) {
-            if constexpr (sizeof(typename T::VT) == 8 && sizeof(typename T::XT) == 8) {
-                if (g.sl.ndiag < 1 || g.sl.ndiag > DIAG_MAX || a.n < 2 || (int64_t)g.sl.nslice * 128 < a.n ||
-                    a.dshift)
-                    return hipErrorInvalidValue;
-                return go_diag<T>(g, a, s);
-            }
-            return hipErrorInvalidValue; // FP64 values and iterates only
+            if (g.sl.ndiag < 1 || g.sl.ndiag > DIAG_MAX || a.n < 2 || (int64_t)g.sl.nslice * 128 < a.n || a.dshift)
+                return hipErrorInvalidValue;
+            return go_diag<T>(g, a, s);
         }
         if (g.sl.code == 8) {
             if (g.sl.npat < 1 || g.sl.kp < 4 || (g.sl.kp & 3) || g.sl.npat * g.sl.kp > PAT_MAX_ENTRIES ||
