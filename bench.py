@@ -348,7 +348,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="aniso200", choices=sorted(WORKLOADS))
     ap.add_argument("--N", type=int, default=None, help="override grid side (testing only)")
-    ap.add_argument("--kernel", default=None, choices=[None, "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
+    ap.add_argument("--kernel", default=None, choices=[None, "rowpat", "sliced8", "sliced_loop", "sliced16", "sliced32", "stream", "win", "stream16", "stream32", "vector", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
