@@ -1119,7 +1119,7 @@ int make_owned_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbyte
     if (vbytes != 8 && vbytes != 4) return SILU_ERR_ARG;
     Sliced *S = new (std::nothrow) Sliced();
     if (!S) return SILU_ERR_NOMEM;
-    const int st = build_sliced(c, N, val, vbytes, 1, *S);
+    const int st = build_sliced(c, N, val, vbytes, 0, *S);
     if (st || !S->ok) {
         free_sliced(*S);
         delete S;

@@ -837,7 +837,11 @@ __global__ void __launch_bounds__(64 * WPB) k_sweep_sliced(SweepArgs a, SlicedVi
 
 // One 256-row tile of a batched op, run by a workgroup of 256 lanes: as four
 // 64-row slices of the op's sliced copy when it has one (a.sv), else as the
-// CSR stream.  Either way each row is summed in ascending column order, so
+// CSR stream.  Row-pattern and diagonal-table slices of at most two groups
+// take the prefetched bodies, larger ones their loops: with a bound of two
+// the kernel keeps the loop form's 76 registers, where bounds of four and
+// eight (122 and 132 registers) cost 20 and 32 % of the batched saturation
+// rate on 7-point matrices.  Either way each row is summed in ascending column order, so
 // the result is the single-request one bit for bit.
 // A solve request's op is skipped once its request has stopped (the flag was
 // set by an earlier launch); a check op then reduces r_i^2 (and b_i^2 on the
@@ -855,10 +859,16 @@ __device__ __forceinline__ void batch_tile(const SweepArgs &a, int tile)
         __shared__ int32_t dtab[256];
         const SlicedView s = *a.sv;
         const int wave = tile * 4 + ((int)threadIdx.x >> 6);
-        if (s.code == 1) {
+        if (s.code == 8) {
+            const int wc = min(__builtin_amdgcn_readfirstlane(wave), s.nslice - 1);
+            const int lane = (int)threadIdx.x & 63;
+            t = wave < s.nslice ? sliced_wave_pat<T, 2>(a, s, wc, s.sk[wc], s.sptr[wc],
+                                                         s.ptab + (int)s.pid[wc * 64 + lane] * s.kp)
+                                : 0.0;
+        } else if (s.code == 1) {
             for (int k = (int)threadIdx.x; k < s.ndiag; k += 256) dtab[k] = s.dtab[k];
             __syncthreads();
-            t = sliced_wave<T, 1, 2>(a, s, wave, dtab);
+            t = sliced_wave_pf<T, 2>(a, s, wave, dtab);
         } else if (s.code == 2) {
             t = sliced_wave<T, 2, 2>(a, s, wave, dtab);
         } else {
