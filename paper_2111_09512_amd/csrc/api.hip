@@ -63,6 +63,7 @@ struct Sliced {
     SlicedView v;
     int32_t *sptr = nullptr, *sk = nullptr, *dtab = nullptr, *ptab = nullptr;
     uint8_t *pid = nullptr;
+    uint16_t *ltab = nullptr;
     void *val = nullptr, *codes = nullptr;
     int64_t masked_rows = 0;
     bool ok = false;
@@ -110,6 +111,7 @@ void free_sliced(Sliced &S)
     (void)hipFree(S.codes);
     (void)hipFree(S.ptab);
     (void)hipFree(S.pid);
+    (void)hipFree(S.ltab);
     S = Sliced();
 }
 
@@ -503,6 +505,36 @@ bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<i
     return true;
 }
 
+// Iterate windows of a pattern table: its distinct offsets in ascending
+// order, cut into runs that start at an even offset w and reach at most w +
+// 64, so that lane l of a slice starting at row r0 finds every slot of row
+// r0 + l in x[r0 + w .. r0 + w + 127] for the run holding the slot's offset.
+// ltab holds each pattern's kp slots as LDS elements in rows of kl = kp
+// rounded up to 8 (the padding 0).  False when more than PAT_WIN_MAX runs are
+// needed.
+bool pattern_windows(const std::vector<int32_t> &ptab, int kp, std::vector<int32_t> &wst,
+                     std::vector<uint16_t> &ltab)
+{
+    std::vector<int32_t> offs(ptab);
+    std::sort(offs.begin(), offs.end());
+    offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+    wst.clear();
+    for (int32_t o : offs) {
+        if (!wst.empty() && (int64_t)o - wst.back() <= 64) continue;
+        if ((int)wst.size() == PAT_WIN_MAX) return false;
+        wst.push_back((int32_t)((int64_t)o - ((int64_t)o & 1))); // rounded down to even
+    }
+    const size_t kl = (size_t)(kp + 7) / 8 * 8, npat = ptab.size() / (size_t)kp;
+    ltab.assign(npat * kl, 0);
+    for (size_t p = 0; p < npat; p++)
+        for (size_t k = 0; k < (size_t)kp; k++) {
+            const int32_t o = ptab[p * (size_t)kp + k];
+            const int c = (int)(std::upper_bound(wst.begin(), wst.end(), o) - wst.begin()) - 1;
+            ltab[p * kl + k] = (uint16_t)(128 * c + (o - wst[(size_t)c])); // in [128 c, 128 c + 64]
+        }
+    return true;
+}
+
 // Diagonal slices of N (code 16) when every row lies on at most DIAG_MAX
 // diagonals col - row and their slots (one per diagonal for every row, in
 // 128-row slices) exceed the entries by at most 1/16: *built is then true.
@@ -687,12 +719,21 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     if (e == hipSuccess) e = hipMemcpyAsync(S.sptr, sptr.data(), (size_t)nslice * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMalloc(&S.val, (size_t)slots * (size_t)vbytes);
     if (e == hipSuccess && code != 8) e = hipMalloc(&S.codes, (size_t)slots * (size_t)code);
+    std::vector<int32_t> wst;
+    std::vector<uint16_t> ltab;
     if (e == hipSuccess && code == 8) {
         e = hipMalloc(&S.ptab, ptab.size() * 4);
         if (e == hipSuccess)
             e = hipMemcpyAsync(S.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipMalloc(&S.pid, pid.size());
         if (e == hipSuccess) e = hipMemcpyAsync(S.pid, pid.data(), pid.size(), hipMemcpyHostToDevice, c->stream);
+        // windows for FP64 values only: the FP32 sweeps' 4-byte gathers are
+        // cheaper than the windows' LDS round trip (4-5 % slower with them)
+        if (e == hipSuccess && vbytes == 8 && pattern_windows(ptab, 4 * gmax, wst, ltab)) {
+            e = hipMalloc(&S.ltab, ltab.size() * 2);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(S.ltab, ltab.data(), ltab.size() * 2, hipMemcpyHostToDevice, c->stream);
+        }
     }
     if (e == hipSuccess && code == 1) {
         e = hipMalloc(&S.dtab, dtab.size() * 4);
@@ -726,6 +767,13 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     S.v.ptab = S.ptab;
     S.v.npat = npat;
     S.v.kp = code == 8 ? 4 * gmax : 0;
+    if (S.ltab) {
+        S.v.nwin = (int)wst.size();
+        S.v.wspan = wst.back() + 128 - wst.front();
+        S.v.kl = (4 * gmax + 7) / 8 * 8;
+        std::copy(wst.begin(), wst.end(), S.v.wst);
+        S.v.ltab = S.ltab;
+    }
     S.ok = true;
     return store();
 }

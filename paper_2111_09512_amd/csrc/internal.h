@@ -39,6 +39,9 @@ enum class SweepKernel : int { STREAM = 0, VECTOR = 1, BLOCKED = 2, SLICED = 3 }
 // code -- 1 (index into the table of distinct diagonals col - row), 2
 // (slice-relative offset col - 64 s - shift) or 4 (the column); 8: row
 // patterns (below); 16: diagonal slices (below).
+// Iterate windows of the row-pattern sweep: at most this many per matrix.
+constexpr int PAT_WIN_MAX = 12;
+
 struct SlicedView {
     int nslice = 0;
     int code = 4;
@@ -57,6 +60,16 @@ struct SlicedView {
     const uint8_t *pid = nullptr;  // [nslice * 64] pattern of each row
     const int32_t *ptab = nullptr; // [npat * kp]
     int npat = 0, kp = 0;
+    // iterate windows of code 8 with FP64 values (nwin = 0: none): the
+    // table's offsets fall in nwin runs, run c covering offsets [wst[c],
+    // wst[c] + 64] (wst[c] even, ascending), so the 64 rows of a slice starting
+    // at row r0 gather only from x[r0 + wst[c] .. r0 + wst[c] + 127];
+    // ltab[pid * kl + k] (k < kp; kl = kp rounded up to 8, for 16-byte
+    // loads) is slot k's element in the wave's copy of those windows,
+    // 128 c + ptab[pid * kp + k] - wst[c]
+    int nwin = 0, wspan = 0, kl = 0; // wspan = wst[nwin - 1] + 128 - wst[0]
+    int32_t wst[PAT_WIN_MAX] = {};
+    const uint16_t *ltab = nullptr; // [npat * kl]
     // code 16 (diagonal slices, FP64 or FP32 values): every row of the matrix lies
     // on the ndiag <= DIAG_MAX diagonals dtab[] (ascending); nslice slices of
     // 128 rows, slot k of row r holding its entry on diagonal dtab[k] (0 where

@@ -619,3 +619,43 @@ def test_diagonal_slices(orc, B, ctx, n, diags, drop):
             ref = orc.richardson(L, x, m)
             for kernel in (None, "rowpat"):
                 np.testing.assert_array_equal(host(ctx.trisolve_iter(Ld, dev(x), m, kernel=kernel)), ref)
+
+
+def _runs(n, starts, width, seed, drop=0.0):
+    """n x n matrix on runs of `width` consecutive diagonals beginning at each
+    offset in `starts` (entries outside the matrix dropped)."""
+    diags = sorted({s + j for s in starts for j in range(width)})
+    return _banded(n, diags, seed, drop), diags
+
+
+@pytest.mark.parametrize("n", [3001, 64 * 70 + 17])
+@pytest.mark.parametrize("starts,width,drop", [
+    ((-1,), 1, 0.0),                                      # one window
+    (tuple(-200 * k - 1 for k in range(1, 13)), 2, 0.0),  # twelve (the most), odd first offsets
+    (tuple(-200 * k for k in range(1, 14)), 1, 0.0),      # thirteen: no windows, the gather body
+    ((-300,), 65, 0.0),                                   # offsets w .. w + 64 (w even): one window, read to its end
+    ((-301,), 64, 0.0),                                   # from an odd offset, rounded down: still one
+    ((-300,), 66, 0.0),                                   # one offset more: two windows
+    ((-700, -3), 3, 0.03),                                # missing entries: several row patterns
+    ((-150, 1, 140), 3, 0.0),                             # both sides of the diagonal
+])
+def test_pattern_windows(orc, B, ctx, n, starts, width, drop):
+    """Row-pattern copies whose offsets fall in runs: the windowed sweep (each
+    slice's iterate windows staged in LDS, one load per window, slots read at
+    lane + index) covers the slices whose windows lie inside the matrix, the
+    gather body the slices at either end, those with an empty row (row 0 of a
+    strictly lower matrix) and the ragged last one; product and Richardson
+    iterates equal the oracle's bit for bit, for 1 to 12 windows and for 13
+    (none kept), with runs reaching the last entry of a window from even and
+    odd starts."""
+    say("pattern windows", n, len(starts), width, drop)
+    L, diags = _runs(n, starts, width, seed=n + width, drop=drop)
+    Ld = B.Csr.from_host(L)
+    x = W.rhs(n, 5)
+    want = orc.spmv(L, x)
+    for kernel in (None, "rowpat"):
+        np.testing.assert_array_equal(host(ctx.spmv(Ld, dev(x), kernel=kernel)), want)
+    if all(d < 0 for d in diags):
+        for m in (1, 3):
+            ref = orc.richardson(L, x, m)
+            np.testing.assert_array_equal(host(ctx.trisolve_iter(Ld, dev(x), m, kernel="rowpat")), ref)
