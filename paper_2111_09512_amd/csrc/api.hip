@@ -511,7 +511,8 @@ bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<i
 // r0 + l in x[r0 + w .. r0 + w + 127] for the run holding the slot's offset.
 // ltab holds each pattern's kp slots as LDS elements in rows of kl = kp
 // rounded up to 8 (the padding 0).  False when more than PAT_WIN_MAX runs are
-// needed.
+// needed, or when they span more than 2^24 rows (the kernel addresses the
+// span as one buffer of at most 2^31 bytes).
 bool pattern_windows(const std::vector<int32_t> &ptab, int kp, std::vector<int32_t> &wst,
                      std::vector<uint16_t> &ltab)
 {
@@ -524,6 +525,7 @@ bool pattern_windows(const std::vector<int32_t> &ptab, int kp, std::vector<int32
         if ((int)wst.size() == PAT_WIN_MAX) return false;
         wst.push_back((int32_t)((int64_t)o - ((int64_t)o & 1))); // rounded down to even
     }
+    if ((int64_t)wst.back() + 128 - wst.front() > (int64_t)1 << 24) return false;
     const size_t kl = (size_t)(kp + 7) / 8 * 8, npat = ptab.size() / (size_t)kp;
     ltab.assign(npat * kl, 0);
     for (size_t p = 0; p < npat; p++)
