@@ -838,7 +838,7 @@ hipError_t go_diag(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 // slices above GM groups and those whose windows would reach outside the
 // matrix take the gather body.  Built for FP64 values (the FP32-inner sweeps
 // keep their 4-byte gathers, 4-5 % faster than windows there); on the n = 8M
-// 27-point ILUT factors 256 us per FP64 sweep against 269 us with gathers.
+// 27-point ILUT factors 252 us per FP64 sweep against 269 us with gathers.
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
