@@ -729,9 +729,7 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
             e = hipMemcpyAsync(S.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipMalloc(&S.pid, pid.size());
         if (e == hipSuccess) e = hipMemcpyAsync(S.pid, pid.data(), pid.size(), hipMemcpyHostToDevice, c->stream);
-        // windows for FP64 values only: the FP32 sweeps' 4-byte gathers are
-        // cheaper than the windows' LDS round trip (4-5 % slower with them)
-        if (e == hipSuccess && vbytes == 8 && pattern_windows(ptab, 4 * gmax, wst, ltab)) {
+        if (e == hipSuccess && pattern_windows(ptab, 4 * gmax, wst, ltab)) {
             e = hipMalloc(&S.ltab, ltab.size() * 2);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(S.ltab, ltab.data(), ltab.size() * 2, hipMemcpyHostToDevice, c->stream);

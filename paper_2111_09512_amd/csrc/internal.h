@@ -60,10 +60,10 @@ struct SlicedView {
     const uint8_t *pid = nullptr;  // [nslice * 64] pattern of each row
     const int32_t *ptab = nullptr; // [npat * kp]
     int npat = 0, kp = 0;
-    // iterate windows of code 8 with FP64 values (nwin = 0: none): the
-    // table's offsets fall in nwin runs, run c covering offsets [wst[c],
-    // wst[c] + 64] (wst[c] even, ascending), so the 64 rows of a slice starting
-    // at row r0 gather only from x[r0 + wst[c] .. r0 + wst[c] + 127];
+    // iterate windows of code 8 (nwin = 0: none): the table's offsets fall
+    // in nwin runs, run c covering offsets [wst[c], wst[c] + 64] (wst[c]
+    // even, ascending), so the 64 rows of a slice starting at row r0 gather
+    // only from x[r0 + wst[c] .. r0 + wst[c] + 127];
     // ltab[pid * kl + k] (k < kp; kl = kp rounded up to 8, for 16-byte
     // loads) is slot k's element in the wave's copy of those windows,
     // 128 c + ptab[pid * kp + k] - wst[c]

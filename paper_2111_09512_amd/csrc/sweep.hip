@@ -836,9 +836,12 @@ hipError_t go_diag(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 // The x read for a slot is x[row + offset] as in the gather body, and the
 // sums keep the same order: results are the same bit for bit.  Masked slices,
 // slices above GM groups and those whose windows would reach outside the
-// matrix take the gather body.  Built for FP64 values (the FP32-inner sweeps
-// keep their 4-byte gathers, 4-5 % faster than windows there); on the n = 8M
-// 27-point ILUT factors 252 us per FP64 sweep against 269 us with gathers.
+// matrix take the gather body.  On the n = 8M 27-point ILUT factors: 252 us
+// per FP64 sweep against 269 us with gathers; the FP32-inner sweeps gain
+// 1-1.5 % (137 against 139 us), and only when held to six waves per SIMD
+// (70-72 registers; at the unconstrained 85 registers and five waves they
+// were 4-5 % slower than their 4-byte gathers, at eight waves they spill;
+// above six groups six waves spill too, so those bodies get five).
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
@@ -935,7 +938,9 @@ __device__ __forceinline__ typename T::AT slice_sum_win_g(int G, const SlicedVie
 }
 
 template <class T, int WPB, int GM>
-__global__ void __launch_bounds__(64 * WPB) k_sweep_pat_win(SweepArgs a, SlicedView s)
+__global__ void __launch_bounds__(64 * WPB)
+    __attribute__((amdgpu_waves_per_eu(sizeof(typename T::XT) == 4 ? (GM <= 6 ? 6 : 5) : 1)))
+    k_sweep_pat_win(SweepArgs a, SlicedView s)
 {
     using XT = typename T::XT;
     using RT = typename T::RT;
@@ -1412,15 +1417,13 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
             if (g.sl.npat < 1 || g.sl.kp < 4 || (g.sl.kp & 3) || g.sl.npat * g.sl.kp > PAT_MAX_ENTRIES ||
                 g.sl.gmax > 8 || g.sl.kp != 4 * g.sl.gmax)
                 return hipErrorInvalidValue;
-            if constexpr (sizeof(typename T::VT) == 8) {
-                if (g.sl.nwin > 0) {
-                    if (g.sl.nwin > PAT_WIN_MAX || !g.sl.ltab || g.sl.wspan < 128 || (g.sl.wst[0] & 1) ||
-                        g.sl.kl < g.sl.kp || (g.sl.kl & 7))
-                        return hipErrorInvalidValue;
-                    // eight waves per workgroup (1 % faster) while two such
-                    // workgroups' windows fit in a CU's 160 KB of LDS
-                    return g.sl.nwin <= 9 ? go_pat_win<T, 8>(g, a, s) : go_pat_win<T, WPB>(g, a, s);
-                }
+            if (g.sl.nwin > 0) {
+                if (g.sl.nwin > PAT_WIN_MAX || !g.sl.ltab || g.sl.wspan < 128 || (g.sl.wst[0] & 1) ||
+                    g.sl.kl < g.sl.kp || (g.sl.kl & 7))
+                    return hipErrorInvalidValue;
+                // eight waves per workgroup (1 % faster) while two such
+                // workgroups' FP64 windows fit in a CU's 160 KB of LDS
+                return g.sl.nwin <= 9 ? go_pat_win<T, 8>(g, a, s) : go_pat_win<T, WPB>(g, a, s);
             }
             return go_pat<T, WPB>(g, a, s);
         }
