@@ -64,6 +64,7 @@ struct Sliced {
     int32_t *sptr = nullptr, *sk = nullptr, *dtab = nullptr, *ptab = nullptr;
     uint8_t *pid = nullptr;
     uint16_t *ltab = nullptr;
+    int32_t *wflag = nullptr;
     void *val = nullptr, *codes = nullptr;
     int64_t masked_rows = 0;
     bool ok = false;
@@ -112,6 +113,7 @@ void free_sliced(Sliced &S)
     (void)hipFree(S.ptab);
     (void)hipFree(S.pid);
     (void)hipFree(S.ltab);
+    (void)hipFree(S.wflag);
     S = Sliced();
 }
 
@@ -509,31 +511,59 @@ bool row_patterns(int64_t n, const std::vector<int32_t> &rp, const std::vector<i
 // order, cut into runs that start at an even offset w and reach at most w +
 // 64, so that lane l of a slice starting at row r0 finds every slot of row
 // r0 + l in x[r0 + w .. r0 + w + 127] for the run holding the slot's offset.
-// ltab holds each pattern's kp slots as LDS elements in rows of kl = kp
-// rounded up to 8 (the padding 0).  False when more than PAT_WIN_MAX runs are
-// needed, or when they span more than 2^24 rows (the kernel addresses the
-// span as one buffer of at most 2^31 bytes).
-bool pattern_windows(const std::vector<int32_t> &ptab, int kp, std::vector<int32_t> &wst,
-                     std::vector<uint16_t> &ltab)
+// A run that fewer than 1/16 of the slices need (a rare fill offset) is
+// dropped: every slice would load its window for a few slices' sake, so the
+// slices needing it take the gather body instead (wflag[slice] = 0; the
+// others 1).  ltab holds each pattern's kp slots as LDS elements in rows of
+// kl = kp rounded up to 8 (the padding 0; all 0 for a pattern on a dropped
+// run).  False when more than PAT_WIN_MAX runs are kept, or when they span
+// more than 2^24 rows (the kernel addresses the span as one buffer of at
+// most 2^31 bytes).
+bool pattern_windows(const std::vector<int32_t> &ptab, int kp, const std::vector<uint8_t> &pid, int64_t n,
+                     std::vector<int32_t> &wst, std::vector<uint16_t> &ltab, std::vector<int32_t> &wflag)
 {
     std::vector<int32_t> offs(ptab);
     std::sort(offs.begin(), offs.end());
     offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
-    wst.clear();
+    std::vector<int32_t> run_start; // every run, kept or not
     for (int32_t o : offs) {
-        if (!wst.empty() && (int64_t)o - wst.back() <= 64) continue;
-        if ((int)wst.size() == PAT_WIN_MAX) return false;
-        wst.push_back((int32_t)((int64_t)o - ((int64_t)o & 1))); // rounded down to even
+        if (!run_start.empty() && (int64_t)o - run_start.back() <= 64) continue;
+        if (run_start.size() == 64) return false; // one bit per run below
+        run_start.push_back((int32_t)((int64_t)o - ((int64_t)o & 1))); // rounded down to even
     }
-    if ((int64_t)wst.back() + 128 - wst.front() > (int64_t)1 << 24) return false;
-    const size_t kl = (size_t)(kp + 7) / 8 * 8, npat = ptab.size() / (size_t)kp;
-    ltab.assign(npat * kl, 0);
+    const size_t npat = ptab.size() / (size_t)kp, nslice = (size_t)((n + 63) / 64);
+    auto run_of = [&](int32_t o) {
+        return (int)(std::upper_bound(run_start.begin(), run_start.end(), o) - run_start.begin()) - 1;
+    };
+    std::vector<uint64_t> pat_runs(npat, 0);
     for (size_t p = 0; p < npat; p++)
+        for (size_t k = 0; k < (size_t)kp; k++) pat_runs[p] |= 1ull << run_of(ptab[p * (size_t)kp + k]);
+    std::vector<uint64_t> slice_runs(nslice, 0);
+    for (int64_t r = 0; r < n; r++) slice_runs[(size_t)(r >> 6)] |= pat_runs[pid[(size_t)r]];
+    std::vector<int64_t> need(run_start.size(), 0);
+    for (uint64_t m : slice_runs)
+        for (size_t c = 0; c < run_start.size(); c++) need[c] += (m >> c) & 1;
+    uint64_t kept = 0;
+    wst.clear();
+    for (size_t c = 0; c < run_start.size(); c++)
+        if (need[c] >= (int64_t)(nslice / 16)) {
+            kept |= 1ull << c;
+            wst.push_back(run_start[c]);
+        }
+    if (wst.empty() || (int)wst.size() > PAT_WIN_MAX) return false;
+    if ((int64_t)wst.back() + 128 - wst.front() > (int64_t)1 << 24) return false;
+    const size_t kl = (size_t)(kp + 7) / 8 * 8;
+    ltab.assign(npat * kl, 0);
+    for (size_t p = 0; p < npat; p++) {
+        if (pat_runs[p] & ~kept) continue;
         for (size_t k = 0; k < (size_t)kp; k++) {
             const int32_t o = ptab[p * (size_t)kp + k];
             const int c = (int)(std::upper_bound(wst.begin(), wst.end(), o) - wst.begin()) - 1;
             ltab[p * kl + k] = (uint16_t)(128 * c + (o - wst[(size_t)c])); // in [128 c, 128 c + 64]
         }
+    }
+    wflag.assign(nslice, 0);
+    for (size_t t = 0; t < nslice; t++) wflag[t] = (slice_runs[t] & ~kept) ? 0 : 1;
     return true;
 }
 
@@ -721,7 +751,7 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     if (e == hipSuccess) e = hipMemcpyAsync(S.sptr, sptr.data(), (size_t)nslice * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMalloc(&S.val, (size_t)slots * (size_t)vbytes);
     if (e == hipSuccess && code != 8) e = hipMalloc(&S.codes, (size_t)slots * (size_t)code);
-    std::vector<int32_t> wst;
+    std::vector<int32_t> wst, wflag;
     std::vector<uint16_t> ltab;
     if (e == hipSuccess && code == 8) {
         e = hipMalloc(&S.ptab, ptab.size() * 4);
@@ -729,10 +759,13 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
             e = hipMemcpyAsync(S.ptab, ptab.data(), ptab.size() * 4, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipMalloc(&S.pid, pid.size());
         if (e == hipSuccess) e = hipMemcpyAsync(S.pid, pid.data(), pid.size(), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess && pattern_windows(ptab, 4 * gmax, wst, ltab)) {
+        if (e == hipSuccess && pattern_windows(ptab, 4 * gmax, pid, n, wst, ltab, wflag)) {
             e = hipMalloc(&S.ltab, ltab.size() * 2);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(S.ltab, ltab.data(), ltab.size() * 2, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipMalloc(&S.wflag, wflag.size() * 4);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(S.wflag, wflag.data(), wflag.size() * 4, hipMemcpyHostToDevice, c->stream);
         }
     }
     if (e == hipSuccess && code == 1) {
@@ -767,12 +800,13 @@ int build_sliced(silu_ctx *c, const silu_csr *N, const void *val, int vbytes, in
     S.v.ptab = S.ptab;
     S.v.npat = npat;
     S.v.kp = code == 8 ? 4 * gmax : 0;
-    if (S.ltab) {
+    if (S.ltab && S.wflag) {
         S.v.nwin = (int)wst.size();
         S.v.wspan = wst.back() + 128 - wst.front();
         S.v.kl = (4 * gmax + 7) / 8 * 8;
         std::copy(wst.begin(), wst.end(), S.v.wst);
         S.v.ltab = S.ltab;
+        S.v.wflag = S.wflag;
     }
     S.ok = true;
     return store();

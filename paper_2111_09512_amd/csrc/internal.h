@@ -66,10 +66,12 @@ struct SlicedView {
     // only from x[r0 + wst[c] .. r0 + wst[c] + 127];
     // ltab[pid * kl + k] (k < kp; kl = kp rounded up to 8, for 16-byte
     // loads) is slot k's element in the wave's copy of those windows,
-    // 128 c + ptab[pid * kp + k] - wst[c]
+    // 128 c + ptab[pid * kp + k] - wst[c]; runs few slices need are left
+    // out, and a slice with a row on one has wflag 0 (gathers)
     int nwin = 0, wspan = 0, kl = 0; // wspan = wst[nwin - 1] + 128 - wst[0]
     int32_t wst[PAT_WIN_MAX] = {};
-    const uint16_t *ltab = nullptr; // [npat * kl]
+    const uint16_t *ltab = nullptr;  // [npat * kl]
+    const int32_t *wflag = nullptr;  // [nslice] 1: the slice's rows lie on the windows
     // code 16 (diagonal slices, FP64 or FP32 values): every row of the matrix lies
     // on the ndiag <= DIAG_MAX diagonals dtab[] (ascending); nslice slices of
     // 128 rows, slot k of row r holding its entry on diagonal dtab[k] (0 where

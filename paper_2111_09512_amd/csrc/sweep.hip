@@ -835,8 +835,9 @@ hipError_t go_diag(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 // and LDS operations of one wave complete in order, so no barrier is needed.
 // The x read for a slot is x[row + offset] as in the gather body, and the
 // sums keep the same order: results are the same bit for bit.  Masked slices,
-// slices above GM groups and those whose windows would reach outside the
-// matrix take the gather body.  On the n = 8M 27-point ILUT factors: 252 us
+// slices above GM groups, those whose windows would reach outside the matrix
+// and those with a row on an offset run left without a window take the
+// gather body.  On the n = 8M 27-point ILUT factors: 252 us
 // per FP64 sweep against 269 us with gathers; the FP32-inner sweeps gain
 // 1-1.5 % (137 against 139 us), and only when held to six waves per SIMD
 // (70-72 registers; at the unconstrained 85 registers and five waves they
@@ -953,7 +954,7 @@ __global__ void __launch_bounds__(64 * WPB)
     const int pidl = (int)s.pid[wave * 64 + lane];
     const int G = (kf & 0x7fffffff) >> 2;
     const int r0 = wave * 64;
-    if (kf < 0 || G > GM || G < 1 || r0 + s.wst[0] < 0 || (int64_t)r0 + s.wst[0] + s.wspan > a.n) {
+    if (kf < 0 || G > GM || G < 1 || !s.wflag[wave] || r0 + s.wst[0] < 0 || (int64_t)r0 + s.wst[0] + s.wspan > a.n) {
         sliced_wave_pat<T, GM>(a, s, wave, kf, p0, s.ptab + pidl * s.kp);
         return;
     }
@@ -1418,7 +1419,7 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
                 g.sl.gmax > 8 || g.sl.kp != 4 * g.sl.gmax)
                 return hipErrorInvalidValue;
             if (g.sl.nwin > 0) {
-                if (g.sl.nwin > PAT_WIN_MAX || !g.sl.ltab || g.sl.wspan < 128 || (g.sl.wst[0] & 1) ||
+                if (g.sl.nwin > PAT_WIN_MAX || !g.sl.ltab || !g.sl.wflag || g.sl.wspan < 128 || (g.sl.wst[0] & 1) ||
                     g.sl.kl < g.sl.kp || (g.sl.kl & 7))
                     return hipErrorInvalidValue;
                 // eight waves per workgroup (1 % faster) while two such

@@ -659,3 +659,25 @@ def test_pattern_windows(orc, B, ctx, n, starts, width, drop):
         for m in (1, 3):
             ref = orc.richardson(L, x, m)
             np.testing.assert_array_equal(host(ctx.trisolve_iter(Ld, dev(x), m, kernel="rowpat")), ref)
+
+
+@pytest.mark.parametrize("n", [4000, 64 * 90 + 33])
+@pytest.mark.parametrize("rare_rows", [(1000, 1001, 1063), (2000,), ()])
+def test_pattern_windows_rare_run(orc, B, ctx, n, rare_rows):
+    """A run of offsets that few slices need gets no window: the two common
+    diagonals -1 and -2 are staged as one window, while the rows holding an
+    entry on diagonal -700 (rows in one or two slices, far fewer than 1/16
+    of them) send their slices to the gather body; every result equals the
+    oracle's bit for bit, with and without such rows."""
+    say("pattern windows, rare run", n, rare_rows)
+    L, _ = _runs(n, (-2,), 2, seed=n)
+    D = L.to_dense()
+    rng = np.random.default_rng(n)
+    for r in rare_rows:
+        D[r, r - 700] = rng.uniform(-1.0, 1.0)
+    M = W.CSR.from_dense(D)
+    Md = B.Csr.from_host(M)
+    x = W.rhs(n, 7)
+    np.testing.assert_array_equal(host(ctx.spmv(Md, dev(x), kernel="rowpat")), orc.spmv(M, x))
+    for m in (1, 3):
+        np.testing.assert_array_equal(host(ctx.trisolve_iter(Md, dev(x), m, kernel="rowpat")), orc.richardson(M, x, m))
