@@ -827,18 +827,20 @@ hipError_t go_diag(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
 // gather from nwin windows of 128 consecutive iterate entries (the runs of the
 // pattern table's offsets, each run within 64 of its even start): the wave
 // loads each window with one load of two entries per lane into its own LDS
-// region and takes every slot's x from there, at lane + ltab[...], instead of
-// one gather per slot from the caches -- nwin loads in place of 4G gathers
-// (aniso 27-point ILUT factors: 8-9 windows against 20 gathers per row).  The
-// value loads, the slots' LDS indices and the windows are all issued before
-// the first is waited for.  Each wave writes and reads only its own region,
+// region (FP64: a 16-byte buffer load straight into LDS; FP32: through
+// registers, there being no 8-byte form) and takes every slot's x from
+// there, at lane + ltab[...], instead of one gather per slot from the caches
+// -- nwin loads in place of 4G gathers (aniso 27-point ILUT factors: 7
+// windows against 20 gathers per row).  The windows, the value loads and the
+// slots' LDS indices are all issued before the first is waited for.  Each wave writes and reads only its own region,
 // and LDS operations of one wave complete in order, so no barrier is needed.
 // The x read for a slot is x[row + offset] as in the gather body, and the
 // sums keep the same order: results are the same bit for bit.  Masked slices,
 // slices above GM groups, those whose windows would reach outside the matrix
 // and those with a row on an offset run left without a window take the
-// gather body.  On the n = 8M 27-point ILUT factors: 252 us
-// per FP64 sweep against 269 us with gathers; the FP32-inner sweeps gain
+// gather body.  On the n = 8M 27-point ILUT factors: about 241 us per FP64
+// sweep (252 us with the windows staged through registers) against 269 us
+// with gathers; the FP32-inner sweeps gain
 // 1-1.5 % (137 against 139 us), and only when held to six waves per SIMD
 // (70-72 registers; at the unconstrained 85 registers and five waves they
 // were 4-5 % slower than their 4-byte gathers, at eight waves they spill;
@@ -855,11 +857,42 @@ __device__ __forceinline__ void load_windows(const SlicedView &s, const typename
     constexpr int xb = (int)sizeof(XT);
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc((void *)(xin + (r0 + s.wst[0])), (short)0, s.wspan * xb, 0x00020000);
-    XP w[NW];
+    if constexpr (xb == 8) {
+        // straight into LDS, lane l's 16 bytes at window + 16 l: no registers
+        // and no LDS writes; the caller waits for them before reading
 #pragma unroll
-    for (int c = 0; c < NW; ++c) w[c] = buf_pair<XT, 0>(rx, lane * 2 * xb, (s.wst[c] - s.wst[0]) * xb);
+        for (int c = 0; c < NW; ++c)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (__attribute__((address_space(3))) void *)(lw + 128 * c), 16,
+                                                     lane * 16, (s.wst[c] - s.wst[0]) * 8, 0, 0);
+    } else { // no 8-byte form of those loads: through registers
+        XP w[NW];
 #pragma unroll
-    for (int c = 0; c < NW; ++c) *(XP *)(lw + 128 * c + 2 * lane) = w[c];
+        for (int c = 0; c < NW; ++c) w[c] = buf_pair<XT, 0>(rx, lane * 2 * xb, (s.wst[c] - s.wst[0]) * xb);
+#pragma unroll
+        for (int c = 0; c < NW; ++c) *(XP *)(lw + 128 * c + 2 * lane) = w[c];
+    }
+}
+
+// All of the slice's windows, one case per window count.
+template <class T>
+__device__ __forceinline__ void stage_windows(const SlicedView &s, const typename T::XT *__restrict__ xin, int r0,
+                                              int lane, typename T::XT *lw)
+{
+    switch (s.nwin) {
+    case 1: load_windows<T, 1>(s, xin, r0, lane, lw); break;
+    case 2: load_windows<T, 2>(s, xin, r0, lane, lw); break;
+    case 3: load_windows<T, 3>(s, xin, r0, lane, lw); break;
+    case 4: load_windows<T, 4>(s, xin, r0, lane, lw); break;
+    case 5: load_windows<T, 5>(s, xin, r0, lane, lw); break;
+    case 6: load_windows<T, 6>(s, xin, r0, lane, lw); break;
+    case 7: load_windows<T, 7>(s, xin, r0, lane, lw); break;
+    case 8: load_windows<T, 8>(s, xin, r0, lane, lw); break;
+    case 9: load_windows<T, 9>(s, xin, r0, lane, lw); break;
+    case 10: load_windows<T, 10>(s, xin, r0, lane, lw); break;
+    case 11: load_windows<T, 11>(s, xin, r0, lane, lw); break;
+    default: load_windows<T, 12>(s, xin, r0, lane, lw); break;
+    }
+    static_assert(PAT_WIN_MAX == 12, "one case per window count");
 }
 
 template <class T, int GG>
@@ -895,21 +928,10 @@ __device__ __forceinline__ typename T::AT slice_sum_win(const SlicedView &s, int
         o[q] = t.lo;
         if (q + 1 < GG) o[q + 1] = t.hi;
     }
-    switch (s.nwin) {
-    case 1: load_windows<T, 1>(s, xin, r0, lane, lw); break;
-    case 2: load_windows<T, 2>(s, xin, r0, lane, lw); break;
-    case 3: load_windows<T, 3>(s, xin, r0, lane, lw); break;
-    case 4: load_windows<T, 4>(s, xin, r0, lane, lw); break;
-    case 5: load_windows<T, 5>(s, xin, r0, lane, lw); break;
-    case 6: load_windows<T, 6>(s, xin, r0, lane, lw); break;
-    case 7: load_windows<T, 7>(s, xin, r0, lane, lw); break;
-    case 8: load_windows<T, 8>(s, xin, r0, lane, lw); break;
-    case 9: load_windows<T, 9>(s, xin, r0, lane, lw); break;
-    case 10: load_windows<T, 10>(s, xin, r0, lane, lw); break;
-    case 11: load_windows<T, 11>(s, xin, r0, lane, lw); break;
-    default: load_windows<T, 12>(s, xin, r0, lane, lw); break;
-    }
-    static_assert(PAT_WIN_MAX == 12, "one case per window count");
+    if constexpr (sizeof(XT) == 8)
+        __builtin_amdgcn_s_waitcnt(0x0F70); // vmcnt(0): the windows, loaded straight into LDS, have landed
+    else
+        stage_windows<T>(s, xin, r0, lane, lw);
     __builtin_amdgcn_wave_barrier();
     XT xv[GG][4];
 #pragma unroll
@@ -972,6 +994,11 @@ __global__ void __launch_bounds__(64 * WPB)
     if (a.dshift) dsh = a.dshift[row];
     AT sum = (AT)0;
     if (a.dshift) sum = (AT)((dsh - 1.0) * (double)xin[row]);
+    // FP64 windows go straight to LDS and are issued here, once, ahead of the
+    // group dispatch: issued inside each group count's body, the compiler
+    // merged the bodies' copies and waited for every load in flight before
+    // each window, not telling the windows' LDS targets apart
+    if constexpr (sizeof(XT) == 8) stage_windows<T>(s, xin, r0, lane, lw);
     sum = slice_sum_win_g<T, GM>(G, s, p0, lane, r0, xin, lw, s.ltab + pidl * s.kl, sum);
     const AT t = a.epi == EPI_SPMV ? sum : (AT)rhs_v - sum;
     epilogue_pre<T>(a, row, t, aux, aux2, cf);
