@@ -1445,7 +1445,10 @@ hipError_t dispatch(const SweepGeom &g, const SweepArgs &a, hipStream_t s)
             if (g.sl.npat < 1 || g.sl.kp < 4 || (g.sl.kp & 3) || g.sl.npat * g.sl.kp > PAT_MAX_ENTRIES ||
                 g.sl.gmax > 8 || g.sl.kp != 4 * g.sl.gmax)
                 return hipErrorInvalidValue;
-            if (g.sl.nwin > 0) {
+            // windows load two iterate entries per lane at even offsets: with
+            // an iterate aligned to that width (the library's own vectors
+            // are; a caller's may not be) every load is aligned to its size
+            if (g.sl.nwin > 0 && ((uintptr_t)a.xin & (2 * sizeof(typename T::XT) - 1)) == 0) {
                 if (g.sl.nwin > PAT_WIN_MAX || !g.sl.ltab || !g.sl.wflag || g.sl.wspan < 128 || (g.sl.wst[0] & 1) ||
                     g.sl.kl < g.sl.kp || (g.sl.kl & 7))
                     return hipErrorInvalidValue;

@@ -681,3 +681,21 @@ def test_pattern_windows_rare_run(orc, B, ctx, n, rare_rows):
     np.testing.assert_array_equal(host(ctx.spmv(Md, dev(x), kernel="rowpat")), orc.spmv(M, x))
     for m in (1, 3):
         np.testing.assert_array_equal(host(ctx.trisolve_iter(Md, dev(x), m, kernel="rowpat")), orc.richardson(M, x, m))
+
+
+@pytest.mark.parametrize("shift", [0, 1])
+def test_pattern_windows_unaligned_iterate(orc, B, ctx, shift):
+    """An iterate that is not 16-byte aligned (a view one element into a
+    larger tensor) takes the gather body instead of the windows; both give the
+    oracle's product bit for bit."""
+    import torch
+    n = 3001
+    say("pattern windows, unaligned iterate", shift)
+    L, _ = _runs(n, (-300, -2), 3, seed=11)
+    Ld = B.Csr.from_host(L)
+    x = W.rhs(n, 9)
+    big = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    big[shift:shift + n] = dev(x)
+    xv = big[shift:shift + n]
+    assert (xv.data_ptr() % 16 != 0) == bool(shift)
+    np.testing.assert_array_equal(host(ctx.spmv(Ld, xv, kernel="rowpat")), orc.spmv(L, x))
